@@ -1,0 +1,320 @@
+/*
+ * libtnt_mi355x -- two-site DMRG hot path for 1D U(1)-symmetric MPS on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem statement follows "The Tensor Network Theory Library"
+ * (Al-Assam, Clark, Jaksch):
+ *   - block tensors with U(1) charges: appendix A.1.1 (symmetric nodes: each
+ *     leg is incoming or outgoing, only elements whose incoming charges sum
+ *     to the outgoing charge are stored, one dense block per charge label);
+ *   - the H_eff contractor handed to an eigensolver: Sec. 4.2;
+ *   - the iterative lowest-eigenpair search driven by that contractor:
+ *     Sec. 4.2 (network minimisation);
+ *   - the truncated SVD, its four truncation rules and its error: appendix
+ *     B.1.2 (Eq. trunc_err);
+ *   - the variational sweep over an MPS with an MPO Hamiltonian: Sec. 4.3.
+ *
+ * Conventions shared by every call
+ *   - Complex data are split into two real planes (re, im) of the same dtype.
+ *     A block is stored row-major with the leg order given below; `offset`
+ *     is the element offset of the block inside each plane.
+ *   - Host metadata arrays are borrowed for the duration of the call only.
+ *     Device planes are borrowed; the library never frees caller memory.
+ *   - Every call is enqueued on the context's stream.  Calls that must
+ *     inspect device results on the host (eigensolver, SVD, sweep) block
+ *     until those results are available; tnt_heff2_apply does not block.
+ *   - Status codes: 0 = OK, > 0 = warning (result valid), < 0 = error (no
+ *     output written, or outputs unspecified).  tnt_last_error() gives a
+ *     human-readable reason.  The library never prints and never aborts.
+ *     A kernel fault surfaces as TNT_E_HIP at the next blocking call or
+ *     tnt_sync().
+ *   - Not thread safe per context: calls on one context must not overlap.
+ */
+#ifndef TNT_MI355X_H
+#define TNT_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tnt_status;
+
+enum {
+  TNT_OK = 0,
+  TNT_W_NOCONV = 1,      /* eigensolver residual above tolerance after kmax steps */
+  TNT_E_ARG = -1,        /* invalid argument (null pointer, bad enum, bad size)    */
+  TNT_E_SHAPE = -2,      /* block extents inconsistent between tensors           */
+  TNT_E_CHARGE = -3,     /* a block violates the U(1) rule sum(in) = sum(out)     */
+  TNT_E_CAPACITY = -4,   /* caller buffer too small                               */
+  TNT_E_ALLOC = -5,      /* device allocation failed                              */
+  TNT_E_NONFINITE = -6,  /* NaN or Inf found in an input or produced               */
+  TNT_E_HIP = -7,        /* HIP runtime or library error                          */
+  TNT_E_STATE = -8       /* object used in a wrong state                          */
+};
+
+/* arithmetic of the H_eff contraction */
+enum { TNT_FP64 = 0, TNT_FP32 = 1, TNT_BF16X3 = 2 };
+/* element type of a plane */
+enum { TNT_DT_F64 = 0, TNT_DT_F32 = 1 };
+/* where the singular values go after the SVD */
+enum { TNT_ABSORB_RIGHT = 0, TNT_ABSORB_LEFT = 1 };
+/* truncation error function (appendix B.1.2) */
+enum { TNT_ERR_2NORM = 0, TNT_ERR_SUMSQ = 1, TNT_ERR_1NORM = 2 };
+
+typedef struct tnt_ctx_s* tnt_ctx;
+
+/* ------------------------------------------------------------------------
+ * Context
+ * ------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  The context owns a caching
+ * device-memory pool (workspaces, plans, MPS storage); it is released by
+ * tnt_ctx_destroy.  Errors: TNT_E_ARG (out is NULL), TNT_E_HIP. */
+tnt_status tnt_ctx_create(int32_t device, void* hip_stream, tnt_ctx* out);
+void tnt_ctx_destroy(tnt_ctx ctx);
+/* Reason for the last non-OK status on this context (never NULL). */
+const char* tnt_last_error(tnt_ctx ctx);
+/* Wait for all work enqueued by the context; TNT_E_HIP on a device fault. */
+tnt_status tnt_sync(tnt_ctx ctx);
+/* Bytes currently held by the context's device pool (in use + cached). */
+int64_t tnt_pool_bytes(tnt_ctx ctx);
+
+/* ------------------------------------------------------------------------
+ * Block tensors (appendix A.1.1)
+ *
+ * Each block carries one integer label and one extent per leg.  Roles:
+ *   theta  rank 4, legs (a, s1, s2, b), dir (+1, +1, +1, -1):
+ *          labels (q_a, s1, s2, q_b), extents (dim_a, 1, 1, dim_b),
+ *          rule q_b = q_a + s1 + s2.  Stored as a dim_a x dim_b matrix.
+ *   L env  rank 3, legs (a', w, a), dir (-1, +1, +1): labels (q_a', w, q_a)
+ *          where w is the MPO bond index (its charge is the MPO's
+ *          bond_charge[w]), extents (dim_a', 1, dim_a), rule
+ *          q_a' = q_a + bond_charge[w].  a' is the bra index.
+ *   R env  same as L env with legs (b', u, b), rule q_b' = q_b + charge[u].
+ * A block whose labels violate its rule is rejected with TNT_E_CHARGE.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t rank;
+  int32_t nblocks;
+  const int32_t* qn;      /* [nblocks * rank] host: labels                      */
+  const int32_t* extent;  /* [nblocks * rank] host: extents                     */
+  const int64_t* offset;  /* [nblocks] host: element offset of each block        */
+  void* re;               /* device plane, dtype elements                        */
+  void* im;               /* device plane                                        */
+  int32_t dtype;          /* TNT_DT_F64 | TNT_DT_F32                             */
+  int64_t capacity;       /* elements available in each plane                    */
+} tnt_btensor;
+
+/* One MPO site W[w, w', s', s] (Sec. 4.3: the Hamiltonian as a chain).
+ * Host arrays, borrowed.  Every nonzero element must obey
+ * s' - s = bond_charge[w'] - bond_charge[w]  (else TNT_E_CHARGE). */
+typedef struct {
+  int32_t d;                  /* physical dimension (labels s = 0..d-1 are the charges) */
+  int32_t D;                  /* MPO bond dimension                                     */
+  const int32_t* bond_charge; /* [D]                                                    */
+  const double* W;            /* [D*D*d*d], index ((w*D + w')*d + s')*d + s              */
+} tnt_mpo_site;
+
+/* ------------------------------------------------------------------------
+ * H_eff . theta (Sec. 4.2, the contractor, in two-site form)
+ *
+ *   out[a', s1', s2', b'] = sum L[a', w, a] W1[w, v, s1', s1] W2[v, u, s2', s2]
+ *                               R[b', u, b] theta[a, s1, s2, b]
+ *
+ * theta and out: same block set and extents (offsets may differ), dtype
+ * TNT_DT_F64.  L, R: TNT_DT_F64.  precision selects the arithmetic of the
+ * contraction (TNT_FP64; TNT_FP32 = FP32 MFMA with FP32 accumulation;
+ * TNT_BF16X3 = three-term bf16 split products with FP32 accumulation); the
+ * result is always written as FP64.  Output blocks no term reaches are
+ * written as zeros.  Asynchronous (no host wait).
+ * Errors: TNT_E_ARG, TNT_E_SHAPE (extents disagree), TNT_E_CHARGE,
+ * TNT_E_CAPACITY (a block runs past a plane's capacity), TNT_E_ALLOC.
+ * ------------------------------------------------------------------------ */
+tnt_status tnt_heff2_apply(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_site* W1,
+                           const tnt_mpo_site* W2, const tnt_btensor* R,
+                           const tnt_btensor* theta, tnt_btensor* out, int32_t precision);
+
+/* Algorithmic FLOP count of one tnt_heff2_apply on these block structures
+ * (host only, no device access).  Counting rule: a complex multiply-add is
+ * 8 flops, a real-times-complex term 4 flops per element; step 1 (L.theta
+ * slabs that feed a nonzero MPO term), the MPO terms, and step 4 (. R).
+ * Writes {step1, mpo, step4} to `parts` when non-NULL.  Returns the total,
+ * or -1 on invalid input. */
+int64_t tnt_heff2_flops(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt_mpo_site* W2,
+                        const tnt_btensor* R, const tnt_btensor* theta, int64_t* parts);
+
+/* ------------------------------------------------------------------------
+ * Lowest eigenpair of H_eff (Sec. 4.2, network minimisation; the initial
+ * guess is the current theta).  Plain Lanczos in FP64: alpha/beta
+ * recurrence, two passes of full re-orthogonalisation, stop at kmax steps
+ * or when beta_j <= beta_tol * max(1, |alpha_0|); lowest Ritz pair of the
+ * tridiagonal matrix; then one FP64 matvec for the Rayleigh quotient
+ * E_refined and the residual |H psi - E psi|.  The matvecs inside the
+ * iteration use `precision`; the refinement is always FP64.
+ * theta (FP64) is the start vector on entry and the normalised ground
+ * vector on exit.  Blocks until the result is on the host.
+ * Returns TNT_W_NOCONV when residual > resid_tol (> 0) after kmax steps.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t kmax;        /* Krylov steps (>= 1, <= 256)          */
+  int32_t precision;   /* TNT_FP64 | TNT_FP32 | TNT_BF16X3      */
+  double beta_tol;     /* breakdown tolerance (e.g. 1e-12)      */
+  double resid_tol;    /* <= 0: never warn                      */
+} tnt_lanczos_params;
+
+typedef struct {
+  double E_ritz;
+  double E_refined;
+  double residual;
+  int32_t steps;
+} tnt_lanczos_result;
+
+tnt_status tnt_lanczos_ground(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_site* W1,
+                              const tnt_mpo_site* W2, const tnt_btensor* R,
+                              tnt_btensor* theta, const tnt_lanczos_params* p,
+                              tnt_lanczos_result* r);
+
+/* ------------------------------------------------------------------------
+ * Truncated SVD of theta (appendix B.1.2).
+ *
+ * For every middle charge m = q_a + s1, the matrix with rows (s1, a) and
+ * columns (s2, b) (s ascending, then the sector's index) is decomposed in
+ * FP64.  Singular values of all sectors are pooled and sorted descending
+ * (ties: smaller m, then smaller index); the kept number chi is the
+ * smallest allowed by the active rules: chi <= chi_max; lambda >= abs_tol
+ * (if > 0); lambda/lambda_0 >= rel_tol (if > 0); the largest discard whose
+ * error stays strictly below err_tol (if > 0); at least 1.
+ * eps = error of the discarded values (err_type).  With renormalise != 0 the
+ * kept values are scaled to unit 2-norm.
+ *
+ * Outputs (FP64 planes, written by the call):
+ *   A[a, s1, c]: blocks (q_a, s1) in ascending (q_a, s1), extent
+ *                (dim_a, kept(m)), rank-3 labels (q_a, s1, m);
+ *   B[c, s2, b]: blocks (m, s2) in ascending (m, s2), labels (m, s2, q_b);
+ *   absorb RIGHT: A = U, B = S V^+;  absorb LEFT: A = U S, B = V^+.
+ *   Blocks are packed contiguously from offset 0 in the order above; the
+ *   call writes nblocks, qn, extent and offset of A and B into the
+ *   caller's arrays (capacity max_blocks each) and the kept (renormalised)
+ *   singular values, sector by sector in ascending m, into S (capacity
+ *   s_capacity); bond_q/bond_dim (capacity max_blocks) get the new bond.
+ * Errors: TNT_E_CAPACITY when planes, metadata or S are too small
+ * (nothing is written to the planes then), TNT_E_NONFINITE.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t chi_max;
+  int32_t err_type;    /* TNT_ERR_*                     */
+  double abs_tol;      /* <= 0: off                     */
+  double rel_tol;      /* <= 0: off                     */
+  double err_tol;      /* <= 0: off                     */
+  int32_t renormalise; /* non-zero: unit 2-norm          */
+} tnt_trunc_params;
+
+typedef struct {
+  int32_t max_blocks;  /* capacity of qn/extent (x3) and offset arrays  */
+  int32_t nblocks;     /* written                                       */
+  int32_t* qn;         /* [max_blocks*3] written                        */
+  int32_t* extent;     /* [max_blocks*3] written                        */
+  int64_t* offset;     /* [max_blocks] written                          */
+  double* re;          /* device plane                                  */
+  double* im;          /* device plane                                  */
+  int64_t capacity;    /* elements per plane                            */
+} tnt_site_out;
+
+typedef struct {
+  int32_t chi;         /* kept bond dimension           */
+  int32_t nsectors;    /* sectors of the new bond       */
+  double eps;          /* truncation error              */
+  double lambda0;      /* largest singular value        */
+  double norm_kept;    /* 2-norm of the kept values before renormalising */
+} tnt_trunc_result;
+
+tnt_status tnt_theta_svd_truncate(tnt_ctx ctx, const tnt_btensor* theta,
+                                  const tnt_trunc_params* p, int32_t absorb,
+                                  tnt_site_out* A, tnt_site_out* B,
+                                  double* S, int32_t s_capacity,
+                                  int32_t* bond_q, int32_t* bond_dim,
+                                  tnt_trunc_result* r);
+
+/* Host-only helper: the kept count the rules above give for a descending
+ * spectrum `lam` of length n (no device access).  Returns chi >= 1, or -1
+ * on invalid input; writes the truncation error to *eps when non-NULL. */
+int32_t tnt_trunc_select(const double* lam, int32_t n, const tnt_trunc_params* p, double* eps);
+
+/* ------------------------------------------------------------------------
+ * MPS, environments and the sweep (Sec. 4.3, two-site form)
+ *
+ * An MPS handle owns device storage for L site tensors A_j[a, s, b]
+ * (blocks (q_left, s), extents (dim(q_left), dim(q_left + s))) and their
+ * bond sector tables; bond 0 holds one charge and bond L holds one charge.
+ * ------------------------------------------------------------------------ */
+typedef struct tnt_mps_s* tnt_mps;
+typedef struct tnt_env_s* tnt_env;
+
+/* Create an empty MPS of L sites with physical dimension d. */
+tnt_status tnt_mps_create(tnt_ctx ctx, int32_t L, int32_t d, tnt_mps* out);
+void tnt_mps_destroy(tnt_mps mps);
+/* Set bond `ell` (0..L) to sectors q[i] of dimension dim[i] (ascending q). */
+tnt_status tnt_mps_set_bond(tnt_mps mps, int32_t ell, int32_t nsec, const int32_t* q,
+                            const int32_t* dim);
+/* Upload site j (1..L) from host planes: blocks listed by (q_left[i], s[i]),
+ * each dim(q_left) x dim(q_left + s) row-major, concatenated in list order.
+ * Bonds j-1 and j must be set first.  Blocks not listed are zero. */
+tnt_status tnt_mps_set_site(tnt_mps mps, int32_t j, int32_t nblocks, const int32_t* q_left,
+                            const int32_t* s, const double* re, const double* im);
+/* Number of sectors of bond ell, and its table (arrays of capacity cap). */
+int32_t tnt_mps_bond_size(tnt_mps mps, int32_t ell);
+tnt_status tnt_mps_get_bond(tnt_mps mps, int32_t ell, int32_t cap, int32_t* q, int32_t* dim);
+/* Download site j: writes its blocks in ascending (q_left, s) into the
+ * host arrays (block count capacity cap, element capacity ecap). */
+tnt_status tnt_mps_get_site(tnt_mps mps, int32_t j, int32_t cap, int32_t* nblocks,
+                            int32_t* q_left, int32_t* s, int64_t ecap, double* re, double* im);
+/* Bring the MPS to right-canonical form (sites L..2 right isometries,
+ * norm carried by site 1, then site 1 scaled to unit norm), by exact
+ * (untruncated) SVDs on the device. */
+tnt_status tnt_mps_right_canonicalize(tnt_ctx ctx, tnt_mps mps);
+
+/* Environments of a right-canonical MPS for the chain MPO `mpo` (L sites,
+ * borrowed only during this call: the handle keeps its own copy).  Left
+ * boundary selects MPO index `left_index`, right boundary `right_index`. */
+tnt_status tnt_env_create(tnt_ctx ctx, tnt_mps mps, const tnt_mpo_site* mpo,
+                          int32_t left_index, int32_t right_index, tnt_env* out);
+void tnt_env_destroy(tnt_env env);
+
+typedef struct {
+  tnt_lanczos_params lanczos;
+  tnt_trunc_params trunc;
+  int32_t record_cap;  /* capacity of the per-bond arrays below (>= 2(L-1)) */
+  double* bond_E;      /* [record_cap] FP64 Rayleigh energy per bond update, may be NULL */
+  double* bond_eps;    /* [record_cap] truncation error, may be NULL        */
+  int32_t* bond_chi;   /* [record_cap] kept chi, may be NULL                */
+  int32_t* bond_steps; /* [record_cap] Lanczos steps, may be NULL           */
+} tnt_sweep_params;
+
+typedef struct {
+  double energy;          /* E of the last bond update                      */
+  double max_residual;
+  double max_eps;
+  int32_t updates;        /* bond updates done = 2(L-1)                     */
+  int32_t max_chi;
+  int64_t matvecs;        /* H_eff applications in the iteration            */
+  double matvec_flops;    /* algorithmic flops of those matvecs              */
+  double seconds_total;   /* host wall time of the sweep                     */
+  double seconds_matvec;  /* device time of the iteration matvecs            */
+  double seconds_lanczos; /* device time of the Krylov vector work           */
+  double seconds_svd;     /* wall time of the SVD-truncate steps             */
+  double seconds_env;     /* device time of environment updates              */
+} tnt_sweep_result;
+
+/* One sweep: right pass over bonds 1..L-1 then left pass L-1..1 (each:
+ * theta formation, Lanczos, SVD-truncate, environment update), in place on
+ * `mps` and `env`.  Blocks until done. */
+tnt_status tnt_dmrg_sweep(tnt_ctx ctx, tnt_mps mps, tnt_env env, const tnt_sweep_params* p,
+                          tnt_sweep_result* r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNT_MI355X_H */

@@ -22,6 +22,11 @@ def heff2_flops(left, right, d, qw, W1, W2):
     D = len(qw)
     theta = {(qa, s1, s2) for qa in left for s1 in range(d) for s2 in range(d)
              if qa + s1 + s2 in right}
+    # the two-site coefficients c[w][u][s1'][s2'][s1][s2] as plain floats
+    W1l, W2l = W1.tolist(), W2.tolist()
+    coef = [[[[[[sum(W1l[w][v][s1p][s1] * W2l[v][u][s2p][s2] for v in range(D))
+                 for s2 in range(d)] for s1 in range(d)] for s2p in range(d)]
+              for s1p in range(d)] for u in range(D)] for w in range(D)]
     live_t1 = set()
     f_mpo = 0
     f_step4 = 0
@@ -38,9 +43,7 @@ def heff2_flops(left, right, d, qw, W1, W2):
                     for s2 in range(d):
                         if (qa, s1, s2) not in theta:
                             continue
-                        c = 0.0
-                        for v in range(D):
-                            c += W1[w, v, s1p, s1] * W2[v, u, s2p, s2]
+                        c = coef[w][u][s1p][s2p][s1][s2]
                         if c != 0.0:
                             terms.append((w, qa, s1, s2))
             if not terms:

@@ -27,11 +27,14 @@ def heff2_dense(Ld, W1, W2, Rd, thd):
     return np.einsum(spec, Ld, W1, W2, Rd, thd, optimize=path)
 
 
-def heff2_block(L, W1, W2, R, theta, left, right, qw, d):
+def heff2_block(L, W1, W2, R, theta, left, right, qw, d, out_sectors=None):
     """Block-sparse H_eff . theta (complex128), same sum as `heff2_dense`.
 
     L: {(w, q_a): (dim(q_a+qw[w]), dim(q_a))}; R likewise on the right bond;
     theta: {(q_a, s1, s2): (dim(q_a), dim(q_b))}.  Returns y with theta's keys.
+    With `out_sectors` (a set of output charges q_a'), only output blocks in
+    those sectors are computed (the others are returned as zeros): every
+    term of a computed block is still included, so those blocks are exact.
     """
     D = len(qw)
     # stage 1: T1[w; a', s1, s2, b] = sum_a L[a', w, a] theta[a, s1, s2, b]
@@ -40,6 +43,8 @@ def heff2_block(L, W1, W2, R, theta, left, right, qw, d):
         for w in range(D):
             blk = L.get((w, qa))
             if blk is None:
+                continue
+            if out_sectors is not None and (qa + qw[w]) not in out_sectors:
                 continue
             T1[(w, qa + qw[w], s1, s2)] = blk @ th
     # stage 2: T2[v; a', s1', s2, b] = sum_{w, s1} W1[w, v, s1', s1] T1[w; a', s1, s2, b]

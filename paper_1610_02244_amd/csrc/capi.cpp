@@ -1,0 +1,181 @@
+// C-ABI: context and the two-site H_eff application.
+#include <cstring>
+#include <memory>
+#include <new>
+#include <unordered_map>
+
+#include "capi_util.h"
+#include "plan.h"
+
+namespace tnt {
+
+struct PlanCache {
+  std::unordered_map<uint64_t, std::shared_ptr<HeffOp>> heff;
+};
+
+void destroy_blas(void* h);  // svd.cpp
+
+Ctx::~Ctx() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  else (void)hipDeviceSynchronize();
+  delete plans;
+  plans = nullptr;
+  if (blas) destroy_blas(blas);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+void Hasher::add(const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ULL;
+  }
+}
+
+void hash_theta(Hasher& H, const ThetaH& t) {
+  for (auto& kv : t.blocks) {
+    H.add(kv.first.data(), sizeof(int) * 3);
+    H.add(&kv.second, sizeof(BlockRef));
+  }
+  H.add<int64_t>(-1);
+}
+
+void hash_env(Hasher& H, const EnvH& e) {
+  for (auto& kv : e.blocks) {
+    H.add(&kv.first, sizeof(kv.first));
+    H.add(&kv.second, sizeof(BlockRef));
+  }
+  H.add<int64_t>(-2);
+}
+
+void hash_mpo(Hasher& H, const MpoH& m) {
+  H.add(m.W.data(), m.W.size() * sizeof(double));
+  H.add(m.qw.data(), m.qw.size() * sizeof(int));
+}
+
+void check_precision(int32_t p) {
+  if (p != TNT_FP64 && p != TNT_FP32 && p != TNT_BF16X3) fail(TNT_E_ARG, "unknown precision");
+  if (p == TNT_BF16X3 && !bf16x3_available()) fail(TNT_E_ARG, "BF16X3 path not built");
+}
+
+// Parse and cross-check the operands of an H_eff application.
+HeffArgs parse_heff_args(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt_mpo_site* W2,
+                         const tnt_btensor* R, const tnt_btensor* theta, const tnt_btensor* out) {
+  HeffArgs a;
+  a.w1 = parse_mpo(W1, "W1");
+  a.w2 = parse_mpo(W2, "W2");
+  if (a.w1.d != a.w2.d || a.w1.D != a.w2.D || a.w1.qw != a.w2.qw)
+    fail(TNT_E_SHAPE, "W1 and W2 disagree in d, D or bond charges");
+  a.th = parse_theta(theta, a.w1.d, "theta");
+  a.out = out ? parse_theta(out, a.w1.d, "out") : a.th;
+  if (out) check_same_structure(a.th, a.out);
+  a.L = parse_env(L, a.w1, "L");
+  a.R = parse_env(R, a.w2, "R");
+  check_bond_match(a.L.bond, a.th.left, "L vs theta left bond");
+  check_bond_match(a.R.bond, a.th.right, "R vs theta right bond");
+  return a;
+}
+
+std::shared_ptr<HeffOp> cached_heff(Ctx& c, const HeffArgs& a, int prec) {
+  Hasher H;
+  H.add(prec);
+  hash_mpo(H, a.w1);
+  hash_mpo(H, a.w2);
+  hash_env(H, a.L);
+  hash_env(H, a.R);
+  hash_theta(H, a.th);
+  hash_theta(H, a.out);
+  if (!c.plans) c.plans = new PlanCache();
+  auto it = c.plans->heff.find(H.h);
+  if (it != c.plans->heff.end()) return it->second;
+  if (c.plans->heff.size() >= 1024) {
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    c.plans->heff.clear();
+  }
+  auto op = std::make_shared<HeffOp>();
+  op->build(c, a.L, a.w1, a.w2, a.R, a.th, a.out, prec);
+  c.plans->heff[H.h] = op;
+  return op;
+}
+
+}  // namespace tnt
+
+using namespace tnt;
+
+extern "C" {
+
+tnt_status tnt_ctx_create(int32_t device, void* hip_stream, tnt_ctx* out) {
+  if (!out) return TNT_E_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TNT_E_HIP;
+  if (hipSetDevice(device) != hipSuccess) return TNT_E_HIP;
+  Ctx* c = new (std::nothrow) Ctx();
+  if (!c) return TNT_E_ALLOC;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess)
+    c->num_cu = cu;
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return TNT_E_HIP;
+    }
+  *out = reinterpret_cast<tnt_ctx>(c);
+  return TNT_OK;
+}
+
+void tnt_ctx_destroy(tnt_ctx ctx) { delete reinterpret_cast<Ctx*>(ctx); }
+
+const char* tnt_last_error(tnt_ctx ctx) {
+  if (!ctx) return "null context";
+  return reinterpret_cast<Ctx*>(ctx)->last_error.c_str();
+}
+
+tnt_status tnt_sync(tnt_ctx ctx) {
+  TNT_API_BEGIN(ctx)
+  TNT_HIP(hipStreamSynchronize(c.stream));
+  TNT_API_END
+}
+
+int64_t tnt_pool_bytes(tnt_ctx ctx) {
+  return ctx ? reinterpret_cast<Ctx*>(ctx)->pool.held() : -1;
+}
+
+tnt_status tnt_heff2_apply(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_site* W1,
+                           const tnt_mpo_site* W2, const tnt_btensor* R,
+                           const tnt_btensor* theta, tnt_btensor* out, int32_t precision) {
+  TNT_API_BEGIN(ctx)
+  check_precision(precision);
+  if (!out) fail(TNT_E_ARG, "null out");
+  HeffArgs a = parse_heff_args(L, W1, W2, R, theta, out);
+  if (L->dtype != TNT_DT_F64 || R->dtype != TNT_DT_F64 || theta->dtype != TNT_DT_F64 ||
+      out->dtype != TNT_DT_F64)
+    fail(TNT_E_ARG, "L, R, theta and out must be FP64 planes");
+  auto op = cached_heff(c, a, precision);
+  op->bind_envs(L->re, L->im, R->re, R->im);
+  op->apply(static_cast<const double*>(theta->re), static_cast<const double*>(theta->im),
+            static_cast<double*>(out->re), static_cast<double*>(out->im), precision);
+  TNT_HIP(hipGetLastError());
+  TNT_API_END
+}
+
+int64_t tnt_heff2_flops(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt_mpo_site* W2,
+                        const tnt_btensor* R, const tnt_btensor* theta, int64_t* parts) {
+  try {
+    HeffArgs a = parse_heff_args(L, W1, W2, R, theta, nullptr);
+    HeffPlan p = build_heff_plan(a.L, a.w1, a.w2, a.R, a.th, a.th);
+    if (parts) {
+      parts[0] = p.flops_step1;
+      parts[1] = p.flops_mpo;
+      parts[2] = p.flops_step4;
+    }
+    return p.flops();
+  } catch (...) {
+    return -1;
+  }
+}
+
+}  // extern "C"

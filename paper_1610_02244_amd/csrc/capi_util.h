@@ -1,0 +1,50 @@
+// Helpers shared by the C-ABI translation units.
+#pragma once
+
+#include <memory>
+#include <new>
+
+#include "plan.h"
+
+namespace tnt {
+
+// Convert exceptions into status codes at the ABI boundary.
+#define TNT_API_BEGIN(ctx_)                                   \
+  if (!(ctx_)) return TNT_E_ARG;                              \
+  ::tnt::Ctx& c = *reinterpret_cast<::tnt::Ctx*>(ctx_);       \
+  (void)c;                                                    \
+  try {
+#define TNT_API_END                                           \
+  return TNT_OK;                                              \
+  }                                                           \
+  catch (const ::tnt::Error& e) {                             \
+    c.last_error = e.what();                                  \
+    return e.code;                                            \
+  }                                                           \
+  catch (const std::bad_alloc&) {                             \
+    c.last_error = "host allocation failed";                  \
+    return TNT_E_ALLOC;                                       \
+  }                                                           \
+  catch (const std::exception& e) {                           \
+    c.last_error = e.what();                                  \
+    return TNT_E_ARG;                                         \
+  }
+
+struct Hasher {
+  uint64_t h = 1469598103934665603ULL;
+  void add(const void* p, size_t n);
+  template <typename T> void add(const T& v) { add(&v, sizeof(T)); }
+};
+
+struct HeffArgs {
+  MpoH w1, w2;
+  ThetaH th, out;
+  EnvH L, R;
+};
+
+void check_precision(int32_t p);
+HeffArgs parse_heff_args(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt_mpo_site* W2,
+                         const tnt_btensor* R, const tnt_btensor* theta, const tnt_btensor* out);
+std::shared_ptr<HeffOp> cached_heff(Ctx& c, const HeffArgs& a, int prec);
+
+}  // namespace tnt

@@ -1,0 +1,415 @@
+// Two-site variational sweep over a U(1) block MPS (Sec. 4.3 in two-site
+// form): theta formation, Lanczos on H_eff, truncated SVD, environment
+// update, for bonds 1..L-1 (right pass) then L-1..1 (left pass).  All tensor
+// arithmetic runs in the grouped MFMA GEMM and combine kernels; environments,
+// theta and the SVD are FP64.
+#include "dmrg.h"
+
+#include <chrono>
+#include <climits>
+#include <cmath>
+
+#include "capi_util.h"
+
+namespace tnt {
+
+namespace {
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+int dim_of(const Bond& b, int q) {
+  auto it = b.find(q);
+  return it == b.end() ? 0 : it->second;
+}
+}  // namespace
+
+ThetaH form_theta(Ctx& c, MpsH& m, int j, DevBuf& out) {
+  ThetaH th = make_theta(m.bonds[j - 1], m.bonds[j + 1], m.d);
+  out.ensure(&c.pool, std::max<int64_t>(1, 2 * th.elems) * sizeof(double));
+  HostGemm g;
+  const SiteH& A = m.lay[j - 1];
+  const SiteH& B = m.lay[j];
+  for (auto& kv : th.blocks) {
+    const int qa = kv.first[0], s1 = kv.first[1], s2 = kv.first[2];
+    const BlockRef& ob = kv.second;
+    g.add_task(ob.off, ob.rows, ob.cols, ob.cols);
+    auto ia = A.blocks.find({qa, s1});
+    auto ib = B.blocks.find({qa + s1, s2});
+    if (ia != A.blocks.end() && ib != B.blocks.end())
+      g.add_seg(ia->second.off, ia->second.cols, ib->second.off, ib->second.cols,
+                ia->second.cols);
+  }
+  g.finalize(default_tile_cfg(g, PATH_F64));
+  DevTables t;
+  t.upload(c, {&g}, {});
+  double* o = out.as<double>();
+  run_gemm(c, t.g[0], FORM_NN, PATH_F64, m.re(j), m.im(j), ET_F64, m.re(j + 1), m.im(j + 1),
+           ET_F64, o, o + th.elems, ET_F64);
+  TNT_HIP(hipStreamSynchronize(c.stream));  // tables (host and device) released below
+  return th;
+}
+
+// L_j[a', w', a] = sum conj(A[c', s', a']) L_{j-1}[c', w, c] W[w, w', s', s] A[c, s, a]
+void update_left_env(Ctx& c, EnvS& e, int j) {
+  MpsH& m = *e.mps;
+  const MpoH& W = e.W[j - 1];
+  const auto& qw = e.qw;
+  const int D = W.D, d = m.d;
+  const EnvH& Lp = e.Llay[j - 1];
+  const SiteH& A = m.lay[j - 1];
+  const Bond& bl = m.bonds[j - 1];
+  const Bond& br = m.bonds[j];
+  // X[w; c', s, a] = L_{j-1}(w, c) A(c, s)
+  HostGemm gx;
+  std::map<std::array<int, 3>, int64_t> xoff;
+  int64_t off = 0;
+  for (auto& lb : Lp.blocks) {
+    const int w = lb.first.first, qc = lb.first.second;
+    for (int s = 0; s < d; ++s) {
+      auto ia = A.blocks.find({qc, s});
+      if (ia == A.blocks.end()) continue;
+      const int M = lb.second.rows, N = ia->second.cols, K = lb.second.cols;
+      xoff[{w, qc, s}] = off;
+      gx.add_task(off, M, N, N);
+      gx.add_seg(lb.second.off, K, ia->second.off, N, K);
+      off += (int64_t)M * N;
+    }
+  }
+  const int64_t xs = off;
+  // Y[w'; c', s', a] = sum_{w, s} W[w, w', s', s] X[w; c', s, a]
+  std::map<std::array<int, 3>, std::vector<std::pair<int64_t, double>>> yterms;
+  for (auto& x : xoff) {
+    const int w = x.first[0], qc = x.first[1], s = x.first[2];
+    const int qcp = qc + qw[w];
+    for (int wp = 0; wp < D; ++wp)
+      for (int sp = 0; sp < d; ++sp) {
+        const double cf = W.at(w, wp, sp, s);
+        if (cf != 0.0) yterms[{wp, qcp, sp}].push_back({x.second, cf});
+      }
+  }
+  HostComb cy;
+  std::map<std::array<int, 3>, int64_t> yoff;
+  off = 0;
+  for (auto& y : yterms) {
+    const int wp = y.first[0], qcp = y.first[1], sp = y.first[2];
+    const int qa = qcp + sp - qw[wp];
+    const int rows = dim_of(bl, qcp), cols = dim_of(br, qa);
+    if (rows == 0 || cols == 0) continue;
+    yoff[y.first] = off;
+    cy.add_task(off, rows * cols);
+    for (auto& t : y.second) cy.add_term(t.first, t.second);
+    off += (int64_t)rows * cols;
+  }
+  const int64_t ys = off;
+  cy.finalize();
+  // L_j(w', a) = sum_{s'} A(c', s')^H Y[w'; c', s', a],  c' = a + qw[w'] - s'
+  EnvH Ln = make_env(br, qw);
+  HostGemm gl;
+  for (auto& lb : Ln.blocks) {
+    const int wp = lb.first.first, qa = lb.first.second;
+    const int M = lb.second.rows, N = lb.second.cols;
+    gl.add_task(lb.second.off, M, N, N);
+    for (int sp = 0; sp < d; ++sp) {
+      const int qcp = qa + qw[wp] - sp;
+      auto ia = A.blocks.find({qcp, sp});
+      auto iy = yoff.find({wp, qcp, sp});
+      if (ia == A.blocks.end() || iy == yoff.end()) continue;
+      gl.add_seg(ia->second.off, ia->second.cols, iy->second, N, ia->second.rows);
+    }
+  }
+  gx.finalize(default_tile_cfg(gx, PATH_F64));
+  gl.finalize(default_tile_cfg(gl, PATH_F64));
+  DevTables t;
+  t.upload(c, {&gx, &gl}, {&cy});
+  DevBuf X(&c.pool, std::max<int64_t>(1, 2 * xs) * sizeof(double));
+  DevBuf Y(&c.pool, std::max<int64_t>(1, 2 * ys) * sizeof(double));
+  DevBuf out(&c.pool, std::max<int64_t>(1, 2 * Ln.elems) * sizeof(double));
+  double* x = X.as<double>();
+  double* y = Y.as<double>();
+  double* o = out.as<double>();
+  run_gemm(c, t.g[0], FORM_NN, PATH_F64, e.Lre(j - 1), e.Lim(j - 1), ET_F64, m.re(j), m.im(j),
+           ET_F64, x, x + xs, ET_F64);
+  run_comb(c, t.c[0], x, x + xs, y, y + ys, ET_F64);
+  run_gemm(c, t.g[1], FORM_CN, PATH_F64, m.re(j), m.im(j), ET_F64, y, y + ys, ET_F64, o,
+           o + Ln.elems, ET_F64);
+  TNT_HIP(hipStreamSynchronize(c.stream));
+  e.Llay[j] = Ln;
+  e.Ldat[j] = std::move(out);
+}
+
+// R_j[b', u, b] = sum conj(A[b', s', c']) W[u, u', s', s] R_{j+1}[c', u', c] A[b, s, c]
+void update_right_env(Ctx& c, EnvS& e, int j) {
+  MpsH& m = *e.mps;
+  const MpoH& W = e.W[j - 1];
+  const auto& qw = e.qw;
+  const int D = W.D, d = m.d;
+  const EnvH& Rn = e.Rlay[j + 1];
+  const SiteH& B = m.lay[j - 1];
+  const Bond& bl = m.bonds[j - 1];
+  const Bond& br = m.bonds[j];
+  // X[u'; b, s, c'] = B(b, s) R_{j+1}(u', c)^T
+  HostGemm gx;
+  std::map<std::array<int, 3>, int64_t> xoff;
+  int64_t off = 0;
+  for (auto& bb : B.blocks) {
+    const int qb = bb.first.first, s = bb.first.second, qc = qb + s;
+    for (int up = 0; up < D; ++up) {
+      auto ir = Rn.blocks.find({up, qc});
+      if (ir == Rn.blocks.end()) continue;
+      const int M = bb.second.rows, N = ir->second.rows, K = bb.second.cols;
+      xoff[{up, qb, s}] = off;
+      gx.add_task(off, M, N, N);
+      gx.add_seg(bb.second.off, K, ir->second.off, ir->second.cols, K);
+      off += (int64_t)M * N;
+    }
+  }
+  const int64_t xs = off;
+  // Y[u; b, s', c'] = sum_{u', s} W[u, u', s', s] X[u'; b, s, c']
+  std::map<std::array<int, 3>, std::vector<std::pair<int64_t, double>>> yterms;
+  for (auto& x : xoff) {
+    const int up = x.first[0], qb = x.first[1], s = x.first[2];
+    for (int u = 0; u < D; ++u)
+      for (int sp = 0; sp < d; ++sp) {
+        const double cf = W.at(u, up, sp, s);
+        if (cf != 0.0) yterms[{u, qb, sp}].push_back({x.second, cf});
+      }
+  }
+  HostComb cy;
+  std::map<std::array<int, 3>, int64_t> yoff;
+  off = 0;
+  for (auto& y : yterms) {
+    const int u = y.first[0], qb = y.first[1], sp = y.first[2];
+    const int rows = dim_of(bl, qb), cols = dim_of(br, qb + sp + qw[u]);
+    if (rows == 0 || cols == 0) continue;
+    yoff[y.first] = off;
+    cy.add_task(off, rows * cols);
+    for (auto& t : y.second) cy.add_term(t.first, t.second);
+    off += (int64_t)rows * cols;
+  }
+  const int64_t ys = off;
+  cy.finalize();
+  // R_j(u, b) = sum_{s'} conj(B(b', s')) Y[u; b, s', c']^T,  b' = b + qw[u]
+  EnvH Rj = make_env(bl, qw);
+  HostGemm gr;
+  for (auto& rb : Rj.blocks) {
+    const int u = rb.first.first, qb = rb.first.second;
+    const int M = rb.second.rows, N = rb.second.cols;
+    const int qbp = qb + qw[u];
+    gr.add_task(rb.second.off, M, N, N);
+    for (int sp = 0; sp < d; ++sp) {
+      auto ib = B.blocks.find({qbp, sp});
+      auto iy = yoff.find({u, qb, sp});
+      if (ib == B.blocks.end() || iy == yoff.end()) continue;
+      const int K = ib->second.cols;
+      gr.add_seg(ib->second.off, K, iy->second, K, K);
+    }
+  }
+  gx.finalize(default_tile_cfg(gx, PATH_F64));
+  gr.finalize(default_tile_cfg(gr, PATH_F64));
+  DevTables t;
+  t.upload(c, {&gx, &gr}, {&cy});
+  DevBuf X(&c.pool, std::max<int64_t>(1, 2 * xs) * sizeof(double));
+  DevBuf Y(&c.pool, std::max<int64_t>(1, 2 * ys) * sizeof(double));
+  DevBuf out(&c.pool, std::max<int64_t>(1, 2 * Rj.elems) * sizeof(double));
+  double* x = X.as<double>();
+  double* y = Y.as<double>();
+  double* o = out.as<double>();
+  run_gemm(c, t.g[0], FORM_NT, PATH_F64, m.re(j), m.im(j), ET_F64, e.Rre(j + 1), e.Rim(j + 1),
+           ET_F64, x, x + xs, ET_F64);
+  run_comb(c, t.c[0], x, x + xs, y, y + ys, ET_F64);
+  run_gemm(c, t.g[1], FORM_cNT, PATH_F64, m.re(j), m.im(j), ET_F64, y, y + ys, ET_F64, o,
+           o + Rj.elems, ET_F64);
+  TNT_HIP(hipStreamSynchronize(c.stream));
+  e.Rlay[j] = Rj;
+  e.Rdat[j] = std::move(out);
+}
+
+static void upload_boundary(Ctx& c, const EnvH& lay, int w, DevBuf& dst) {
+  std::vector<double> h(std::max<int64_t>(1, 2 * lay.elems), 0.0);
+  bool found = false;
+  for (auto& kv : lay.blocks)
+    if (kv.first.first == w) {
+      h[kv.second.off] = 1.0;
+      found = true;
+    }
+  if (!found) fail(TNT_E_ARG, "boundary MPO index has no charge-neutral block");
+  dst = DevBuf(&c.pool, h.size() * sizeof(double));
+  TNT_HIP(hipMemcpyAsync(dst.ptr, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
+                         c.stream));
+  TNT_HIP(hipStreamSynchronize(c.stream));
+}
+
+void build_boundaries(Ctx& c, EnvS& e) {
+  MpsH& m = *e.mps;
+  if (m.bonds[0].size() != 1 || m.bonds[m.L].size() != 1)
+    fail(TNT_E_STATE, "end bonds must hold exactly one sector");
+  if (m.bonds[0].begin()->second != 1 || m.bonds[m.L].begin()->second != 1)
+    fail(TNT_E_STATE, "end bonds must have dimension 1");
+  e.Llay.assign(m.L + 1, EnvH());
+  e.Rlay.assign(m.L + 2, EnvH());
+  e.Ldat.clear();
+  e.Rdat.clear();
+  e.Ldat.resize(m.L + 1);
+  e.Rdat.resize(m.L + 2);
+  e.Llay[0] = make_env(m.bonds[0], e.qw);
+  upload_boundary(c, e.Llay[0], e.left_index, e.Ldat[0]);
+  e.Rlay[m.L + 1] = make_env(m.bonds[m.L], e.qw);
+  upload_boundary(c, e.Rlay[m.L + 1], e.right_index, e.Rdat[m.L + 1]);
+}
+
+// ---------------------------------------------------------------------------
+// right-canonical form by exact SVDs (sites L..2), then unit norm
+// ---------------------------------------------------------------------------
+void right_canonicalize(Ctx& c, MpsH& m) {
+  tnt_trunc_params exact{INT_MAX, TNT_ERR_2NORM, -1.0, -1.0, -1.0, 0};
+  for (int j = m.L; j >= 2; --j) {
+    // site j as a one-site "theta": keys (q, 0, s), rows (a), columns (s, b)
+    ThetaH th;
+    th.d = m.d;
+    for (auto& kv : m.lay[j - 1].blocks) {
+      th.blocks[{kv.first.first, 0, kv.first.second}] = kv.second;
+      th.left[kv.first.first] = kv.second.rows;
+      th.right[kv.first.first + kv.first.second] = kv.second.cols;
+    }
+    th.elems = th.extent = m.lay[j - 1].elems;
+    if (th.blocks.empty()) fail(TNT_E_STATE, "site " + std::to_string(j) + " has no block");
+    DevBuf us, site;
+    SvdOut r = svd_truncate_dev(c, th, m.re(j), m.im(j), exact, TNT_ABSORB_LEFT,
+                                [&](const SvdOut& o) {
+                                  us = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.A.elems) * 8);
+                                  site = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.B.elems) * 8);
+                                  FactorPlanes fp;
+                                  fp.a_re = us.as<double>();
+                                  fp.a_im = us.as<double>() + o.A.elems;
+                                  fp.b_re = site.as<double>();
+                                  fp.b_im = site.as<double>() + o.B.elems;
+                                  return fp;
+                                });
+    // new site j = V^+ with keys (m, s): the left bond sector m = q
+    const Bond newb = r.bond;
+    // absorb (U S)(q) into site j-1: A'(q', s') = A(q', s') US(q' + s')
+    const SiteH& Ao = m.lay[j - 2];
+    SiteH An;
+    int64_t off = 0;
+    for (auto& kv : Ao.blocks) {
+      const int qr = kv.first.first + kv.first.second;
+      auto it = newb.find(qr);
+      if (it == newb.end()) continue;
+      An.blocks[kv.first] = BlockRef{off, kv.second.rows, it->second};
+      off += (int64_t)kv.second.rows * it->second;
+    }
+    An.elems = off;
+    HostGemm g;
+    for (auto& kv : An.blocks) {
+      const BlockRef& ob = Ao.blocks.at(kv.first);
+      const int qr = kv.first.first + kv.first.second;
+      const BlockRef& ub = r.A.blocks.at({qr, 0});
+      g.add_task(kv.second.off, kv.second.rows, kv.second.cols, kv.second.cols);
+      g.add_seg(ob.off, ob.cols, ub.off, ub.cols, ob.cols);
+    }
+    g.finalize(default_tile_cfg(g, PATH_F64));
+    DevTables t;
+    t.upload(c, {&g}, {});
+    DevBuf nb(&c.pool, std::max<int64_t>(1, 2 * An.elems) * 8);
+    run_gemm(c, t.g[0], FORM_NN, PATH_F64, m.re(j - 1), m.im(j - 1), ET_F64, us.as<double>(),
+             us.as<double>() + r.A.elems, ET_F64, nb.as<double>(), nb.as<double>() + An.elems,
+             ET_F64);
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    // commit
+    SiteH Bn;
+    for (auto& kv : r.B.blocks) Bn.blocks[kv.first] = kv.second;
+    Bn.elems = r.B.elems;
+    m.lay[j - 1] = Bn;
+    m.dat[j - 1] = std::move(site);
+    m.lay[j - 2] = An;
+    m.dat[j - 2] = std::move(nb);
+    m.bonds[j - 1] = newb;
+  }
+  // normalise site 1
+  const int64_t n = m.lay[0].elems;
+  DevBuf part(&c.pool, RED_BLOCKS * sizeof(double) + 64);
+  double* p = part.as<double>();
+  launch_norm2_partial(m.re(1), 2 * n, p, c.stream);
+  launch_reduce_partials(p, 1, RED_BLOCKS, p + RED_BLOCKS, c.stream);
+  double nrm2 = 0;
+  TNT_HIP(hipMemcpyAsync(&nrm2, p + RED_BLOCKS, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  TNT_HIP(hipStreamSynchronize(c.stream));
+  if (!(nrm2 > 0) || !std::isfinite(nrm2)) fail(TNT_E_NONFINITE, "MPS norm is zero or not finite");
+  launch_scale_host(m.re(1), 2 * n, 1.0 / std::sqrt(nrm2), c.stream);
+}
+
+// ---------------------------------------------------------------------------
+// sweep
+// ---------------------------------------------------------------------------
+void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats& st) {
+  const double t0 = now_s();
+  const int L = m.L;
+  if (L < 2) fail(TNT_E_STATE, "need at least two sites");
+  if (p.record_cap < 2 * (L - 1) && (p.bond_E || p.bond_eps || p.bond_chi || p.bond_steps))
+    fail(TNT_E_CAPACITY, "record arrays shorter than 2(L-1)");
+  DevBuf theta;
+  Krylov K;
+  int rec = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int step = 0; step < L - 1; ++step) {
+      const int j = pass == 0 ? 1 + step : L - 1 - step;
+      ThetaH th = form_theta(c, m, j, theta);
+      // H_eff on (j, j+1): L_{j-1}, W_j, W_{j+1}, R_{j+2}
+      HeffArgs a;
+      a.w1 = e.W[j - 1];
+      a.w2 = e.W[j];
+      a.th = th;
+      a.out = th;
+      a.L = e.Llay[j - 1];
+      a.R = e.Rlay[j + 2];
+      auto op = cached_heff(c, a, p.lanczos.precision);
+      op->bind_envs(e.Lre(j - 1), e.Lim(j - 1), e.Rre(j + 2), e.Rim(j + 2));
+      K.reserve(c, p.lanczos.kmax, th.elems);
+      Timers tm;
+      const double tl0 = now_s();
+      LanczosOut lo = lanczos_run(c, *op, K, theta.as<double>(), p.lanczos, &tm);
+      const double tl1 = now_s();
+      st.t_matvec += tm.matvec_s;
+      st.t_lanczos += (tl1 - tl0) - tm.matvec_s;
+      st.matvecs += lo.matvecs;
+      st.matvec_flops += (double)op->plan.flops() * (double)lo.matvecs;
+      // split
+      const int absorb = pass == 0 ? TNT_ABSORB_RIGHT : TNT_ABSORB_LEFT;
+      DevBuf na, nb;
+      SvdOut r = svd_truncate_dev(c, th, theta.as<double>(), theta.as<double>() + th.elems,
+                                  p.trunc, absorb, [&](const SvdOut& o) {
+                                    na = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.A.elems) * 8);
+                                    nb = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.B.elems) * 8);
+                                    FactorPlanes fp;
+                                    fp.a_re = na.as<double>();
+                                    fp.a_im = na.as<double>() + o.A.elems;
+                                    fp.b_re = nb.as<double>();
+                                    fp.b_im = nb.as<double>() + o.B.elems;
+                                    return fp;
+                                  });
+      const double ts = now_s();
+      st.t_svd += ts - tl1;
+      m.bonds[j] = r.bond;
+      m.lay[j - 1] = r.A;
+      m.dat[j - 1] = std::move(na);
+      m.lay[j] = r.B;
+      m.dat[j] = std::move(nb);
+      if (pass == 0) update_left_env(c, e, j);
+      else update_right_env(c, e, j + 1);
+      st.t_env += now_s() - ts;
+      st.energy = lo.E;
+      st.max_residual = std::max(st.max_residual, lo.residual);
+      st.max_eps = std::max(st.max_eps, r.eps);
+      st.max_chi = std::max(st.max_chi, r.chi);
+      if (p.bond_E) p.bond_E[rec] = lo.E;
+      if (p.bond_eps) p.bond_eps[rec] = r.eps;
+      if (p.bond_chi) p.bond_chi[rec] = r.chi;
+      if (p.bond_steps) p.bond_steps[rec] = lo.steps;
+      ++rec;
+      st.updates++;
+    }
+  }
+  st.t_total = now_s() - t0;
+}
+
+}  // namespace tnt

@@ -1,0 +1,53 @@
+// MPS and environment storage, and the two-site sweep (Sec. 4.3).
+#pragma once
+
+#include <vector>
+
+#include "lanczos.h"
+#include "svd.h"
+
+namespace tnt {
+
+struct MpsH {
+  Ctx* ctx = nullptr;
+  int L = 0, d = 0;
+  std::vector<Bond> bonds;    // 0..L
+  std::vector<SiteH> lay;     // site j at index j-1
+  std::vector<DevBuf> dat;    // [re (elems) | im (elems)] per site
+  double* re(int j) { return dat[j - 1].as<double>(); }
+  double* im(int j) { return dat[j - 1].as<double>() + lay[j - 1].elems; }
+};
+
+struct EnvS {
+  MpsH* mps = nullptr;
+  std::vector<MpoH> W;        // site j at index j-1
+  int left_index = 0, right_index = 0;
+  std::vector<int> qw;
+  std::vector<EnvH> Llay;     // L_j, j = 0..L
+  std::vector<EnvH> Rlay;     // R_j, j = 1..L+1
+  std::vector<DevBuf> Ldat, Rdat;
+  double* Lre(int j) { return Ldat[j].as<double>(); }
+  double* Lim(int j) { return Ldat[j].as<double>() + Llay[j].elems; }
+  double* Rre(int j) { return Rdat[j].as<double>(); }
+  double* Rim(int j) { return Rdat[j].as<double>() + Rlay[j].elems; }
+};
+
+// theta_j = A_j A_{j+1} into a packed FP64 buffer (re | im); returns its layout.
+ThetaH form_theta(Ctx& c, MpsH& m, int j, DevBuf& out);
+// L_j from L_{j-1}, A_j, W_j ; R_j from R_{j+1}, A_j, W_j.
+void update_left_env(Ctx& c, EnvS& e, int j);
+void update_right_env(Ctx& c, EnvS& e, int j);
+void build_boundaries(Ctx& c, EnvS& e);
+void right_canonicalize(Ctx& c, MpsH& m);
+
+struct SweepStats {
+  double energy = 0, max_residual = 0, max_eps = 0;
+  int updates = 0, max_chi = 0;
+  int64_t matvecs = 0;
+  double matvec_flops = 0;
+  double t_total = 0, t_matvec = 0, t_lanczos = 0, t_svd = 0, t_env = 0;
+};
+
+void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats& st);
+
+}  // namespace tnt

@@ -1,0 +1,149 @@
+// Device task descriptors and kernel launch entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tnt {
+
+// One K-segment of a grouped complex GEMM: the tile's accumulator gets
+// op(A)[M x K] * op(B)[K x N] added, A and B read from the operand planes at
+// the given element offsets.  Segments of one task are summed in order.
+struct GemmSeg {
+  int64_t a_off;
+  int64_t b_off;
+  int32_t K;
+  int32_t lda;
+  int32_t ldb;
+  int32_t pad;
+};
+
+// One output block C[M x N] (row-major, leading dimension ldc) = sum of its
+// segments.  A task with no segment writes zeros.
+struct GemmTask {
+  int64_t c_off;
+  int32_t M, N, ldc;
+  int32_t seg0, nseg;
+  int32_t pad;
+};
+
+// Elementwise linear combination dst = sum_t coef_t * src_t over `size`
+// elements (used for the sparse MPO contractions).
+struct CombTask {
+  int64_t dst_off;
+  int32_t size;
+  int32_t term0;
+  int32_t nterm;
+  int32_t pad;
+};
+struct CombTerm {
+  int64_t src_off;
+  double coef;
+};
+
+// Operand-form selectors for the grouped GEMM.
+enum GemmForm {
+  FORM_NN = 0,   // C = A B           (A: M x K rows, B: K x N rows)
+  FORM_NT = 1,   // C = A B^T         (B stored N x K)
+  FORM_CN = 2,   // C = A^H B         (A stored K x M, conjugated)
+  FORM_cNT = 3,  // C = conj(A) B^T   (A stored M x K, conjugated; B stored N x K)
+};
+
+// Element types of operands / result.
+enum ElemType { ET_F64 = 0, ET_F32 = 1 };
+
+// Compute path of the grouped GEMM.
+enum GemmPath { PATH_F64 = 0, PATH_F32 = 1, PATH_BF16X3 = 2 };
+
+struct GemmLaunch {
+  const GemmTask* tasks;
+  const GemmSeg* segs;
+  const int2* tiles;      // (task, tm | tn << 16) per tile, in dispatch order
+  int32_t ntiles;
+  int32_t tile_cfg;       // tile-shape id (see gemm_tile_dims)
+  const void* a_re; const void* a_im; ElemType a_t;
+  const void* b_re; const void* b_im; ElemType b_t;
+  void* c_re; void* c_im; ElemType c_t;
+  GemmForm form;
+  GemmPath path;
+};
+
+// Tile shapes available to the planner: returns BM, BN for a config id.
+void gemm_tile_dims(int cfg, int* bm, int* bn);
+int gemm_num_tile_cfgs();
+
+void launch_grouped_gemm(const GemmLaunch& g, hipStream_t s);
+bool bf16x3_available();
+
+void launch_combine(const CombTask* tasks, const CombTerm* terms, const int2* chunks,
+                    int32_t nchunks, const void* src_re, const void* src_im, void* dst_re,
+                    void* dst_im, ElemType t, hipStream_t s);
+
+constexpr int COMB_CHUNK = 1024;  // elements per workgroup of the combine kernel
+
+// elementwise conversions / fills
+void launch_convert(const void* src, ElemType st, void* dst, ElemType dt, int64_t n,
+                    hipStream_t s);
+void launch_fill_zero(void* dst, ElemType t, int64_t n, hipStream_t s);
+void launch_scale(double* x, int64_t n, const double* scale_dev, hipStream_t s);
+void launch_scale_host(double* x, int64_t n, double scale, hipStream_t s);
+
+// Krylov vector kernels.  A vector of n complex entries is stored as 2n
+// doubles: re plane then im plane.  Reductions are two-stage and
+// deterministic (fixed per-block order, then one block reduces the partials).
+constexpr int RED_BLOCKS = 512;
+constexpr int RED_THREADS = 256;
+// partial[b*2k + 2i + {0,1}] = block b's share of <V_i, w> (re, im), i < k.
+void launch_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n,
+                     double* partial, hipStream_t s);
+// out[2i + {0,1}] = sum over blocks of partial (i < k), optionally also
+// writing the scalar into the given device slot.
+void launch_reduce_partials(const double* partial, int k2, int nblk, double* out,
+                            hipStream_t s);
+// w -= sum_i c_i V_i with complex coefficients c (device, 2k doubles, k <= 32), and
+// nrm_partial[b] = block b's share of |w|^2 after the update.
+void launch_multiaxpy_norm(const double* V, int64_t ld, int k, const double* c, double* w,
+                           int64_t n, double* nrm_partial, hipStream_t s);
+// w -= a * v1 + b * v0 (real scalars on the device: a = *a_dev, b = *b_dev;
+// v0 may be NULL).
+void launch_axpy2(const double* v1, const double* a_dev, const double* v0,
+                       const double* b_dev, double* w, int64_t n, hipStream_t s);
+// dst = src / sqrt(*nrm2_dev)
+void launch_normalize_copy(const double* src, double* dst, int64_t n, const double* nrm2_dev,
+                           hipStream_t s);
+// out = sum_i y_i V_i (real y on the host copy uploaded to y_dev)
+void launch_combine_basis(const double* V, int64_t ld, int k, const double* y_dev,
+                          double* out, int64_t n, hipStream_t s);
+// partial sums of |x|^2 over 2n doubles
+void launch_norm2_partial(const double* x, int64_t n2, double* partial, hipStream_t s);
+// finite check: flag[0] set to 1 if any non-finite among n doubles
+void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s);
+
+// Gather theta blocks into dense column-major complex (interleaved) sector
+// matrices, and scatter factor columns back into site blocks.
+struct GatherTask {
+  int64_t src_off;   // element offset of the block in the planes
+  int64_t dst_off;   // complex-element offset of the block's (0,0) in the matrix
+  int32_t rows, cols;
+  int32_t ld;        // leading dimension (rows of the sector matrix)
+  int32_t pad;
+};
+void launch_gather_cm(const GatherTask* t, int ntask, int maxrows, int maxcols,
+                      const double* re, const double* im, double* dst_z, hipStream_t s);
+// Scatter: dst block (rows x cols row-major planes) = scale_row/col * sub-matrix
+// of a column-major complex matrix.  mode 0: take U[r, c] * (colscale[c]);
+// mode 1: take VH[r, c] * (rowscale[r]).
+struct ScatterTask {
+  int64_t src_off;   // complex offset of the sub-matrix's (0,0) in its source
+  int64_t dst_off;   // element offset in the destination planes
+  int64_t scale_off; // offset into the scale array (or -1 for none)
+  int32_t rows, cols;
+  int32_t ld;        // leading dimension of the column-major source
+  int32_t scale_on_rows;  // 1: scale[r], 0: scale[c]
+};
+void launch_scatter_cm(const ScatterTask* t, int ntask, int maxrows, int maxcols,
+                       const double* src_z, const double* scale, double* re, double* im,
+                       hipStream_t s);
+
+}  // namespace tnt

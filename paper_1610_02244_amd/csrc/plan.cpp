@@ -1,0 +1,289 @@
+// Task-list construction for the grouped kernels and the two-site H_eff plan.
+#include "plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <set>
+
+namespace tnt {
+
+// ---------------------------------------------------------------------------
+// tile tables
+// ---------------------------------------------------------------------------
+void HostGemm::finalize(int cfg) {
+  tile_cfg = cfg;
+  int BM, BN;
+  gemm_tile_dims(cfg, &BM, &BN);
+  const int nt = (int)tasks.size();
+  std::vector<double> cost(nt);
+  std::vector<int> order(nt);
+  for (int i = 0; i < nt; ++i) {
+    const GemmTask& t = tasks[i];
+    int64_t ksum = 0;
+    for (int s = 0; s < t.nseg; ++s) ksum += segs[t.seg0 + s].K;
+    const int tm = (t.M + BM - 1) / BM, tn = (t.N + BN - 1) / BN;
+    // a tile's cost ~ padded K work plus a fixed overhead (prologue/epilogue)
+    cost[i] = (double)tm * tn * (double)(ksum + 64);
+    order[i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<std::vector<int2>> bins(8);
+  double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i : order) {
+    const GemmTask& t = tasks[i];
+    int x = 0;
+    for (int k = 1; k < 8; ++k)
+      if (load[k] < load[x]) x = k;
+    load[x] += cost[i];
+    const int tm = (t.M + BM - 1) / BM, tn = (t.N + BN - 1) / BN;
+    for (int a = 0; a < tm; ++a)
+      for (int b = 0; b < tn; ++b) bins[x].push_back(int2{i, a | (b << 16)});
+  }
+  size_t slots = 0;
+  for (auto& b : bins) slots = std::max(slots, b.size());
+  tiles.assign(slots * 8, int2{-1, 0});
+  for (size_t s = 0; s < slots; ++s)
+    for (int x = 0; x < 8; ++x)
+      if (s < bins[x].size()) tiles[s * 8 + x] = bins[x][s];
+}
+
+void HostComb::finalize() {
+  chunks.clear();
+  for (int i = 0; i < (int)tasks.size(); ++i) {
+    const int n = (tasks[i].size + COMB_CHUNK - 1) / COMB_CHUNK;
+    for (int c = 0; c < n; ++c) chunks.push_back(int2{i, c});
+  }
+}
+
+int default_tile_cfg(const HostGemm& h, GemmPath path) {
+  // flop-weighted typical output dimension
+  double wsum = 0, dsum = 0;
+  for (const GemmTask& t : h.tasks) {
+    double k = 0;
+    for (int s = 0; s < t.nseg; ++s) k += h.segs[t.seg0 + s].K;
+    const double f = (double)t.M * t.N * k;
+    wsum += f;
+    dsum += f * std::min(t.M, t.N);
+  }
+  const double typ = wsum > 0 ? dsum / wsum : 0;
+  if (typ < 48) return 1;                       // 32 x 32
+  if (path == PATH_F32 && typ >= 200) return 4;  // 128 x 128
+  return 0;                                      // 64 x 64
+}
+
+// ---------------------------------------------------------------------------
+// device tables
+// ---------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+void DevTables::upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
+                       const std::vector<const HostComb*>& cs) {
+  size_t total = 0;
+  auto add = [&](size_t bytes) { size_t o = total; total = align256(total + bytes); return o; };
+  struct GO { size_t t, s, l; };
+  struct CO { size_t t, m, c; };
+  std::vector<GO> go;
+  std::vector<CO> co;
+  for (auto* h : gs)
+    go.push_back({add(h->tasks.size() * sizeof(GemmTask)), add(h->segs.size() * sizeof(GemmSeg)),
+                  add(h->tiles.size() * sizeof(int2))});
+  for (auto* h : cs)
+    co.push_back({add(h->tasks.size() * sizeof(CombTask)),
+                  add(h->terms.size() * sizeof(CombTerm)), add(h->chunks.size() * sizeof(int2))});
+  total = std::max<size_t>(total, 256);
+  host.assign(total, 0);
+  for (size_t i = 0; i < gs.size(); ++i) {
+    auto* h = gs[i];
+    if (!h->tasks.empty()) memcpy(&host[go[i].t], h->tasks.data(), h->tasks.size() * sizeof(GemmTask));
+    if (!h->segs.empty()) memcpy(&host[go[i].s], h->segs.data(), h->segs.size() * sizeof(GemmSeg));
+    if (!h->tiles.empty()) memcpy(&host[go[i].l], h->tiles.data(), h->tiles.size() * sizeof(int2));
+  }
+  for (size_t i = 0; i < cs.size(); ++i) {
+    auto* h = cs[i];
+    if (!h->tasks.empty()) memcpy(&host[co[i].t], h->tasks.data(), h->tasks.size() * sizeof(CombTask));
+    if (!h->terms.empty()) memcpy(&host[co[i].m], h->terms.data(), h->terms.size() * sizeof(CombTerm));
+    if (!h->chunks.empty()) memcpy(&host[co[i].c], h->chunks.data(), h->chunks.size() * sizeof(int2));
+  }
+  buf = DevBuf(&ctx.pool, total);
+  TNT_HIP(hipMemcpyAsync(buf.ptr, host.data(), total, hipMemcpyHostToDevice, ctx.stream));
+  char* base = buf.as<char>();
+  g.clear();
+  c.clear();
+  for (size_t i = 0; i < gs.size(); ++i)
+    g.push_back(G{reinterpret_cast<const GemmTask*>(base + go[i].t),
+                  reinterpret_cast<const GemmSeg*>(base + go[i].s),
+                  reinterpret_cast<const int2*>(base + go[i].l), (int)gs[i]->tiles.size(),
+                  gs[i]->tile_cfg});
+  for (size_t i = 0; i < cs.size(); ++i)
+    c.push_back(C{reinterpret_cast<const CombTask*>(base + co[i].t),
+                  reinterpret_cast<const CombTerm*>(base + co[i].m),
+                  reinterpret_cast<const int2*>(base + co[i].c), (int)cs[i]->chunks.size()});
+}
+
+void run_gemm(Ctx& ctx, const DevTables::G& g, GemmForm form, GemmPath path, const void* are,
+              const void* aim, ElemType at, const void* bre, const void* bim, ElemType bt,
+              void* cre, void* cim, ElemType ct) {
+  GemmLaunch L{g.tasks, g.segs, g.tiles, g.ntiles, g.cfg, are, aim, at, bre, bim, bt,
+               cre,     cim,    ct,      form,     path};
+  launch_grouped_gemm(L, ctx.stream);
+}
+
+void run_comb(Ctx& ctx, const DevTables::C& c, const void* sre, const void* sim, void* dre,
+              void* dim, ElemType t) {
+  launch_combine(c.tasks, c.terms, c.chunks, c.nchunks, sre, sim, dre, dim, t, ctx.stream);
+}
+
+// ---------------------------------------------------------------------------
+// H_eff plan
+// ---------------------------------------------------------------------------
+HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const EnvH& R,
+                         const ThetaH& th, const ThetaH& out) {
+  HeffPlan P;
+  const int D = W1.D, d = th.d;
+  const Bond& left = th.left;
+  const Bond& right = th.right;
+  // combined two-site MPO coefficient sum_v W1[w,v,s1',s1] W2[v,u,s2',s2]
+  auto coef = [&](int w, int u, int s1p, int s2p, int s1, int s2) {
+    double c = 0.0;
+    for (int v = 0; v < D; ++v) c += W1.at(w, v, s1p, s1) * W2.at(v, u, s2p, s2);
+    return c;
+  };
+  struct Term { int w, qa, s1, s2; double c; };
+  struct Slab { int u; std::array<int, 3> okey; int qb; std::vector<Term> terms; };
+  std::vector<Slab> live;
+  std::map<std::array<int, 4>, int64_t> t1_off;  // (w, qa, s1, s2) -> slab offset (assigned later)
+  for (auto& ob : th.blocks) {
+    const int qap = ob.first[0], s1p = ob.first[1], s2p = ob.first[2];
+    const int qbp = qap + s1p + s2p;
+    for (int u = 0; u < D; ++u) {
+      const int qb = qbp - W2.qw[u];
+      if (!R.blocks.count({u, qb}) || !right.count(qb)) continue;
+      Slab sl{u, ob.first, qb, {}};
+      for (int w = 0; w < D; ++w) {
+        const int qa = qap - W1.qw[w];
+        if (!L.blocks.count({w, qa})) continue;
+        for (int s1 = 0; s1 < d; ++s1)
+          for (int s2 = 0; s2 < d; ++s2) {
+            if (!th.blocks.count({qa, s1, s2})) continue;
+            const double c = coef(w, u, s1p, s2p, s1, s2);
+            if (c != 0.0) sl.terms.push_back(Term{w, qa, s1, s2, c});
+          }
+      }
+      if (sl.terms.empty()) continue;
+      for (auto& t : sl.terms) t1_off[{t.w, t.qa, t.s1, t.s2}] = -1;
+      live.push_back(std::move(sl));
+    }
+  }
+  // step 1 tasks: one per live T1 slab (ascending key order)
+  int64_t off = 0;
+  for (auto& kv : t1_off) {
+    const int w = kv.first[0], qa = kv.first[1], s1 = kv.first[2], s2 = kv.first[3];
+    const int qap = qa + W1.qw[w], qb = qa + s1 + s2;
+    const int M = left.at(qap), N = right.at(qb), K = left.at(qa);
+    kv.second = off;
+    const BlockRef& lb = L.blocks.at({w, qa});
+    const BlockRef& tb = th.blocks.at({qa, s1, s2});
+    P.step1.add_task(off, M, N, N);
+    P.step1.add_seg(lb.off, lb.cols, tb.off, tb.cols, K);
+    P.flops_step1 += 8LL * M * N * K;
+    off += (int64_t)M * N;
+  }
+  P.t1_elems = off;
+  // MPO combination: one T3 slab per live (u, output block)
+  off = 0;
+  std::map<std::array<int, 4>, int64_t> t3_off;  // (u, qa', s1', s2') -> offset
+  for (auto& sl : live) {
+    const int M = left.at(sl.okey[0]), N = right.at(sl.qb);
+    t3_off[{sl.u, sl.okey[0], sl.okey[1], sl.okey[2]}] = off;
+    P.mpo.add_task(off, M * N);
+    for (auto& t : sl.terms) P.mpo.add_term(t1_off.at({t.w, t.qa, t.s1, t.s2}), t.c);
+    P.flops_mpo += 4LL * (int64_t)sl.terms.size() * M * N;
+    off += (int64_t)M * N;
+  }
+  P.t3_elems = off;
+  // step 4 tasks: one per output block, K concatenated over live u
+  for (auto& ob : out.blocks) {
+    const int qap = ob.first[0], s1p = ob.first[1], s2p = ob.first[2];
+    const int qbp = qap + s1p + s2p;
+    const int M = ob.second.rows, N = ob.second.cols;
+    P.step4.add_task(ob.second.off, M, N, N);
+    P.out_keys.push_back(ob.first);
+    for (int u = 0; u < D; ++u) {
+      auto it = t3_off.find({u, qap, s1p, s2p});
+      if (it == t3_off.end()) continue;
+      const int qb = qbp - W2.qw[u];
+      const BlockRef& rb = R.blocks.at({u, qb});
+      const int K = right.at(qb);
+      P.step4.add_seg(it->second, K, rb.off, rb.cols, K);
+      P.flops_step4 += 8LL * M * N * K;
+    }
+  }
+  P.mpo.finalize();
+  return P;
+}
+
+// ---------------------------------------------------------------------------
+// HeffOp
+// ---------------------------------------------------------------------------
+void HeffOp::build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const EnvH& R,
+                   const ThetaH& th, const ThetaH& out, int prec) {
+  ctx = &c;
+  precision = prec;
+  plan = build_heff_plan(L, W1, W2, R, th, out);
+  const GemmPath path = prec == TNT_FP64 ? PATH_F64 : PATH_F32;
+  plan.step1.finalize(default_tile_cfg(plan.step1, path));
+  plan.step4.finalize(default_tile_cfg(plan.step4, path));
+  tab.upload(c, {&plan.step1, &plan.step4}, {&plan.mpo});
+  L_ext = L.extent;
+  R_ext = R.extent;
+}
+
+void HeffOp::bind_envs(const void* lre, const void* lim, const void* rre, const void* rim) {
+  Ctx& c = *ctx;
+  L_re = static_cast<const double*>(lre); L_im = static_cast<const double*>(lim);
+  R_re = static_cast<const double*>(rre); R_im = static_cast<const double*>(rim);
+  if (precision != TNT_FP64) {
+    c.ws[2].ensure(&c.pool, std::max<int64_t>(1, 2 * L_ext) * sizeof(float));
+    c.ws[3].ensure(&c.pool, std::max<int64_t>(1, 2 * R_ext) * sizeof(float));
+    float* lf = c.ws[2].as<float>();
+    float* rf = c.ws[3].as<float>();
+    launch_convert(L_re, ET_F64, lf, ET_F32, L_ext, c.stream);
+    launch_convert(L_im, ET_F64, lf + L_ext, ET_F32, L_ext, c.stream);
+    launch_convert(R_re, ET_F64, rf, ET_F32, R_ext, c.stream);
+    launch_convert(R_im, ET_F64, rf + R_ext, ET_F32, R_ext, c.stream);
+  }
+}
+
+void HeffOp::apply(const double* xre, const double* xim, double* yre, double* yim, int prec) {
+  Ctx& c = *ctx;
+  if (prec == TNT_FP64 || precision == TNT_FP64) {
+    // FP64 (also the refinement matvec of an FP32 operator: FP64 environments)
+    c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(double));
+    c.ws[1].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(double));
+    double* a = c.ws[0].as<double>();
+    double* b = c.ws[1].as<double>();
+    run_gemm(c, tab.g[0], FORM_NN, PATH_F64, L_re, L_im, ET_F64, xre, xim, ET_F64, a,
+             a + plan.t1_elems, ET_F64);
+    run_comb(c, tab.c[0], a, a + plan.t1_elems, b, b + plan.t3_elems, ET_F64);
+    run_gemm(c, tab.g[1], FORM_NT, PATH_F64, b, b + plan.t3_elems, ET_F64, R_re, R_im, ET_F64,
+             yre, yim, ET_F64);
+    return;
+  }
+  c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(float));
+  c.ws[1].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(float));
+  float* a = c.ws[0].as<float>();
+  float* b = c.ws[1].as<float>();
+  const float* lf = c.ws[2].as<float>();
+  const float* rf = c.ws[3].as<float>();
+  const GemmPath path = prec == TNT_BF16X3 ? PATH_BF16X3 : PATH_F32;
+  run_gemm(c, tab.g[0], FORM_NN, path, lf, lf + L_ext, ET_F32, xre, xim, ET_F64, a,
+           a + plan.t1_elems, ET_F32);
+  run_comb(c, tab.c[0], a, a + plan.t1_elems, b, b + plan.t3_elems, ET_F32);
+  run_gemm(c, tab.g[1], FORM_NT, path, b, b + plan.t3_elems, ET_F32, rf, rf + R_ext, ET_F32, yre,
+           yim, ET_F64);
+}
+
+void HeffOp::autotune(const double*, const double*, double*, double*) {}
+
+}  // namespace tnt

@@ -1,0 +1,114 @@
+// Task-list plans for the grouped kernels and their device copies.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "layout.h"
+
+namespace tnt {
+
+// Host task list of one grouped-GEMM launch.
+struct HostGemm {
+  std::vector<GemmTask> tasks;
+  std::vector<GemmSeg> segs;
+  std::vector<int2> tiles;  // built by finalize
+  int tile_cfg = 0;
+  double flops = 0;         // 8 * sum M N K (complex MACs)
+
+  int add_task(int64_t c_off, int M, int N, int ldc) {
+    tasks.push_back(GemmTask{c_off, M, N, ldc, (int)segs.size(), 0, 0});
+    return (int)tasks.size() - 1;
+  }
+  void add_seg(int64_t a_off, int lda, int64_t b_off, int ldb, int K) {
+    segs.push_back(GemmSeg{a_off, b_off, K, lda, ldb, 0});
+    GemmTask& t = tasks.back();
+    t.nseg++;
+    flops += 8.0 * t.M * (double)t.N * K;
+  }
+  // Build the tile table for a tile shape: tasks are spread over the 8 XCD
+  // bins by greedy cost balancing (largest first); block b of the launch
+  // runs on XCD b % 8 and takes slot b / 8 of that bin (empty slots exit).
+  void finalize(int cfg);
+};
+
+// Host task list of one combine launch.
+struct HostComb {
+  std::vector<CombTask> tasks;
+  std::vector<CombTerm> terms;
+  std::vector<int2> chunks;
+  double flops = 0;  // 4 per term per element
+
+  void add_task(int64_t dst_off, int size) {
+    tasks.push_back(CombTask{dst_off, size, (int)terms.size(), 0, 0});
+  }
+  void add_term(int64_t src_off, double coef) {
+    terms.push_back(CombTerm{src_off, coef});
+    tasks.back().nterm++;
+    flops += 4.0 * tasks.back().size;
+  }
+  void finalize();
+};
+
+// Device copy of several host task lists in one allocation.
+struct DevTables {
+  DevBuf buf;
+  std::vector<char> host;  // kept alive until the tables are dropped
+  struct G { const GemmTask* tasks; const GemmSeg* segs; const int2* tiles; int ntiles; int cfg; };
+  struct C { const CombTask* tasks; const CombTerm* terms; const int2* chunks; int nchunks; };
+  std::vector<G> g;
+  std::vector<C> c;
+  void upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
+              const std::vector<const HostComb*>& cs);
+};
+
+void run_gemm(Ctx& ctx, const DevTables::G& g, GemmForm form, GemmPath path,
+              const void* are, const void* aim, ElemType at, const void* bre, const void* bim,
+              ElemType bt, void* cre, void* cim, ElemType ct);
+void run_comb(Ctx& ctx, const DevTables::C& c, const void* sre, const void* sim, void* dre,
+              void* dim, ElemType t);
+
+// Default tile shape for a task list (used when no tuned choice exists).
+int default_tile_cfg(const HostGemm& h, GemmPath path);
+
+// ---------------------------------------------------------------------------
+// The two-site H_eff plan: step 1 (L . theta), MPO combination, step 4 (. R)
+// ---------------------------------------------------------------------------
+struct HeffPlan {
+  HostGemm step1, step4;
+  HostComb mpo;
+  int64_t t1_elems = 0, t3_elems = 0;
+  int64_t flops_step1 = 0, flops_mpo = 0, flops_step4 = 0;
+  int64_t flops() const { return flops_step1 + flops_mpo + flops_step4; }
+  std::vector<std::array<int, 3>> out_keys;
+};
+
+HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const EnvH& R,
+                         const ThetaH& th, const ThetaH& out);
+
+// A ready-to-apply H_eff operator on one bond: the plan and its device
+// tables.  Intermediate slabs and FP32 environment copies live in the
+// context's shared workspaces (Ctx::ws), sized on use.
+struct HeffOp {
+  Ctx* ctx = nullptr;
+  HeffPlan plan;
+  DevTables tab;
+  int precision = TNT_FP64;
+  const double* L_re = nullptr; const double* L_im = nullptr;
+  const double* R_re = nullptr; const double* R_im = nullptr;
+  int64_t L_ext = 0, R_ext = 0;
+
+  // plan + device tables + workspaces for these block structures
+  void build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const EnvH& R,
+             const ThetaH& th, const ThetaH& out, int prec);
+  // point at the environments' FP64 planes (and refresh the FP32 copies)
+  void bind_envs(const void* lre, const void* lim, const void* rre, const void* rim);
+  // y = H_eff x with x, y in the theta / out layouts given at build (FP64 planes)
+  void apply(const double* xre, const double* xim, double* yre, double* yim, int prec);
+  // re-select tile shapes by timing each candidate on (x -> y)
+  void autotune(const double* xre, const double* xim, double* yre, double* yim);
+};
+
+}  // namespace tnt

@@ -1,0 +1,44 @@
+// Truncated SVD of a two-site vector with U(1) sectors.
+#pragma once
+
+#include <functional>
+#include <vector>
+
+#include "layout.h"
+
+namespace tnt {
+
+// Site-tensor layout A[x, s, y]: key (q_x, s) -> block dim(q_x) x dim(q_x + s).
+struct SiteH {
+  std::map<std::pair<int, int>, BlockRef> blocks;
+  int64_t elems = 0;
+};
+// Canonical packed site layout: ascending (q, s) over every allowed block.
+SiteH make_site(const Bond& left, const Bond& right, int d);
+
+struct SvdOut {
+  Bond bond;                 // new middle bond (kept dims per sector)
+  SiteH A, B;                // packed layouts of the two factors
+  std::vector<double> lam;   // kept singular values, sectors ascending (renormalised)
+  int chi = 0;
+  double eps = 0, lambda0 = 0, norm_kept = 0;
+};
+
+// Output planes for the factors, provided once the kept bond is known.
+struct FactorPlanes {
+  double *a_re = nullptr, *a_im = nullptr, *b_re = nullptr, *b_im = nullptr;
+};
+using FactorAlloc = std::function<FactorPlanes(const SvdOut&)>;
+
+// Selection of the kept count (host); see tnt_trunc_select.
+int trunc_select(const double* lam, int n, const tnt_trunc_params& p, double* eps);
+double trunc_error(const double* lam, int n, int kind);
+
+// theta (FP64 planes in layout th) -> factors A[a, s1, c], B[c, s2, b]
+// written packed into the planes `alloc` returns (it may throw to abort
+// before anything is written).  Rows of sector m are the (s1, q_a) pairs and
+// columns the (s2, q_b) pairs present among theta's blocks with q_a + s1 = m.
+SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double* im,
+                        const tnt_trunc_params& p, int absorb, const FactorAlloc& alloc);
+
+}  // namespace tnt

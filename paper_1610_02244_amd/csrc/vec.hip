@@ -1,0 +1,364 @@
+// Bandwidth-bound kernels: sparse MPO slab combinations, precision
+// conversions, FP64 Krylov-vector algebra with deterministic two-stage
+// reductions, and the gather/scatter between U(1) blocks and the dense
+// sector matrices of the SVD.
+#include "kernels.h"
+
+namespace tnt {
+
+// ---------------------------------------------------------------------------
+// dst slab = sum_t coef_t src_t (one workgroup per COMB_CHUNK elements)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void combine_kernel(const CombTask* __restrict__ tasks,
+                                                      const CombTerm* __restrict__ terms,
+                                                      const int2* __restrict__ chunks,
+                                                      const T* __restrict__ sre,
+                                                      const T* __restrict__ sim,
+                                                      T* __restrict__ dre, T* __restrict__ dim_) {
+  const int2 c = chunks[blockIdx.x];
+  const CombTask tk = tasks[c.x];
+  const int base = c.y * COMB_CHUNK;
+#pragma unroll
+  for (int e = 0; e < COMB_CHUNK / 256; ++e) {
+    const int i = base + e * 256 + threadIdx.x;
+    if (i >= tk.size) break;
+    T ar = 0, ai = 0;
+    for (int t = 0; t < tk.nterm; ++t) {
+      const CombTerm tm = terms[tk.term0 + t];
+      const T cf = (T)tm.coef;
+      ar += cf * sre[tm.src_off + i];
+      ai += cf * sim[tm.src_off + i];
+    }
+    dre[tk.dst_off + i] = ar;
+    dim_[tk.dst_off + i] = ai;
+  }
+}
+
+void launch_combine(const CombTask* tasks, const CombTerm* terms, const int2* chunks,
+                    int32_t nchunks, const void* src_re, const void* src_im, void* dst_re,
+                    void* dst_im, ElemType t, hipStream_t s) {
+  if (nchunks <= 0) return;
+  if (t == ET_F64)
+    hipLaunchKernelGGL(combine_kernel<double>, dim3(nchunks), dim3(256), 0, s, tasks, terms,
+                       chunks, (const double*)src_re, (const double*)src_im, (double*)dst_re,
+                       (double*)dst_im);
+  else
+    hipLaunchKernelGGL(combine_kernel<float>, dim3(nchunks), dim3(256), 0, s, tasks, terms,
+                       chunks, (const float*)src_re, (const float*)src_im, (float*)dst_re,
+                       (float*)dst_im);
+}
+
+// ---------------------------------------------------------------------------
+// conversions and fills
+// ---------------------------------------------------------------------------
+template <typename S, typename D>
+__global__ void convert_kernel(const S* __restrict__ s, D* __restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = (D)s[i];
+}
+
+static int grid_for(int64_t n, int threads = 256, int cap = 4096) {
+  int64_t g = (n + threads - 1) / threads;
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+void launch_convert(const void* src, ElemType st, void* dst, ElemType dt, int64_t n,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  const int g = grid_for(n);
+  if (st == ET_F64 && dt == ET_F32)
+    hipLaunchKernelGGL((convert_kernel<double, float>), dim3(g), dim3(256), 0, s,
+                       (const double*)src, (float*)dst, n);
+  else if (st == ET_F32 && dt == ET_F64)
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(g), dim3(256), 0, s,
+                       (const float*)src, (double*)dst, n);
+  else if (st == ET_F64)
+    hipLaunchKernelGGL((convert_kernel<double, double>), dim3(g), dim3(256), 0, s,
+                       (const double*)src, (double*)dst, n);
+  else
+    hipLaunchKernelGGL((convert_kernel<float, float>), dim3(g), dim3(256), 0, s,
+                       (const float*)src, (float*)dst, n);
+}
+
+template <typename T>
+__global__ void fill_zero_kernel(T* d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = 0;
+}
+
+void launch_fill_zero(void* dst, ElemType t, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int g = grid_for(n);
+  if (t == ET_F64)
+    hipLaunchKernelGGL(fill_zero_kernel<double>, dim3(g), dim3(256), 0, s, (double*)dst, n);
+  else
+    hipLaunchKernelGGL(fill_zero_kernel<float>, dim3(g), dim3(256), 0, s, (float*)dst, n);
+}
+
+__global__ void scale_dev_kernel(double* x, int64_t n, const double* sc) {
+  const double f = *sc;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] *= f;
+}
+void launch_scale(double* x, int64_t n, const double* scale_dev, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(scale_dev_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, scale_dev);
+}
+__global__ void scale_host_kernel(double* x, int64_t n, double f) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] *= f;
+}
+void launch_scale_host(double* x, int64_t n, double scale, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(scale_host_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, scale);
+}
+
+// ---------------------------------------------------------------------------
+// Krylov vectors: [re (n) | im (n)] doubles.  Block partial sums are
+// reduced in a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum(double v, double* sh) {
+  // 256 threads: wave reduction by shuffles, then across the 4 waves
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  return r;  // valid in thread 0
+}
+
+constexpr int MAXK = 32;  // largest basis handled by one multi-axpy
+
+// partial[b * 2k + 2i + {0,1}] = sum over block b's range of conj(V_i) w.
+// Vectors are taken 8 at a time so the accumulators stay in registers.
+__global__ __launch_bounds__(RED_THREADS) void multidot_kernel(const double* __restrict__ V,
+                                                               int64_t ld, int k,
+                                                               const double* __restrict__ w,
+                                                               int64_t n,
+                                                               double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+  for (int i0 = 0; i0 < k; i0 += 8) {
+    double accr[8], acci[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) { accr[u] = 0; acci[u] = 0; }
+    for (int64_t x = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; x < n; x += stride) {
+      const double wr = w[x], wi = w[n + x];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (i0 + u < k) {
+          const double vr = V[(i0 + u) * ld + x], vi = V[(i0 + u) * ld + n + x];
+          accr[u] += vr * wr + vi * wi;
+          acci[u] += vr * wi - vi * wr;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (i0 + u < k) {
+        const double r = block_sum(accr[u], sh);
+        const double m = block_sum(acci[u], sh);
+        if (threadIdx.x == 0) {
+          partial[blockIdx.x * 2 * k + 2 * (i0 + u)] = r;
+          partial[blockIdx.x * 2 * k + 2 * (i0 + u) + 1] = m;
+        }
+      }
+    }
+  }
+}
+
+void launch_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n,
+                     double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(multidot_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, w,
+                     n, partial);
+}
+
+// out[j] = sum_b partial[b * k2 + j], j < k2, summed in block order
+__global__ void reduce_partials_kernel(const double* __restrict__ partial, int k2, int nblk,
+                                       double* __restrict__ out) {
+  const int j = blockIdx.x;
+  __shared__ double sh[4];
+  double v = 0;
+  // fixed assignment of blocks to threads, then a fixed tree
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[b * k2 + j];
+  const double r = block_sum(v, sh);
+  if (threadIdx.x == 0) out[j] = r;
+}
+
+void launch_reduce_partials(const double* partial, int k2, int nblk, double* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(k2), dim3(256), 0, s, partial, k2, nblk, out);
+}
+
+// w -= sum_i c_i V_i ; then |w|^2 partials
+__global__ __launch_bounds__(RED_THREADS) void multiaxpy_norm_kernel(
+    const double* __restrict__ V, int64_t ld, int k, const double* __restrict__ c,
+    double* __restrict__ w, int64_t n, double* __restrict__ nrm_partial) {
+  __shared__ double sh[4];
+  __shared__ double cs[2 * MAXK];
+  if (threadIdx.x < 2 * k) cs[threadIdx.x] = c[threadIdx.x];
+  __syncthreads();
+  double acc = 0;
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+  for (int64_t x = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; x < n; x += stride) {
+    double wr = w[x], wi = w[n + x];
+    for (int i = 0; i < k; ++i) {
+      const double vr = V[i * ld + x], vi = V[i * ld + n + x];
+      const double cr = cs[2 * i], ci = cs[2 * i + 1];
+      wr -= cr * vr - ci * vi;
+      wi -= cr * vi + ci * vr;
+    }
+    w[x] = wr;
+    w[n + x] = wi;
+    acc += wr * wr + wi * wi;
+  }
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0 && nrm_partial) nrm_partial[blockIdx.x] = r;
+}
+
+void launch_multiaxpy_norm(const double* V, int64_t ld, int k, const double* c, double* w,
+                           int64_t n, double* nrm_partial, hipStream_t s) {
+  hipLaunchKernelGGL(multiaxpy_norm_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k,
+                     c, w, n, nrm_partial);
+}
+
+// w -= a v1 + b v0 (a, b real, read from device)
+__global__ __launch_bounds__(RED_THREADS) void axpy2_kernel(const double* __restrict__ v1,
+                                                            const double* __restrict__ a_dev,
+                                                            const double* __restrict__ v0,
+                                                            const double* __restrict__ b_dev,
+                                                            double* __restrict__ w, int64_t n2) {
+  const double a = *a_dev;
+  const double b = v0 ? *b_dev : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+  for (int64_t x = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; x < n2; x += stride) {
+    double v = w[x] - a * v1[x];
+    if (v0) v -= b * v0[x];
+    w[x] = v;
+  }
+}
+
+void launch_axpy2(const double* v1, const double* a_dev, const double* v0,
+                       const double* b_dev, double* w, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(axpy2_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, v1, a_dev, v0,
+                     b_dev, w, 2 * n);
+}
+
+__global__ void normalize_copy_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                      int64_t n2, const double* __restrict__ nrm2) {
+  const double f = 1.0 / sqrt(*nrm2);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i] * f;
+}
+
+void launch_normalize_copy(const double* src, double* dst, int64_t n, const double* nrm2_dev,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(normalize_copy_kernel, dim3(grid_for(2 * n)), dim3(256), 0, s, src, dst,
+                     2 * n, nrm2_dev);
+}
+
+__global__ void combine_basis_kernel(const double* __restrict__ V, int64_t ld, int k,
+                                     const double* __restrict__ y, double* __restrict__ out,
+                                     int64_t n2) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n2;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0;
+    for (int i = 0; i < k; ++i) acc += y[i] * V[i * ld + x];
+    out[x] = acc;
+  }
+}
+
+void launch_combine_basis(const double* V, int64_t ld, int k, const double* y_dev, double* out,
+                          int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(combine_basis_kernel, dim3(grid_for(2 * n)), dim3(256), 0, s, V, ld, k,
+                     y_dev, out, 2 * n);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void norm2_partial_kernel(const double* __restrict__ x,
+                                                                    int64_t n2,
+                                                                    double* __restrict__ part) {
+  __shared__ double sh[4];
+  double acc = 0;
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n2; i += stride)
+    acc += x[i] * x[i];
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+void launch_norm2_partial(const double* x, int64_t n2, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(norm2_partial_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, n2,
+                     partial);
+}
+
+__global__ void check_finite_kernel(const double* __restrict__ x, int64_t n, int* flag) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) bad = true;
+  if (bad) flag[0] = 1;  // benign race: every writer stores the same value
+}
+
+void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(check_finite_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, flag);
+}
+
+// ---------------------------------------------------------------------------
+// SVD staging: planes (row-major blocks) <-> interleaved column-major matrices
+// ---------------------------------------------------------------------------
+__global__ void gather_cm_kernel(const GatherTask* __restrict__ tasks,
+                                 const double* __restrict__ re, const double* __restrict__ im,
+                                 double* __restrict__ z) {
+  const GatherTask t = tasks[blockIdx.z];
+  // thread grid over (row, col) of the block; rows fastest for the column-major write
+  for (int c = blockIdx.y; c < t.cols; c += gridDim.y)
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < t.rows;
+         r += gridDim.x * blockDim.x) {
+      const int64_t src = t.src_off + (int64_t)r * t.cols + c;
+      const int64_t dst = t.dst_off + (int64_t)c * t.ld + r;
+      z[2 * dst] = re[src];
+      z[2 * dst + 1] = im[src];
+    }
+}
+
+void launch_gather_cm(const GatherTask* t, int ntask, int maxrows, int maxcols,
+                      const double* re, const double* im, double* dst_z, hipStream_t s) {
+  if (ntask <= 0) return;
+  dim3 grid((maxrows + 63) / 64, maxcols < 256 ? maxcols : 256, ntask);
+  hipLaunchKernelGGL(gather_cm_kernel, grid, dim3(64), 0, s, t, re, im, dst_z);
+}
+
+__global__ void scatter_cm_kernel(const ScatterTask* __restrict__ tasks,
+                                  const double* __restrict__ z, const double* __restrict__ scale,
+                                  double* __restrict__ re, double* __restrict__ im) {
+  const ScatterTask t = tasks[blockIdx.z];
+  for (int r = blockIdx.y; r < t.rows; r += gridDim.y)
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < t.cols;
+         c += gridDim.x * blockDim.x) {
+      const int64_t src = t.src_off + (int64_t)c * t.ld + r;
+      double f = 1.0;
+      if (t.scale_off >= 0) f = scale[t.scale_off + (t.scale_on_rows ? r : c)];
+      const int64_t dst = t.dst_off + (int64_t)r * t.cols + c;
+      re[dst] = z[2 * src] * f;
+      im[dst] = z[2 * src + 1] * f;
+    }
+}
+
+void launch_scatter_cm(const ScatterTask* t, int ntask, int maxrows, int maxcols,
+                       const double* src_z, const double* scale, double* re, double* im,
+                       hipStream_t s) {
+  if (ntask <= 0) return;
+  dim3 grid((maxcols + 63) / 64, maxrows < 256 ? maxrows : 256, ntask);
+  hipLaunchKernelGGL(scatter_cm_kernel, grid, dim3(64), 0, s, t, src_z, scale, re, im);
+}
+
+}  // namespace tnt

@@ -57,8 +57,23 @@ def count_configs(nsites: int, q: int, nmax: int, cap: int | None = None) -> int
     return ways[q] if cap is None else min(ways[q], cap)
 
 
+def config_table(nsites_max: int, qmax: int, nmax: int, cap: int):
+    """table[n][q] = min(count_configs(n, q, nmax), cap) for n <= nsites_max, q <= qmax."""
+    table = [[1] + [0] * qmax]
+    for _ in range(nsites_max):
+        prev = table[-1]
+        row = [0] * (qmax + 1)
+        for tot in range(qmax + 1):
+            acc = 0
+            for n in range(0, min(nmax, tot) + 1):
+                acc += prev[tot - n]
+            row[tot] = min(acc, cap)
+        table.append(row)
+    return table
+
+
 def bond_sectors(L: int, N: int, nmax: int, ell: int, chi: int,
-                 sigma: float = SIGMA) -> dict[int, int]:
+                 sigma: float = SIGMA, table=None) -> dict[int, int]:
     """Sector dimensions {q: dim} of bond `ell` (0..L) of an L-site chain.
 
     Recipe: allowed charges are those reachable from both ends; each gets a
@@ -76,9 +91,10 @@ def bond_sectors(L: int, N: int, nmax: int, ell: int, chi: int,
     qlo = max(0, N - (L - ell) * nmax)
     qhi = min(N, ell * nmax)
     caps = {}
+    if table is None:
+        table = config_table(L, N, nmax, chi + 1)
     for q in range(qlo, qhi + 1):
-        c = min(count_configs(ell, q, nmax, cap=chi + 1),
-                count_configs(L - ell, N - q, nmax, cap=chi + 1))
+        c = min(table[ell][q], table[L - ell][N - q])
         if c > 0:
             caps[q] = c
     if sum(caps.values()) <= chi:
@@ -118,7 +134,8 @@ def chain_bonds(L: int, N: int, nmax: int, chi: int) -> list[dict[int, int]]:
     blocks; such sectors are dropped, sweeping left to right then right to
     left, so every block of every site tensor is connected.
     """
-    bonds = [bond_sectors(L, N, nmax, ell, chi) for ell in range(L + 1)]
+    table = config_table(L, N, nmax, chi + 1)
+    bonds = [bond_sectors(L, N, nmax, ell, chi, table=table) for ell in range(L + 1)]
     changed = True
     while changed:
         changed = False

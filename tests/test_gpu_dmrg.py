@@ -1,0 +1,98 @@
+"""GPU two-site sweeps against the oracle's reference sweeps.
+
+The GPU path gets the seeded random MPS (synth) and does everything else on
+the device: right-canonicalisation, environments, theta formation, Lanczos,
+truncated SVD and environment updates.  The oracle's per-bond energies for
+the same inputs are stored in tests/golden/sweep_*.json (written by
+tests/golden/make_golden.py, oracle only).  Bars: FP64 |dE/E| <= 1e-10 per
+bond; FP32-MFMA matvecs |dE/E| <= 1e-9 at the end of the last sweep.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import model
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(case):
+    with open(os.path.join(GOLD, f"sweep_{case}.json")) as f:
+        return json.load(f)
+
+
+def gpu_sweeps(tnt, g, precision, sweeps=None):
+    from paper_1610_02244_amd import binding as B
+    s = synth.CONFIGS[g["config"]]
+    W, qw = model.bh_mpo(g["nmax"], g["J"], g["U"], g["mu"])
+    bonds, sites = synth.random_mps(g["L"], g["N"], g["nmax"], g["chi"], g["seed"])
+    mps = tnt.mps(bonds, sites, g["nmax"] + 1)
+    mps.right_canonicalize()
+    env = B.Env(tnt, mps, [W] * g["L"], qw, model.MPO_LEFT, model.MPO_RIGHT)
+    out = []
+    for _ in range(sweeps or len(g["sweeps"])):
+        out.append(tnt.sweep(mps, env, g["chi"], kmax=g["lanczos_steps"], precision=precision,
+                             rel_tol=g["rel_cutoff"]))
+    return out, mps, (W, qw, s)
+
+
+@pytest.mark.parametrize("case", ["cfg1", "cfg1_exact"])
+def test_sweep_fp64_matches_oracle(tnt, case):
+    g = golden(case)
+    print(f"[sweep fp64] {case}", flush=True)
+    res, mps, _ = gpu_sweeps(tnt, g, "fp64")
+    for k, (r, ref) in enumerate(zip(res, g["sweeps"])):
+        e = np.array(r["bond_E"])
+        er = np.array(ref["E"])
+        rel = np.max(np.abs(e - er) / np.abs(er))
+        print(f"  sweep {k + 1}: E {e[-1]:.15f} oracle {er[-1]:.15f} max|dE/E| {rel:.2e}")
+        assert rel <= 1e-10
+        assert list(r["bond_chi"]) == ref["chi"]
+
+
+def test_sweep_cfg1_exact_reaches_ed(tnt):
+    g = golden("cfg1_exact")
+    res, mps, _ = gpu_sweeps(tnt, g, "fp64")
+    e_ed = model.ed_ground_energy(g["L"], g["N"], g["nmax"], g["J"], g["U"])
+    assert res[-1]["energy"] == pytest.approx(e_ed, abs=1e-10)
+
+
+def test_sweep_fp32_cfg1(tnt):
+    g = golden("cfg1")
+    res, mps, _ = gpu_sweeps(tnt, g, "fp32")
+    e = res[-1]["bond_E"][-1]
+    er = g["sweeps"][-1]["E"][-1]
+    rel = abs(e - er) / abs(er)
+    print(f"  [sweep fp32 cfg1] |dE/E| = {rel:.2e}")
+    assert rel <= 1e-9
+
+
+def test_canonical_state_norm_and_density(tnt):
+    """After a sweep the returned MPS is normalised and holds N bosons."""
+    from oracle import dmrg as odmrg
+    g = golden("cfg1")
+    res, mps, (W, qw, s) = gpu_sweeps(tnt, g, "fp64", sweeps=1)
+    bonds, sites = mps.bonds(), mps.sites()
+    d = g["nmax"] + 1
+    assert odmrg.norm2(bonds, sites, d) == pytest.approx(1.0, abs=1e-12)
+    dens = odmrg.site_densities(bonds, sites, d)
+    assert sum(dens) == pytest.approx(g["N"], abs=1e-10)
+    assert odmrg.expectation(bonds, sites, [W] * g["L"], qw, d) == pytest.approx(
+        res[-1]["energy"], abs=1e-10)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sweep_cfg2(tnt, precision):
+    g = golden("cfg2")
+    print(f"[sweep cfg2 {precision}]", flush=True)
+    res, mps, _ = gpu_sweeps(tnt, g, precision)
+    e = np.array(res[-1]["bond_E"])
+    er = np.array(g["sweeps"][-1]["E"])
+    rel_last = abs(e[-1] - er[-1]) / abs(er[-1])
+    print(f"  E {e[-1]:.15f} oracle {er[-1]:.15f} |dE/E| {rel_last:.2e} "
+          f"sweep {res[-1]['seconds_total']:.2f}s")
+    assert rel_last <= (1e-10 if precision == "fp64" else 1e-9)

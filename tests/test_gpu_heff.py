@@ -1,0 +1,119 @@
+"""GPU parity of tnt_heff2_apply against the oracle's block H_eff . theta.
+
+Inputs are seeded synthetic blocks (synth); the oracle and the HIP library
+each compute H_eff . theta on the same arrays.  Bars (normwise relative
+error over all blocks): FP64 <= 1e-12; FP32-MFMA <= 2e-6 (FP32 rounding of
+operands and sums over K <= ~4 * 300 terms).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import heff as oheff
+from oracle import model
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_err(a: dict, b: dict) -> float:
+    num = sum(float(np.sum(np.abs(a[k] - b[k]) ** 2)) for k in b)
+    den = sum(float(np.sum(np.abs(b[k]) ** 2)) for k in b)
+    return (num / den) ** 0.5
+
+
+def make_case(left, right, nmax, seed, U=3.0, J=1.0, mu=0.0, herm=True):
+    d = nmax + 1
+    W, qw = model.bh_mpo(nmax, J, U, mu)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pairs = model.MPO_ADJOINT if herm else None
+    Le = synth.random_env(left, qw, rng, pairs)
+    Re = synth.random_env(right, qw, rng, pairs)
+    th = synth.random_theta(left, right, d, rng)
+    return W, qw, Le, Re, th
+
+
+def bonds_of(cfg):
+    s = synth.CONFIGS[cfg]
+    b = synth.chain_bonds(s.L, s.N, s.nmax, s.chi)
+    j = s.L // 2
+    return b[j - 1], b[j + 1], s.nmax
+
+
+CASES = {
+    "tiny": ({0: 1}, {0: 1, 1: 2, 2: 1}, 1),
+    "cfg1_mid": bonds_of("cfg1"),
+    "ragged": ({10: 37, 11: 130, 12: 65, 13: 3}, {12: 9, 13: 70, 14: 129, 15: 64, 16: 1}, 2),
+    "cfg2_mid": bonds_of("cfg2"),
+}
+
+
+def run_gpu(tnt, W, qw, Le, Re, th, precision):
+    from paper_1610_02244_amd import binding as B
+    mpo = B.Mpo(W, qw)
+    Ld, Rd, td = tnt.env(Le, qw), tnt.env(Re, qw), tnt.theta(th)
+    out = tnt.theta_like(td)
+    tnt.heff2_apply(Ld, mpo, mpo, Rd, td, out, precision)
+    return tnt.download(out)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_heff_fp64_parity(tnt, name):
+    left, right, nmax = CASES[name]
+    print(f"[heff fp64] case={name} left={left} right={right}", flush=True)
+    W, qw, Le, Re, th = make_case(left, right, nmax, seed=17)
+    ref = oheff.heff2_block(Le, W, W, Re, th, left, right, qw, nmax + 1)
+    got = run_gpu(tnt, W, qw, Le, Re, th, "fp64")
+    assert set(got) == set(ref)
+    err = rel_err(got, ref)
+    print(f"  rel err fp64 = {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_heff_fp32_parity(tnt, name):
+    left, right, nmax = CASES[name]
+    print(f"[heff fp32] case={name}", flush=True)
+    W, qw, Le, Re, th = make_case(left, right, nmax, seed=23)
+    ref = oheff.heff2_block(Le, W, W, Re, th, left, right, qw, nmax + 1)
+    got = run_gpu(tnt, W, qw, Le, Re, th, "fp32")
+    err = rel_err(got, ref)
+    print(f"  rel err fp32 = {err:.3e}")
+    assert err <= 2e-6
+
+
+def test_heff_fp64_deterministic(tnt):
+    left, right, nmax = CASES["cfg2_mid"]
+    W, qw, Le, Re, th = make_case(left, right, nmax, seed=5)
+    a = run_gpu(tnt, W, qw, Le, Re, th, "fp64")
+    b = run_gpu(tnt, W, qw, Le, Re, th, "fp64")
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+
+
+def test_heff_full_size_sampled(tnt):
+    """chi = 1024 middle bond: compare the output blocks of two sectors exactly."""
+    left, right, nmax = bonds_of("cfg3")
+    print(f"[heff full size] left={left}", flush=True)
+    W, qw, Le, Re, th = make_case(left, right, nmax, seed=31)
+    qs = sorted(left)
+    pick = {qs[0], qs[len(qs) // 2]}
+    ref = oheff.heff2_block(Le, W, W, Re, th, left, right, qw, nmax + 1, out_sectors=pick)
+    for prec, bar in (("fp64", 1e-12), ("fp32", 2e-6)):
+        got = run_gpu(tnt, W, qw, Le, Re, th, prec)
+        sel = {k: ref[k] for k in ref if k[0] in pick}
+        err = rel_err(got, sel)
+        print(f"  {prec}: sampled rel err = {err:.3e} over {len(sel)} blocks")
+        assert err <= bar
+
+
+def test_heff_rejects_charge_violation(tnt):
+    from paper_1610_02244_amd import binding as B
+    left, right, nmax = CASES["tiny"]
+    W, qw, Le, Re, th = make_case(left, right, nmax, seed=1)
+    mpo = B.Mpo(W, qw)
+    Ld, Rd, td = tnt.env(Le, qw), tnt.env(Re, qw), tnt.theta(th)
+    td.qn[3] += 1
+    out = tnt.theta_like(tnt.theta(th))
+    with pytest.raises(B.TntError) as ei:
+        tnt.heff2_apply(Ld, mpo, mpo, Rd, td, out, "fp64")
+    assert ei.value.code == -3

@@ -1,0 +1,111 @@
+"""GPU parity of tnt_lanczos_ground and tnt_theta_svd_truncate with the oracle.
+
+Lanczos: same start vector and Hermitian operator on both sides; the FP64
+path must reproduce the oracle's refined energy to 1e-11 (relative) and its
+ground vector up to a phase; the FP32 path's energy is checked against the
+same reference (the matvec error enters the final Rayleigh quotient only
+through the Krylov vectors).
+SVD: kept singular values (rtol 1e-12), kept dims per sector, chi, epsilon,
+and the gauge-invariant product A.B, for both absorb directions and several
+truncation rules.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import blocks, heff as oheff, lanczos as olanczos, model, svd as osvd
+
+pytestmark = pytest.mark.gpu
+
+
+def herm_case(left, right, nmax, seed, U=3.0):
+    d = nmax + 1
+    W, qw = model.bh_mpo(nmax, 1.0, U, 0.0)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Le = synth.random_env(left, qw, rng, model.MPO_ADJOINT)
+    Re = synth.random_env(right, qw, rng, model.MPO_ADJOINT)
+    th = synth.random_theta(left, right, d, rng)
+    return W, qw, Le, Re, th
+
+
+def oracle_lanczos(W, qw, Le, Re, th, left, right, d, kmax):
+    keys = sorted(th)
+
+    def mv(x):
+        y = oheff.heff2_block(Le, W, W, Re, blocks.unflatten(x, th, keys), left, right, qw, d)
+        return blocks.flatten(y, keys)
+
+    return olanczos.lanczos_ground(mv, blocks.flatten(th, keys), kmax=kmax), keys
+
+
+LCASES = {
+    "small": ({2: 2, 3: 3}, {4: 2, 5: 3, 6: 1}, 2),
+    "cfg2_like": ({13: 7, 14: 26, 15: 57, 16: 40}, {15: 20, 16: 57, 17: 75, 18: 26}, 4),
+}
+
+
+@pytest.mark.parametrize("name", list(LCASES))
+def test_lanczos_fp64_parity(tnt, name):
+    from paper_1610_02244_amd import binding as B
+    left, right, nmax = LCASES[name]
+    print(f"[lanczos fp64] {name}", flush=True)
+    W, qw, Le, Re, th = herm_case(left, right, nmax, seed=3)
+    ref, keys = oracle_lanczos(W, qw, Le, Re, th, left, right, nmax + 1, 20)
+    mpo = B.Mpo(W, qw)
+    td = tnt.theta(th, keys)
+    res = tnt.lanczos_ground(tnt.env(Le, qw), mpo, mpo, tnt.env(Re, qw), td, kmax=20)
+    print(f"  E gpu {res['E']:.15f} oracle {ref['E']:.15f} steps {res['steps']}/{ref['steps']}")
+    assert res["steps"] == ref["steps"]
+    assert abs(res["E"] - ref["E"]) <= 1e-11 * abs(ref["E"])
+    assert abs(res["E_ritz"] - ref["E_ritz"]) <= 1e-11 * abs(ref["E"])
+    assert res["residual"] == pytest.approx(ref["residual"], rel=1e-6, abs=1e-12)
+    psi = blocks.flatten(tnt.download(td), keys)
+    ov = abs(np.vdot(psi, ref["psi"]))
+    assert ov == pytest.approx(1.0, abs=1e-11)
+
+
+@pytest.mark.parametrize("name", list(LCASES))
+def test_lanczos_fp32_energy(tnt, name):
+    from paper_1610_02244_amd import binding as B
+    left, right, nmax = LCASES[name]
+    W, qw, Le, Re, th = herm_case(left, right, nmax, seed=4)
+    ref, keys = oracle_lanczos(W, qw, Le, Re, th, left, right, nmax + 1, 20)
+    mpo = B.Mpo(W, qw)
+    td = tnt.theta(th, keys)
+    res = tnt.lanczos_ground(tnt.env(Le, qw), mpo, mpo, tnt.env(Re, qw), td, kmax=20,
+                             precision="fp32")
+    rel = abs(res["E"] - ref["E"]) / abs(ref["E"])
+    print(f"  [lanczos fp32] {name}: |dE/E| = {rel:.3e}")
+    assert rel <= 1e-5
+
+
+SCASE_L = {10: 6, 11: 17, 12: 9, 13: 2}
+SCASE_R = {12: 4, 13: 11, 14: 15, 15: 8, 16: 1}
+
+
+@pytest.mark.parametrize("absorb", ["right", "left"])
+@pytest.mark.parametrize("rules", [dict(chi_max=12), dict(chi_max=1000),
+                                   dict(chi_max=40, rel_tol=0.05),
+                                   dict(chi_max=1000, err_tol=0.3),
+                                   dict(chi_max=1000, abs_tol=0.4)])
+def test_svd_truncate_parity(tnt, absorb, rules):
+    d = 3
+    rng = np.random.Generator(np.random.PCG64(9))
+    th = synth.random_theta(SCASE_L, SCASE_R, d, rng)
+    ref = osvd.svd_truncate(th, SCASE_L, SCASE_R, d, rules["chi_max"],
+                            a=rules.get("abs_tol", -1.0), r=rules.get("rel_tol", -1.0),
+                            e=rules.get("err_tol", -1.0), absorb=absorb)
+    got = tnt.svd_truncate(tnt.theta(th), absorb=absorb, **rules)
+    assert got["chi"] == ref["chi"]
+    assert got["bond"] == ref["bond"]
+    assert got["eps"] == pytest.approx(ref["eps"], rel=1e-10, abs=1e-14)
+    for m in ref["bond"]:
+        np.testing.assert_allclose(got["lambdas"][m], ref["lambdas"][m], rtol=1e-12)
+    # the product A.B is gauge invariant
+    for (qa, s1, s2) in blocks.theta_keys(SCASE_L, SCASE_R, d):
+        mid = qa + s1
+        if mid not in ref["bond"]:
+            continue
+        g = got["A"][(qa, s1)] @ got["B"][(mid, s2)]
+        r = ref["A"][(qa, s1)] @ ref["B"][(mid, s2)]
+        np.testing.assert_allclose(g, r, atol=1e-12)
