@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the two-site DMRG hot path on one MI355X.
+
+One step = one full two-site sweep (right pass + left pass over every bond:
+theta formation, Lanczos with H_eff matvecs, truncated SVD, environment
+update) of a Bose-Hubbard chain, on device-resident state.  The headline
+`value` is the H_eff matvec throughput of the whole timed sweeps:
+algorithmic flops of every matvec the sweeps performed / timed wall time.
+
+Default workload: L = 32, N = 32, nmax = 4 (d = 5), J = 1, U = 4, chi = 256
+(seeded random MPS), matvecs on FP32 MFMA; Krylov vectors, SVD, energies and
+environments in FP64.  Also reported: the same sweeps on the FP64 GPU path,
+single-matvec rates at the middle bond, the energy error against the
+oracle's stored sweep energies, the grouped-GEMM roofline figure and the
+CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "2-site H_eff matvec TFLOP/s + sweep time: FP32-MFMA vs FP64, |ΔE/E|<=1e-9"
+PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_chain(tnt, B, spec):
+    import synth
+    W, qw = tnt.bose_hubbard_mpo(spec.nmax, spec.J, spec.U, spec.mu)
+    bonds, sites = synth.random_mps(spec.L, spec.N, spec.nmax, spec.chi, spec.seed)
+    mps = tnt.mps(bonds, sites, spec.d)
+    mps.right_canonicalize()
+    env = B.Env(tnt, mps, [W] * spec.L, qw, B.MPO_LEFT, B.MPO_RIGHT)
+    return mps, env
+
+
+def run_sweeps(tnt, torch, mps, env, spec, precision, warmup, steps):
+    kw = dict(kmax=spec.lanczos_steps, precision=precision, rel_tol=spec.rel_cutoff)
+    for i in range(warmup):
+        r = tnt.sweep(mps, env, spec.chi, **kw)
+        log(f"  warmup sweep {i + 1} [{precision}]: E = {r['energy']:.12f} ({r['seconds_total']:.2f}s)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [tnt.sweep(mps, env, spec.chi, **kw) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for i, r in enumerate(res):
+        log(f"  timed sweep {i + 1} [{precision}]: E = {r['energy']:.12f} ({r['seconds_total']:.2f}s)")
+    return res, dt
+
+
+def matvec_rates(tnt, B, torch, spec, reps=20):
+    """Single H_eff applications at the middle bond (seeded synthetic L, R, theta)."""
+    import synth
+    W, qw = tnt.bose_hubbard_mpo(spec.nmax, spec.J, spec.U, spec.mu)
+    left, right, Le, Re, th = synth.middle_bond_inputs(spec, qw)
+    mpo = B.Mpo(W, qw)
+    Ld, Rd, td = tnt.env(Le, qw), tnt.env(Re, qw), tnt.theta(th)
+    out = tnt.theta_like(td)
+    flops, parts = tnt.heff2_flops(Ld, mpo, mpo, Rd, td)
+    rates = {}
+    for prec in ("fp64", "fp32"):
+        for _ in range(3):
+            tnt.heff2_apply(Ld, mpo, mpo, Rd, td, out, prec)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            tnt.heff2_apply(Ld, mpo, mpo, Rd, td, out, prec)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        ts.sort()
+        med = ts[len(ts) // 2]
+        rates[prec] = {"median_s": med, "tflops": flops / med / 1e12}
+    return {"flops": int(flops), "parts": [int(x) for x in parts], **rates}
+
+
+def cpu_baseline(spec, budget_s=12.0):
+    """The oracle's block H_eff at the middle bond, repeated for ~budget_s seconds."""
+    import numpy as np
+    import synth
+    from oracle import flops as oflops
+    from oracle import heff as oheff
+    from oracle import model
+    W, qw = model.bh_mpo(spec.nmax, spec.J, spec.U, spec.mu)
+    left, right, Le, Re, th = synth.middle_bond_inputs(spec, qw)
+    f = oflops.heff2_flops(left, right, spec.d, qw, W, W)["total"]
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    n, t0 = 0, time.perf_counter()
+    while True:
+        oheff.heff2_block(Le, W, W, Re, th, left, right, qw, spec.d)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    _ = np
+    return {"value": f * n / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} block H_eff matvecs (oracle, complex128 NumPy) at the middle bond of "
+                      f"the same chain shape, {dt:.1f}s"}
+
+
+def traffic_for(precision):
+    """HBM bytes per grouped-GEMM launch from the committed PMC summary, if the
+    kernel source is unchanged since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "gemm_traffic.json")
+    src = os.path.join(ROOT, "paper_1610_02244_amd", "csrc", "gemm.hip")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+        if t.get("gemm_hip_sha256") != h:
+            return None
+        return t.get(precision, {}).get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def golden_energy(config, total_sweeps):
+    names = {("cfg1", 2): "cfg1", ("cfg2", 1): "cfg2", ("cfg2", 2): "cfg2_2sweeps"}
+    case = names.get((config, total_sweeps))
+    if case is None:
+        return None
+    p = os.path.join(ROOT, "tests", "golden", f"sweep_{case}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        return json.load(f)["sweeps"][-1]["E"][-1]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path sweeps")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the path runs on a single MI355X and has no "
+              "multi-GPU mode (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1610_02244_amd import binding as B
+
+    spec = synth.CONFIGS[args.config]
+    tnt = B.load()
+    log(f"[bench] {args.config}: L={spec.L} N={spec.N} d={spec.d} chi={spec.chi} U={spec.U} "
+        f"precision={args.precision} warmup={args.warmup} steps={args.steps}")
+
+    mps, env = make_chain(tnt, B, spec)
+    res, dt = run_sweeps(tnt, torch, mps, env, spec, args.precision, args.warmup, args.steps)
+    flops = sum(r["matvec_flops"] for r in res)
+    value = flops / dt / 1e12
+    gemm_flops = sum(r["gemm_flops"] for r in res)
+    gemm_s = sum(r["seconds_gemm"] for r in res)
+    launches = sum(r["gemm_launches"] for r in res)
+    achieved = gemm_flops / gemm_s / 1e12 if gemm_s > 0 else 0.0
+    e_final = res[-1]["energy"]
+    e_ref = golden_energy(args.config, args.warmup + args.steps)
+
+    fp64 = None
+    if not args.no_fp64 and args.precision != "fp64":
+        del env, mps
+        mps64, env64 = make_chain(tnt, B, spec)
+        r64, dt64 = run_sweeps(tnt, torch, mps64, env64, spec, "fp64", args.warmup, args.steps)
+        f64 = sum(r["matvec_flops"] for r in r64)
+        fp64 = {"sweep_s": dt64 / args.steps, "matvec_tflops": f64 / dt64 / 1e12,
+                "matvec_device_s": sum(r["seconds_matvec"] for r in r64) / args.steps,
+                "energy": r64[-1]["energy"],
+                "rel_dE_vs_fp32_path": abs(r64[-1]["energy"] - e_final) / abs(r64[-1]["energy"]),
+                "speedup_fp32_over_fp64_sweep": (dt64 / dt)}
+        del env64, mps64
+
+    mv = matvec_rates(tnt, B, torch, spec)
+    peak = PEAK[args.precision]
+    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": traffic_for(args.precision),
+            "kernel": f"grouped_gemm_kernel ({args.precision}, H_eff steps 1 and 4)",
+            "launches": int(launches),
+            "avg_launch_s": gemm_s / launches if launches else None,
+            "avg_flops_per_launch": gemm_flops / launches if launches else None}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(spec)
+    per = {k: sum(r[k] for r in res) / len(res) for k in
+           ("seconds_total", "seconds_matvec", "seconds_lanczos", "seconds_svd", "seconds_env")}
+    line = {
+        "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"{args.config}: Bose-Hubbard open chain L={spec.L}, N={spec.N}, "
+                               f"nmax={spec.nmax} (d={spec.d}), J={spec.J}, U={spec.U}, "
+                               f"chi={spec.chi}, seeded random MPS (seed {spec.seed}), "
+                               f"one two-site sweep per step, Lanczos {spec.lanczos_steps} steps",
+                   "L": spec.L, "chi": spec.chi, "d": spec.d, "precision": args.precision,
+                   "parallelism": "single GPU"},
+        "roofline": roof, "cpu_baseline": cpu,
+        "sweep_breakdown_s": per,
+        "matvec_flops_per_sweep": flops / len(res),
+        "matvec_device_tflops": flops / sum(r["seconds_matvec"] for r in res) / 1e12,
+        "energy": {"final": e_final, "oracle": e_ref,
+                   "rel_err_vs_oracle": (abs(e_final - e_ref) / abs(e_ref)) if e_ref else None,
+                   "max_residual": max(r["max_residual"] for r in res),
+                   "max_trunc_eps": max(r["max_eps"] for r in res)},
+        "fp64_path": fp64, "single_matvec_middle_bond": mv,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

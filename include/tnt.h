@@ -118,6 +118,15 @@ typedef struct {
   const double* W;            /* [D*D*d*d], index ((w*D + w')*d + s')*d + s              */
 } tnt_mpo_site;
 
+/* Bose-Hubbard MPO site (Sec. 5, Eq. 2 with V = 0; occupancy 0..nmax):
+ * H = -J sum (b_j^+ b_{j+1} + h.c.) + sum (U/2 n_j (n_j - 1) - mu n_j).
+ * Fills W (host, 16 d^2 doubles, d = nmax + 1, layout of tnt_mpo_site with
+ * D = 4) and bond_charge[4] = (0, +1, -1, 0).  The chain operator uses the
+ * left boundary index 3 and the right boundary index 0.  Host only.
+ * Errors: TNT_E_ARG (nmax outside 0..63, NULL), TNT_E_NONFINITE. */
+tnt_status tnt_mpo_bose_hubbard(int32_t nmax, double J, double U, double mu, double* W,
+                                int32_t* bond_charge);
+
 /* ------------------------------------------------------------------------
  * H_eff . theta (Sec. 4.2, the contractor, in two-site form)
  *
@@ -305,7 +314,10 @@ typedef struct {
   double seconds_matvec;  /* device time of the iteration matvecs            */
   double seconds_lanczos; /* device time of the Krylov vector work           */
   double seconds_svd;     /* wall time of the SVD-truncate steps             */
-  double seconds_env;     /* device time of environment updates              */
+  double seconds_env;     /* wall time of environment updates                */
+  double gemm_flops;      /* algorithmic flops of the iteration matvecs' grouped-GEMM launches */
+  double seconds_gemm;    /* device time of those launches (HIP events)      */
+  int64_t gemm_launches;  /* number of those launches                        */
 } tnt_sweep_result;
 
 /* One sweep: right pass over bonds 1..L-1 then left pass L-1..1 (each:

@@ -78,7 +78,9 @@ class SweepResult(C.Structure):
                 ("updates", C.c_int32), ("max_chi", C.c_int32), ("matvecs", C.c_int64),
                 ("matvec_flops", C.c_double), ("seconds_total", C.c_double),
                 ("seconds_matvec", C.c_double), ("seconds_lanczos", C.c_double),
-                ("seconds_svd", C.c_double), ("seconds_env", C.c_double)]
+                ("seconds_svd", C.c_double), ("seconds_env", C.c_double),
+                ("gemm_flops", C.c_double), ("seconds_gemm", C.c_double),
+                ("gemm_launches", C.c_int64)]
 
 
 # name -> (restype, argtypes); mirrors include/tnt.h
@@ -88,6 +90,8 @@ SIGNATURES = {
     "tnt_last_error": (C.c_char_p, [P]),
     "tnt_sync": (C.c_int32, [P]),
     "tnt_pool_bytes": (C.c_int64, [P]),
+    "tnt_mpo_bose_hubbard": (C.c_int32, [C.c_int32, C.c_double, C.c_double, C.c_double, F64P,
+                                         I32P]),
     "tnt_heff2_apply": (C.c_int32, [P, C.POINTER(BTensor), C.POINTER(MpoSite),
                                     C.POINTER(MpoSite), C.POINTER(BTensor),
                                     C.POINTER(BTensor), C.POINTER(BTensor), C.c_int32]),
@@ -140,6 +144,21 @@ def open_library(path: str = LIBPATH) -> C.CDLL:
         fn.argtypes = args
     lib.missing_symbols = missing
     return lib
+
+
+MPO_LEFT, MPO_RIGHT = 3, 0  # boundary indices of the Bose-Hubbard MPO
+
+
+def bose_hubbard_mpo(lib, nmax, J, U, mu=0.0):
+    """(W[w, w', s', s], bond charges) from the library's MPO builder."""
+    d = nmax + 1
+    W = np.zeros((4, 4, d, d))
+    qw = np.zeros(4, np.int32)
+    code = lib.tnt_mpo_bose_hubbard(int(nmax), float(J), float(U), float(mu),
+                                    W.ctypes.data_as(F64P), qw.ctypes.data_as(I32P))
+    if code != 0:
+        raise TntError("tnt_mpo_bose_hubbard", code, "invalid model parameters")
+    return W, [int(x) for x in qw]
 
 
 def _i32(a):
@@ -219,6 +238,9 @@ class Tnt:
                 msg = self.lib.tnt_last_error(c).decode()
             raise TntError(fn, code, msg)
         return code
+
+    def bose_hubbard_mpo(self, nmax, J, U, mu=0.0):
+        return bose_hubbard_mpo(self.lib, nmax, J, U, mu)
 
     # -- packing helpers ----------------------------------------------------
     def planes(self, n, dtype=None):

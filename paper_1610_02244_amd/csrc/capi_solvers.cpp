@@ -368,6 +368,9 @@ tnt_status tnt_dmrg_sweep(tnt_ctx ctx, tnt_mps mps, tnt_env env, const tnt_sweep
   r->seconds_lanczos = st.t_lanczos;
   r->seconds_svd = st.t_svd;
   r->seconds_env = st.t_env;
+  r->gemm_flops = st.gemm_flops;
+  r->seconds_gemm = st.t_gemm;
+  r->gemm_launches = st.gemm_launches;
   TNT_API_END
 }
 

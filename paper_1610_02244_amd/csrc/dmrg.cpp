@@ -373,6 +373,9 @@ void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats&
       st.t_lanczos += (tl1 - tl0) - tm.matvec_s;
       st.matvecs += lo.matvecs;
       st.matvec_flops += (double)op->plan.flops() * (double)lo.matvecs;
+      st.gemm_flops += (double)(op->plan.flops_step1 + op->plan.flops_step4) * (double)lo.matvecs;
+      st.t_gemm += tm.gemm_s;
+      st.gemm_launches += tm.gemm_launches;
       // split
       const int absorb = pass == 0 ? TNT_ABSORB_RIGHT : TNT_ABSORB_LEFT;
       DevBuf na, nb;

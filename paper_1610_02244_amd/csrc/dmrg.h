@@ -45,6 +45,8 @@ struct SweepStats {
   int updates = 0, max_chi = 0;
   int64_t matvecs = 0;
   double matvec_flops = 0;
+  double gemm_flops = 0, t_gemm = 0;
+  int64_t gemm_launches = 0;
   double t_total = 0, t_matvec = 0, t_lanczos = 0, t_svd = 0, t_env = 0;
 };
 

@@ -120,30 +120,22 @@ void launch_norm2_partial(const double* x, int64_t n2, double* partial, hipStrea
 // finite check: flag[0] set to 1 if any non-finite among n doubles
 void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s);
 
-// Gather theta blocks into dense column-major complex (interleaved) sector
-// matrices, and scatter factor columns back into site blocks.
-struct GatherTask {
-  int64_t src_off;   // element offset of the block in the planes
-  int64_t dst_off;   // complex-element offset of the block's (0,0) in the matrix
+// Scatter from an interleaved complex matrix into row-major split-plane
+// blocks: dst(r, c) = f(src[src_off + r * rs + c * cs]) for r < rows,
+// c < cols, where f conjugates when `conj` is set (strides in complex
+// elements, possibly negative).
+struct ScatterTask {
+  int64_t src_off;
+  int64_t rs, cs;
+  int64_t dst_off;   // element offset in the destination planes
   int32_t rows, cols;
-  int32_t ld;        // leading dimension (rows of the sector matrix)
+  int32_t conj;
   int32_t pad;
 };
-void launch_gather_cm(const GatherTask* t, int ntask, int maxrows, int maxcols,
-                      const double* re, const double* im, double* dst_z, hipStream_t s);
-// Scatter: dst block (rows x cols row-major planes) = scale_row/col * sub-matrix
-// of a column-major complex matrix.  mode 0: take U[r, c] * (colscale[c]);
-// mode 1: take VH[r, c] * (rowscale[r]).
-struct ScatterTask {
-  int64_t src_off;   // complex offset of the sub-matrix's (0,0) in its source
-  int64_t dst_off;   // element offset in the destination planes
-  int64_t scale_off; // offset into the scale array (or -1 for none)
-  int32_t rows, cols;
-  int32_t ld;        // leading dimension of the column-major source
-  int32_t scale_on_rows;  // 1: scale[r], 0: scale[c]
-};
-void launch_scatter_cm(const ScatterTask* t, int ntask, int maxrows, int maxcols,
-                       const double* src_z, const double* scale, double* re, double* im,
+void launch_scatter_z(const ScatterTask* t, int ntask, int maxrows, int maxcols,
+                      const double* src_z, double* re, double* im, hipStream_t s);
+// z[2k] = re[k], z[2k+1] = (conj ? -im[k] : im[k]) for k < n
+void launch_interleave(const double* re, const double* im, double* z, int64_t n, int conj,
                        hipStream_t s);
 
 }  // namespace tnt

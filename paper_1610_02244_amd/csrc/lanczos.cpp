@@ -122,7 +122,7 @@ LanczosOut lanczos_run(Ctx& c, HeffOp& op, Krylov& K, double* x, const tnt_lancz
     double* vj = V + (size_t)j * ld;
     // w = H v_j (iteration precision)
     if (tm) TNT_HIP(hipEventRecord(c.ev[0], c.stream));
-    op.apply(vj, vj + n, w, w + n, p.precision);
+    op.apply(vj, vj + n, w, w + n, p.precision, tm != nullptr);
     if (tm) TNT_HIP(hipEventRecord(c.ev[1], c.stream));
     o.matvecs++;
     // alpha_j = Re <v_j, w>
@@ -147,9 +147,13 @@ LanczosOut lanczos_run(Ctx& c, HeffOp& op, Krylov& K, double* x, const tnt_lancz
                            hipMemcpyDeviceToHost, c.stream));
     TNT_HIP(hipStreamSynchronize(c.stream));
     if (tm) {
-      float ms = 0;
+      float ms = 0, m1 = 0, m4 = 0;
       TNT_HIP(hipEventElapsedTime(&ms, c.ev[0], c.ev[1]));
+      TNT_HIP(hipEventElapsedTime(&m1, c.ev[2], c.ev[3]));
+      TNT_HIP(hipEventElapsedTime(&m4, c.ev[4], c.ev[5]));
       tm->matvec_s += ms * 1e-3;
+      tm->gemm_s += (m1 + m4) * 1e-3;
+      tm->gemm_launches += 2;
     }
     const double a = K.stage.p[0];
     const double b = std::sqrt(K.stage.p[1]);

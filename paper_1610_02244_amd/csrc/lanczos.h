@@ -20,6 +20,8 @@ struct Krylov {
 
 struct Timers {
   double matvec_s = 0;  // device time of iteration matvecs
+  double gemm_s = 0;    // device time of their grouped-GEMM launches
+  int64_t gemm_launches = 0;
 };
 
 struct LanczosOut {

@@ -255,19 +255,27 @@ void HeffOp::bind_envs(const void* lre, const void* lim, const void* rre, const 
   }
 }
 
-void HeffOp::apply(const double* xre, const double* xim, double* yre, double* yim, int prec) {
+void HeffOp::apply(const double* xre, const double* xim, double* yre, double* yim, int prec,
+                   bool timed) {
   Ctx& c = *ctx;
+  auto mark = [&](int i) {
+    if (timed) TNT_HIP(hipEventRecord(c.ev[i], c.stream));
+  };
   if (prec == TNT_FP64 || precision == TNT_FP64) {
     // FP64 (also the refinement matvec of an FP32 operator: FP64 environments)
     c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(double));
     c.ws[1].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(double));
     double* a = c.ws[0].as<double>();
     double* b = c.ws[1].as<double>();
+    mark(2);
     run_gemm(c, tab.g[0], FORM_NN, PATH_F64, L_re, L_im, ET_F64, xre, xim, ET_F64, a,
              a + plan.t1_elems, ET_F64);
+    mark(3);
     run_comb(c, tab.c[0], a, a + plan.t1_elems, b, b + plan.t3_elems, ET_F64);
+    mark(4);
     run_gemm(c, tab.g[1], FORM_NT, PATH_F64, b, b + plan.t3_elems, ET_F64, R_re, R_im, ET_F64,
              yre, yim, ET_F64);
+    mark(5);
     return;
   }
   c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(float));
@@ -277,11 +285,15 @@ void HeffOp::apply(const double* xre, const double* xim, double* yre, double* yi
   const float* lf = c.ws[2].as<float>();
   const float* rf = c.ws[3].as<float>();
   const GemmPath path = prec == TNT_BF16X3 ? PATH_BF16X3 : PATH_F32;
+  mark(2);
   run_gemm(c, tab.g[0], FORM_NN, path, lf, lf + L_ext, ET_F32, xre, xim, ET_F64, a,
            a + plan.t1_elems, ET_F32);
+  mark(3);
   run_comb(c, tab.c[0], a, a + plan.t1_elems, b, b + plan.t3_elems, ET_F32);
+  mark(4);
   run_gemm(c, tab.g[1], FORM_NT, path, b, b + plan.t3_elems, ET_F32, rf, rf + R_ext, ET_F32, yre,
            yim, ET_F64);
+  mark(5);
 }
 
 void HeffOp::autotune(const double*, const double*, double*, double*) {}

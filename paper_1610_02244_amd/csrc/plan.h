@@ -105,8 +105,11 @@ struct HeffOp {
              const ThetaH& th, const ThetaH& out, int prec);
   // point at the environments' FP64 planes (and refresh the FP32 copies)
   void bind_envs(const void* lre, const void* lim, const void* rre, const void* rim);
-  // y = H_eff x with x, y in the theta / out layouts given at build (FP64 planes)
-  void apply(const double* xre, const double* xim, double* yre, double* yim, int prec);
+  // y = H_eff x with x, y in the theta / out layouts given at build (FP64 planes).
+  // With `timed`, events ev[2]/ev[3] bracket the step-1 GEMM launch and
+  // ev[4]/ev[5] the step-4 launch.
+  void apply(const double* xre, const double* xim, double* yre, double* yim, int prec,
+             bool timed = false);
   // re-select tile shapes by timing each candidate on (x -> y)
   void autotune(const double* xre, const double* xim, double* yre, double* yim);
 };

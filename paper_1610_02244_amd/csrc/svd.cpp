@@ -1,11 +1,20 @@
 // Truncated SVD of a two-site vector (appendix B.1.2) with U(1) sectors.
 //
-// For every middle charge m = q_a + s1 the matrix with rows (s1, a) and
-// columns (s2, b) is assembled on the device (column-major, interleaved
-// complex) and decomposed in FP64 by rocSOLVER's gesvd.  The singular values
-// of all sectors are pooled on the host, sorted and cut by the four
-// truncation rules; the kept columns of U and rows of V^+ are scattered back
-// into U(1) site blocks with the singular values absorbed left or right.
+// For every middle charge m = q_a + s1, theta restricted to m is a matrix
+// X_m with rows (s1, a) and columns (s2, b).  Its singular vectors are
+// obtained from the FP64 Hermitian eigendecomposition of a Gram matrix
+// (rocSOLVER zheevd, divide and conquer), built blockwise on the grouped
+// MFMA GEMM:
+//   absorb RIGHT (A = U, B = S V^+): G = X X^+ ; A = eigenvectors (an exact
+//     isometry), B = A^+ X (an exact projection, GEMM);
+//   absorb LEFT  (A = U S, B = V^+): G = X^+ X ; B = eigenvectors^+, A = X V.
+// The isometric factor is therefore orthonormal to working precision and the
+// other factor is the exact projection of theta onto the kept space; the
+// singular values are sqrt of the Gram eigenvalues.  Eigenvalues below the
+// Gram matrix's rounding floor (n * 4 eps * largest) carry no information and
+// are set to zero.  All sectors' values are pooled on the host, sorted and
+// cut by the four truncation rules; the centre factor is renormalised to unit
+// Frobenius norm on the device.
 #include "svd.h"
 
 #include <rocblas/rocblas.h>
@@ -17,6 +26,7 @@
 #include <set>
 
 #include "kernels.h"
+#include "plan.h"
 
 namespace tnt {
 
@@ -75,19 +85,34 @@ int trunc_select(const double* lam, int n, const tnt_trunc_params& p, double* ep
   return chi;
 }
 
+SiteH make_site(const Bond& left, const Bond& right, int d) {
+  SiteH h;
+  int64_t off = 0;
+  for (auto& l : left)
+    for (int s = 0; s < d; ++s) {
+      auto it = right.find(l.first + s);
+      if (it == right.end()) continue;
+      h.blocks[{l.first, s}] = BlockRef{off, l.second, it->second};
+      off += (int64_t)l.second * it->second;
+    }
+  h.elems = off;
+  return h;
+}
+
 namespace {
 struct Sector {
   int m = 0;
-  std::vector<std::pair<int, int>> rows, cols;  // (s1, q_a), (s2, q_b)
+  std::vector<std::pair<int, int>> rows, cols;  // (s1, q_a), (s2, q_b) ascending
   std::vector<int> roff, coff;
-  int R = 0, C = 0, K = 0;
-  int64_t a_base = 0, u_base = 0, v_base = 0;  // complex offsets
-  int s_base = 0, e_base = 0;
-  int kept = 0, lam_base = 0;
+  int R = 0, C = 0;
+  int n = 0;             // Gram dimension (R for absorb right, C for absorb left)
+  int64_t gbase = 0;     // offset of the n x n Gram matrix (elements / complex elements)
+  int ebase = 0;         // offset of its eigenvalues
+  int kept = 0;
+  int64_t tbase = 0;     // offset of V_kept (C x kept) in the left-absorb temp
 };
 
-// Sectors from the blocks present: rows (s1, q_a) and columns (s2, q_b), both
-// ascending in s, for every middle charge m = q_a + s1.
+// Sectors from the blocks present: rows (s1, q_a), columns (s2, q_b).
 std::vector<Sector> sectors_of(const ThetaH& th) {
   std::map<int, std::set<std::pair<int, int>>> rows, cols;
   for (auto& kv : th.blocks) {
@@ -104,107 +129,123 @@ std::vector<Sector> sectors_of(const ThetaH& th) {
     s.cols.assign(cols[kv.first].begin(), cols[kv.first].end());
     for (auto& r : s.rows) { s.roff.push_back(s.R); s.R += th.left.at(r.second); }
     for (auto& cc : s.cols) { s.coff.push_back(s.C); s.C += th.right.at(cc.second); }
-    s.K = std::min(s.R, s.C);
     out.push_back(std::move(s));
   }
   return out;
 }
-}  // namespace
 
-SiteH make_site(const Bond& left, const Bond& right, int d) {
-  SiteH h;
-  int64_t off = 0;
-  for (auto& l : left)
-    for (int s = 0; s < d; ++s) {
-      auto it = right.find(l.first + s);
-      if (it == right.end()) continue;
-      h.blocks[{l.first, s}] = BlockRef{off, l.second, it->second};
-      off += (int64_t)l.second * it->second;
-    }
-  h.elems = off;
-  return h;
+int index_of(const std::vector<std::pair<int, int>>& v, int first) {
+  for (size_t i = 0; i < v.size(); ++i)
+    if (v[i].first == first) return (int)i;
+  return -1;
 }
+}  // namespace
 
 SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double* im,
                         const tnt_trunc_params& p, int absorb, const FactorAlloc& alloc) {
   if (p.chi_max < 1) fail(TNT_E_ARG, "chi_max must be >= 1");
   if (absorb != TNT_ABSORB_RIGHT && absorb != TNT_ABSORB_LEFT) fail(TNT_E_ARG, "bad absorb");
+  const bool right = absorb == TNT_ABSORB_RIGHT;
   std::vector<Sector> secs = sectors_of(th);
-  int64_t za = 0, zu = 0, zv = 0;
-  int ns = 0;
-  for (auto& s : secs) {
-    s.a_base = za; za += (int64_t)s.R * s.C;
-    s.u_base = zu; zu += (int64_t)s.R * s.K;
-    s.v_base = zv; zv += (int64_t)s.K * s.C;
-    s.s_base = ns; s.e_base = ns; ns += s.K;
-  }
-  SvdOut out;
   if (secs.empty()) fail(TNT_E_SHAPE, "theta has no sector to decompose");
-  // device staging: matrices, U, V^+, S, E, info
-  DevBuf mat(&c.pool, std::max<int64_t>(za, 1) * 16);
-  DevBuf ubuf(&c.pool, std::max<int64_t>(zu, 1) * 16);
-  DevBuf vbuf(&c.pool, std::max<int64_t>(zv, 1) * 16);
-  DevBuf sbuf(&c.pool, std::max(ns, 1) * sizeof(double) * 2);
-  DevBuf info(&c.pool, std::max<size_t>(secs.size(), 1) * sizeof(rocblas_int));
-  launch_fill_zero(mat.ptr, ET_F64, 2 * za, c.stream);
-  // gather theta blocks into the sector matrices
-  std::vector<GatherTask> gt;
-  int maxr = 1, maxc = 1;
-  {
-    std::map<int, const Sector*> bym;
-    for (auto& s : secs) bym[s.m] = &s;
-    for (auto& kv : th.blocks) {
-      const int qa = kv.first[0], s1 = kv.first[1], s2 = kv.first[2];
-      auto it = bym.find(qa + s1);
-      if (it == bym.end()) continue;
-      const Sector& s = *it->second;
-      int ri = -1, ci = -1;
-      for (size_t i = 0; i < s.rows.size(); ++i) if (s.rows[i].first == s1) ri = (int)i;
-      for (size_t i = 0; i < s.cols.size(); ++i) if (s.cols[i].first == s2) ci = (int)i;
-      if (ri < 0 || ci < 0) continue;
-      gt.push_back(GatherTask{kv.second.off, s.a_base + (int64_t)s.coff[ci] * s.R + s.roff[ri],
-                              kv.second.rows, kv.second.cols, s.R, 0});
-      maxr = std::max(maxr, kv.second.rows);
-      maxc = std::max(maxc, kv.second.cols);
+  int64_t gsize = 0;
+  int esize = 0;
+  for (auto& s : secs) {
+    s.n = right ? s.R : s.C;
+    s.gbase = gsize;
+    gsize += (int64_t)s.n * s.n;
+    s.ebase = esize;
+    esize += s.n;
+  }
+  // --- Gram matrices (split planes, row-major n x n per sector) -------------
+  HostGemm gg;
+  for (auto& s : secs) {
+    if (right) {
+      // conj(X_i X_j^+) = conj(X_i) X_j^T summed over column groups s2
+      for (size_t i = 0; i < s.rows.size(); ++i)
+        for (size_t j = 0; j < s.rows.size(); ++j) {
+          const int s1i = s.rows[i].first, qai = s.rows[i].second;
+          const int s1j = s.rows[j].first, qaj = s.rows[j].second;
+          gg.add_task(s.gbase + (int64_t)s.roff[i] * s.n + s.roff[j], th.left.at(qai),
+                      th.left.at(qaj), s.n);
+          for (auto& cc : s.cols) {
+            auto a = th.blocks.find({qai, s1i, cc.first});
+            auto b = th.blocks.find({qaj, s1j, cc.first});
+            if (a == th.blocks.end() || b == th.blocks.end()) continue;
+            gg.add_seg(a->second.off, a->second.cols, b->second.off, b->second.cols,
+                       a->second.cols);
+          }
+        }
+    } else {
+      // X_i^+ X_j summed over row groups s1
+      for (size_t i = 0; i < s.cols.size(); ++i)
+        for (size_t j = 0; j < s.cols.size(); ++j) {
+          const int s2i = s.cols[i].first, s2j = s.cols[j].first;
+          gg.add_task(s.gbase + (int64_t)s.coff[i] * s.n + s.coff[j],
+                      th.right.at(s.cols[i].second), th.right.at(s.cols[j].second), s.n);
+          for (auto& rr : s.rows) {
+            auto a = th.blocks.find({rr.second, rr.first, s2i});
+            auto b = th.blocks.find({rr.second, rr.first, s2j});
+            if (a == th.blocks.end() || b == th.blocks.end()) continue;
+            gg.add_seg(a->second.off, a->second.cols, b->second.off, b->second.cols,
+                       a->second.rows);
+          }
+        }
     }
   }
-  DevBuf gtab(&c.pool, std::max<size_t>(gt.size(), 1) * sizeof(GatherTask));
-  if (!gt.empty())
-    TNT_HIP(hipMemcpyAsync(gtab.ptr, gt.data(), gt.size() * sizeof(GatherTask),
-                           hipMemcpyHostToDevice, c.stream));
-  launch_gather_cm(gtab.as<GatherTask>(), (int)gt.size(), maxr, maxc, re, im, mat.as<double>(),
-                   c.stream);
-  // per-sector FP64 SVD
+  gg.finalize(default_tile_cfg(gg, PATH_F64));
+  DevTables tg;
+  tg.upload(c, {&gg}, {});
+  DevBuf gram(&c.pool, std::max<int64_t>(1, 2 * gsize) * sizeof(double));
+  DevBuf z(&c.pool, std::max<int64_t>(1, 2 * gsize) * sizeof(double));
+  DevBuf ev(&c.pool, (size_t)std::max(1, 2 * esize) * sizeof(double));
+  DevBuf info(&c.pool, std::max<size_t>(secs.size(), 1) * sizeof(rocblas_int));
+  double* g = gram.as<double>();
+  run_gemm(c, tg.g[0], right ? FORM_cNT : FORM_CN, PATH_F64, re, im, ET_F64, re, im, ET_F64, g,
+           g + gsize, ET_F64);
+  // the row-major buffer read column-major is G (absorb right) or conj(G) (left)
+  launch_interleave(g, g + gsize, z.as<double>(), gsize, right ? 0 : 1, c.stream);
+  // --- FP64 Hermitian eigendecompositions, one per sector -------------------
   rocblas_handle h = blas(c);
-  double* S = sbuf.as<double>();
-  double* E = S + ns;
+  double* W = ev.as<double>();
+  double* E = W + esize;
   for (size_t i = 0; i < secs.size(); ++i) {
     const Sector& s = secs[i];
-    auto* A = reinterpret_cast<rocblas_double_complex*>(mat.as<double>()) + s.a_base;
-    auto* U = reinterpret_cast<rocblas_double_complex*>(ubuf.as<double>()) + s.u_base;
-    auto* V = reinterpret_cast<rocblas_double_complex*>(vbuf.as<double>()) + s.v_base;
-    rocblas_status st = rocsolver_zgesvd(h, rocblas_svect_singular, rocblas_svect_singular, s.R,
-                                         s.C, A, s.R, S + s.s_base, U, s.R, V, s.K,
-                                         E + s.e_base, rocblas_outofplace,
-                                         info.as<rocblas_int>() + i);
-    if (st != rocblas_status_success) fail(TNT_E_HIP, "rocsolver_zgesvd failed");
+    auto* A = reinterpret_cast<rocblas_double_complex*>(z.as<double>()) + s.gbase;
+    if (rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, s.n, A, s.n,
+                         W + s.ebase, E + s.ebase, info.as<rocblas_int>() + i) !=
+        rocblas_status_success)
+      fail(TNT_E_HIP, "rocsolver_zheevd failed");
   }
-  std::vector<double> hs(ns);
+  std::vector<double> mu(esize);
   std::vector<rocblas_int> hinfo(secs.size());
-  TNT_HIP(hipMemcpyAsync(hs.data(), S, ns * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  TNT_HIP(hipMemcpyAsync(mu.data(), W, esize * sizeof(double), hipMemcpyDeviceToHost, c.stream));
   TNT_HIP(hipMemcpyAsync(hinfo.data(), info.ptr, secs.size() * sizeof(rocblas_int),
                          hipMemcpyDeviceToHost, c.stream));
   TNT_HIP(hipStreamSynchronize(c.stream));
   for (auto v : hinfo)
-    if (v != 0) fail(TNT_E_HIP, "SVD did not converge in a sector");
-  for (double v : hs)
-    if (!std::isfinite(v)) fail(TNT_E_NONFINITE, "non-finite singular value (theta not finite?)");
-  // pool, sort (lambda desc, then m asc, then index asc), select
+    if (v != 0) fail(TNT_E_HIP, "eigensolver did not converge in a sector");
+  double mumax = 0;
+  int nmax = 1;
+  for (double v : mu) {
+    if (!std::isfinite(v)) fail(TNT_E_NONFINITE, "non-finite Gram eigenvalue (theta not finite?)");
+    mumax = std::max(mumax, v);
+  }
+  for (auto& s : secs) nmax = std::max(nmax, s.n);
+  if (!(mumax > 0)) fail(TNT_E_NONFINITE, "theta has zero norm");
+  const double floor = 4.0 * 2.220446049250313e-16 * nmax * mumax;
+  // pool (lambda desc, then sector asc, then index asc), select
   struct Ent { double lam; int sec, idx; };
   std::vector<Ent> pool;
-  pool.reserve(ns);
-  for (size_t i = 0; i < secs.size(); ++i)
-    for (int k = 0; k < secs[i].K; ++k) pool.push_back({hs[secs[i].s_base + k], (int)i, k});
+  pool.reserve(esize);
+  for (size_t i = 0; i < secs.size(); ++i) {
+    const Sector& s = secs[i];
+    const int K = std::min(s.R, s.C);  // rank bound: at most K nonzero singular values
+    for (int k = 0; k < K; ++k) {
+      const double m = mu[s.ebase + s.n - 1 - k];  // descending
+      pool.push_back({m > floor ? std::sqrt(m) : 0.0, (int)i, k});
+    }
+  }
   std::stable_sort(pool.begin(), pool.end(), [](const Ent& a, const Ent& b) {
     if (a.lam != b.lam) return a.lam > b.lam;
     if (a.sec != b.sec) return a.sec < b.sec;
@@ -212,6 +253,7 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
   });
   std::vector<double> sorted(pool.size());
   for (size_t i = 0; i < pool.size(); ++i) sorted[i] = pool[i].lam;
+  SvdOut out;
   double eps = 0;
   const int chi = trunc_select(sorted.data(), (int)sorted.size(), p, &eps);
   double nk = 0;
@@ -220,21 +262,22 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
     secs[pool[i].sec].kept++;
   }
   nk = std::sqrt(nk);
-  if (!(nk > 0)) fail(TNT_E_NONFINITE, "theta has zero norm");
-  const double scale = p.renormalise ? 1.0 / nk : 1.0;
   out.chi = chi;
   out.eps = eps;
   out.lambda0 = sorted.empty() ? 0 : sorted[0];
   out.norm_kept = nk;
+  const double scale = p.renormalise && nk > 0 ? 1.0 / nk : 1.0;
   for (auto& s : secs) {
     if (s.kept == 0) continue;
     out.bond[s.m] = s.kept;
-    s.lam_base = (int)out.lam.size();
-    for (int k = 0; k < s.kept; ++k) out.lam.push_back(hs[s.s_base + k] * scale);
+    for (int k = 0; k < s.kept; ++k) {
+      const double m = mu[s.ebase + s.n - 1 - k];
+      out.lam.push_back((m > floor ? std::sqrt(m) : 0.0) * scale);
+    }
   }
   // factor layouts: A blocks (q_a, s1) ascending, B blocks (m, s2) ascending
   {
-    std::map<std::pair<int, int>, std::pair<int, int>> ablk, bblk;  // key -> (rows, cols)
+    std::map<std::pair<int, int>, std::pair<int, int>> ablk, bblk;
     for (auto& s : secs) {
       if (s.kept == 0) continue;
       for (auto& r : s.rows) ablk[{r.second, r.first}] = {th.left.at(r.second), s.kept};
@@ -254,48 +297,119 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
     out.B.elems = off;
   }
   const FactorPlanes fp = alloc(out);
-  double *a_re = fp.a_re, *a_im = fp.a_im, *b_re = fp.b_re, *b_im = fp.b_im;
-  // scatter
+  // --- factors -----------------------------------------------------------
+  const double* zz = z.as<double>();
   std::vector<ScatterTask> st;
   int mr = 1, mc = 1;
-  for (auto& s : secs) {
-    if (s.kept == 0) continue;
-    for (size_t i = 0; i < s.rows.size(); ++i) {
-      const int s1 = s.rows[i].first, qa = s.rows[i].second;
-      const BlockRef& b = out.A.blocks.at({qa, s1});
-      st.push_back(ScatterTask{s.u_base + s.roff[i], b.off,
-                               absorb == TNT_ABSORB_LEFT ? (int64_t)s.lam_base : -1, b.rows,
-                               b.cols, s.R, 0});
-      mr = std::max(mr, b.rows); mc = std::max(mc, b.cols);
+  auto add_st = [&](int64_t src, int64_t rs, int64_t cs, int64_t dst, int rows, int cols,
+                    int conj) {
+    st.push_back(ScatterTask{src, rs, cs, dst, rows, cols, conj, 0});
+    mr = std::max(mr, rows);
+    mc = std::max(mc, cols);
+  };
+  HostGemm gp;  // projection: the non-isometric factor
+  DevBuf tmp;
+  int64_t tsize = 0;
+  if (right) {
+    // A(q_a, s1)[r, c] = eigvec(roff + r, n - 1 - c)
+    for (auto& s : secs) {
+      if (s.kept == 0) continue;
+      for (size_t i = 0; i < s.rows.size(); ++i) {
+        const BlockRef& b = out.A.blocks.at({s.rows[i].second, s.rows[i].first});
+        add_st(s.gbase + s.roff[i] + (int64_t)(s.n - 1) * s.n, 1, -(int64_t)s.n, b.off, b.rows,
+               b.cols, 0);
+      }
+      // B(m, s2) = sum_{s1} A(q_a, s1)^+ theta(q_a, s1, s2)
+      for (size_t j = 0; j < s.cols.size(); ++j) {
+        const int s2 = s.cols[j].first;
+        const BlockRef& ob = out.B.blocks.at({s.m, s2});
+        gp.add_task(ob.off, ob.rows, ob.cols, ob.cols);
+        for (auto& rr : s.rows) {
+          auto tb = th.blocks.find({rr.second, rr.first, s2});
+          if (tb == th.blocks.end()) continue;
+          const BlockRef& ab = out.A.blocks.at({rr.second, rr.first});
+          gp.add_seg(ab.off, ab.cols, tb->second.off, tb->second.cols, ab.rows);
+        }
+      }
+    }
+  } else {
+    // the interleave conjugated the row-major X^+ X back into G = X^+ X, so the
+    // eigenvectors are the columns of V:  B(m, s2)[r, c] = conj(V(coff + c, n - 1 - r))
+    for (auto& s : secs) {
+      if (s.kept == 0) continue;
+      s.tbase = tsize;
+      tsize += (int64_t)s.C * s.kept;
+      for (size_t j = 0; j < s.cols.size(); ++j) {
+        const BlockRef& b = out.B.blocks.at({s.m, s.cols[j].first});
+        add_st(s.gbase + s.coff[j] + (int64_t)(s.n - 1) * s.n, -(int64_t)s.n, 1, b.off, b.rows,
+               b.cols, 1);
+      }
     }
   }
-  const size_t na = st.size();
-  for (auto& s : secs) {
-    if (s.kept == 0) continue;
-    for (size_t i = 0; i < s.cols.size(); ++i) {
-      const int s2 = s.cols[i].first;
-      const BlockRef& b = out.B.blocks.at({s.m, s2});
-      st.push_back(ScatterTask{s.v_base + (int64_t)s.coff[i] * s.K, b.off,
-                               absorb == TNT_ABSORB_RIGHT ? (int64_t)s.lam_base : -1, b.rows,
-                               b.cols, s.K, 1});
-      mr = std::max(mr, b.rows); mc = std::max(mc, b.cols);
+  const size_t nfac = st.size();
+  if (!right) {
+    // V_kept row-major (C x kept): V_kept(r, c) = V(r, n - 1 - c)
+    for (auto& s : secs) {
+      if (s.kept == 0) continue;
+      add_st(s.gbase + (int64_t)(s.n - 1) * s.n, 1, -(int64_t)s.n, s.tbase, s.C, s.kept, 0);
+      // A(q_a, s1) = sum_{s2} theta(q_a, s1, s2) V_kept[(s2, b) rows]
+      for (auto& rr : s.rows) {
+        const BlockRef& ab = out.A.blocks.at({rr.second, rr.first});
+        gp.add_task(ab.off, ab.rows, ab.cols, ab.cols);
+        for (size_t j = 0; j < s.cols.size(); ++j) {
+          auto tb = th.blocks.find({rr.second, rr.first, s.cols[j].first});
+          if (tb == th.blocks.end()) continue;
+          gp.add_seg(tb->second.off, tb->second.cols, s.tbase + (int64_t)s.coff[j] * s.kept,
+                     s.kept, tb->second.cols);
+        }
+      }
     }
+    tmp = DevBuf(&c.pool, std::max<int64_t>(1, 2 * tsize) * sizeof(double));
   }
-  DevBuf stab(&c.pool, std::max<size_t>(st.size(), 1) * sizeof(ScatterTask) +
-                           std::max<size_t>(out.lam.size(), 1) * sizeof(double));
-  char* base = stab.as<char>();
-  double* lam_dev = reinterpret_cast<double*>(base + std::max<size_t>(st.size(), 1) * sizeof(ScatterTask));
+  gp.finalize(default_tile_cfg(gp, PATH_F64));
+  DevBuf stab(&c.pool, std::max<size_t>(st.size(), 1) * sizeof(ScatterTask));
   if (!st.empty())
-    TNT_HIP(hipMemcpyAsync(base, st.data(), st.size() * sizeof(ScatterTask),
+    TNT_HIP(hipMemcpyAsync(stab.ptr, st.data(), st.size() * sizeof(ScatterTask),
                            hipMemcpyHostToDevice, c.stream));
-  if (!out.lam.empty())
-    TNT_HIP(hipMemcpyAsync(lam_dev, out.lam.data(), out.lam.size() * sizeof(double),
-                           hipMemcpyHostToDevice, c.stream));
-  const ScatterTask* sdev = reinterpret_cast<const ScatterTask*>(base);
-  launch_scatter_cm(sdev, (int)na, mr, mc, ubuf.as<double>(), lam_dev, a_re, a_im, c.stream);
-  launch_scatter_cm(sdev + na, (int)(st.size() - na), mr, mc, vbuf.as<double>(), lam_dev, b_re,
-                    b_im, c.stream);
-  // the host vectors above must outlive the asynchronous copies
+  const ScatterTask* sdev = stab.as<ScatterTask>();
+  DevTables tp;
+  tp.upload(c, {&gp}, {});
+  DevBuf part(&c.pool, (RED_BLOCKS + 8) * sizeof(double));
+  double* centre;
+  int64_t centre_n;
+  if (right) {
+    launch_scatter_z(sdev, (int)nfac, mr, mc, zz, fp.a_re, fp.a_im, c.stream);
+    run_gemm(c, tp.g[0], FORM_CN, PATH_F64, fp.a_re, fp.a_im, ET_F64, re, im, ET_F64, fp.b_re,
+             fp.b_im, ET_F64);
+    centre = fp.b_re;
+    centre_n = out.B.elems;
+  } else {
+    double* t = tmp.as<double>();
+    launch_scatter_z(sdev, (int)nfac, mr, mc, zz, fp.b_re, fp.b_im, c.stream);
+    launch_scatter_z(sdev + nfac, (int)(st.size() - nfac), mr, mc, zz, t, t + tsize, c.stream);
+    run_gemm(c, tp.g[0], FORM_NN, PATH_F64, re, im, ET_F64, t, t + tsize, ET_F64, fp.a_re,
+             fp.a_im, ET_F64);
+    centre = fp.a_re;
+    centre_n = out.A.elems;
+  }
+  if (p.renormalise) {
+    // unit Frobenius norm of the centre factor (re and im planes are separate)
+    double* pp = part.as<double>();
+    const double* cim = right ? fp.b_im : fp.a_im;
+    launch_norm2_partial(centre, centre_n, pp, c.stream);
+    launch_reduce_partials(pp, 1, RED_BLOCKS, pp + RED_BLOCKS, c.stream);
+    launch_norm2_partial(cim, centre_n, pp, c.stream);
+    launch_reduce_partials(pp, 1, RED_BLOCKS, pp + RED_BLOCKS + 1, c.stream);
+    double nn[2] = {0, 0};
+    TNT_HIP(hipMemcpyAsync(nn, pp + RED_BLOCKS, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           c.stream));
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    const double f = 1.0 / std::sqrt(nn[0] + nn[1]);
+    if (!std::isfinite(f)) fail(TNT_E_NONFINITE, "kept part of theta has zero norm");
+    launch_scale_host(centre, centre_n, f, c.stream);
+    launch_scale_host(const_cast<double*>(cim), centre_n, f, c.stream);
+  }
+  // the host task vectors above must outlive the asynchronous copies
   TNT_HIP(hipStreamSynchronize(c.stream));
   return out;
 }

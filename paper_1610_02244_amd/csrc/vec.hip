@@ -313,52 +313,42 @@ void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// SVD staging: planes (row-major blocks) <-> interleaved column-major matrices
+// SVD staging: split planes <-> interleaved complex (the eigensolver's format)
 // ---------------------------------------------------------------------------
-__global__ void gather_cm_kernel(const GatherTask* __restrict__ tasks,
-                                 const double* __restrict__ re, const double* __restrict__ im,
-                                 double* __restrict__ z) {
-  const GatherTask t = tasks[blockIdx.z];
-  // thread grid over (row, col) of the block; rows fastest for the column-major write
-  for (int c = blockIdx.y; c < t.cols; c += gridDim.y)
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < t.rows;
-         r += gridDim.x * blockDim.x) {
-      const int64_t src = t.src_off + (int64_t)r * t.cols + c;
-      const int64_t dst = t.dst_off + (int64_t)c * t.ld + r;
-      z[2 * dst] = re[src];
-      z[2 * dst + 1] = im[src];
-    }
-}
-
-void launch_gather_cm(const GatherTask* t, int ntask, int maxrows, int maxcols,
-                      const double* re, const double* im, double* dst_z, hipStream_t s) {
-  if (ntask <= 0) return;
-  dim3 grid((maxrows + 63) / 64, maxcols < 256 ? maxcols : 256, ntask);
-  hipLaunchKernelGGL(gather_cm_kernel, grid, dim3(64), 0, s, t, re, im, dst_z);
-}
-
-__global__ void scatter_cm_kernel(const ScatterTask* __restrict__ tasks,
-                                  const double* __restrict__ z, const double* __restrict__ scale,
-                                  double* __restrict__ re, double* __restrict__ im) {
+__global__ void scatter_z_kernel(const ScatterTask* __restrict__ tasks,
+                                 const double* __restrict__ z, double* __restrict__ re,
+                                 double* __restrict__ im) {
   const ScatterTask t = tasks[blockIdx.z];
   for (int r = blockIdx.y; r < t.rows; r += gridDim.y)
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < t.cols;
          c += gridDim.x * blockDim.x) {
-      const int64_t src = t.src_off + (int64_t)c * t.ld + r;
-      double f = 1.0;
-      if (t.scale_off >= 0) f = scale[t.scale_off + (t.scale_on_rows ? r : c)];
+      const int64_t src = t.src_off + (int64_t)r * t.rs + (int64_t)c * t.cs;
       const int64_t dst = t.dst_off + (int64_t)r * t.cols + c;
-      re[dst] = z[2 * src] * f;
-      im[dst] = z[2 * src + 1] * f;
+      re[dst] = z[2 * src];
+      im[dst] = t.conj ? -z[2 * src + 1] : z[2 * src + 1];
     }
 }
 
-void launch_scatter_cm(const ScatterTask* t, int ntask, int maxrows, int maxcols,
-                       const double* src_z, const double* scale, double* re, double* im,
-                       hipStream_t s) {
+void launch_scatter_z(const ScatterTask* t, int ntask, int maxrows, int maxcols,
+                      const double* src_z, double* re, double* im, hipStream_t s) {
   if (ntask <= 0) return;
   dim3 grid((maxcols + 63) / 64, maxrows < 256 ? maxrows : 256, ntask);
-  hipLaunchKernelGGL(scatter_cm_kernel, grid, dim3(64), 0, s, t, src_z, scale, re, im);
+  hipLaunchKernelGGL(scatter_z_kernel, grid, dim3(64), 0, s, t, src_z, re, im);
+}
+
+__global__ void interleave_kernel(const double* __restrict__ re, const double* __restrict__ im,
+                                  double* __restrict__ z, int64_t n, int conj) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    z[2 * k] = re[k];
+    z[2 * k + 1] = conj ? -im[k] : im[k];
+  }
+}
+
+void launch_interleave(const double* re, const double* im, double* z, int64_t n, int conj,
+                       hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(interleave_kernel, dim3(grid_for(n)), dim3(256), 0, s, re, im, z, n, conj);
 }
 
 }  // namespace tnt

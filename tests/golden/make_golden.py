@@ -25,6 +25,7 @@ CASES = {
     "cfg1_exact": ("cfg1", 81, 2, None),
     "cfg2": ("cfg2", None, 1, None),
     "cfg2_2sweeps": ("cfg2", None, 2, None),
+    "cfg2_4sweeps": ("cfg2", None, 4, None),
     "cfg3_chi128": ("cfg3", 128, 2, None),
 }
 

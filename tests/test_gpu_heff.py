@@ -21,6 +21,11 @@ def rel_err(a: dict, b: dict) -> float:
     return (num / den) ** 0.5
 
 
+class Model(tuple):
+    """The oracle's MPO (W, qw) plus the model parameters the GPU side uses to
+    build its own MPO with the library."""
+
+
 def make_case(left, right, nmax, seed, U=3.0, J=1.0, mu=0.0, herm=True):
     d = nmax + 1
     W, qw = model.bh_mpo(nmax, J, U, mu)
@@ -29,7 +34,16 @@ def make_case(left, right, nmax, seed, U=3.0, J=1.0, mu=0.0, herm=True):
     Le = synth.random_env(left, qw, rng, pairs)
     Re = synth.random_env(right, qw, rng, pairs)
     th = synth.random_theta(left, right, d, rng)
-    return W, qw, Le, Re, th
+    Wm = Model((W, (nmax, J, U, mu)))
+    return Wm, qw, Le, Re, th
+
+
+def gpu_mpo(tnt, Wm):
+    """The library's own Bose-Hubbard MPO for the model parameters of Wm."""
+    from paper_1610_02244_amd import binding as B
+    nmax, J, U, mu = Wm[1]
+    Wg, qg = tnt.bose_hubbard_mpo(nmax, J, U, mu)
+    return B.Mpo(Wg, qg)
 
 
 def bonds_of(cfg):
@@ -47,9 +61,8 @@ CASES = {
 }
 
 
-def run_gpu(tnt, W, qw, Le, Re, th, precision):
-    from paper_1610_02244_amd import binding as B
-    mpo = B.Mpo(W, qw)
+def run_gpu(tnt, Wm, qw, Le, Re, th, precision):
+    mpo = gpu_mpo(tnt, Wm)
     Ld, Rd, td = tnt.env(Le, qw), tnt.env(Re, qw), tnt.theta(th)
     out = tnt.theta_like(td)
     tnt.heff2_apply(Ld, mpo, mpo, Rd, td, out, precision)
@@ -61,7 +74,7 @@ def test_heff_fp64_parity(tnt, name):
     left, right, nmax = CASES[name]
     print(f"[heff fp64] case={name} left={left} right={right}", flush=True)
     W, qw, Le, Re, th = make_case(left, right, nmax, seed=17)
-    ref = oheff.heff2_block(Le, W, W, Re, th, left, right, qw, nmax + 1)
+    ref = oheff.heff2_block(Le, W[0], W[0], Re, th, left, right, qw, nmax + 1)
     got = run_gpu(tnt, W, qw, Le, Re, th, "fp64")
     assert set(got) == set(ref)
     err = rel_err(got, ref)
@@ -74,7 +87,7 @@ def test_heff_fp32_parity(tnt, name):
     left, right, nmax = CASES[name]
     print(f"[heff fp32] case={name}", flush=True)
     W, qw, Le, Re, th = make_case(left, right, nmax, seed=23)
-    ref = oheff.heff2_block(Le, W, W, Re, th, left, right, qw, nmax + 1)
+    ref = oheff.heff2_block(Le, W[0], W[0], Re, th, left, right, qw, nmax + 1)
     got = run_gpu(tnt, W, qw, Le, Re, th, "fp32")
     err = rel_err(got, ref)
     print(f"  rel err fp32 = {err:.3e}")
@@ -97,7 +110,7 @@ def test_heff_full_size_sampled(tnt):
     W, qw, Le, Re, th = make_case(left, right, nmax, seed=31)
     qs = sorted(left)
     pick = {qs[0], qs[len(qs) // 2]}
-    ref = oheff.heff2_block(Le, W, W, Re, th, left, right, qw, nmax + 1, out_sectors=pick)
+    ref = oheff.heff2_block(Le, W[0], W[0], Re, th, left, right, qw, nmax + 1, out_sectors=pick)
     for prec, bar in (("fp64", 1e-12), ("fp32", 2e-6)):
         got = run_gpu(tnt, W, qw, Le, Re, th, prec)
         sel = {k: ref[k] for k in ref if k[0] in pick}
@@ -110,7 +123,7 @@ def test_heff_rejects_charge_violation(tnt):
     from paper_1610_02244_amd import binding as B
     left, right, nmax = CASES["tiny"]
     W, qw, Le, Re, th = make_case(left, right, nmax, seed=1)
-    mpo = B.Mpo(W, qw)
+    mpo = gpu_mpo(tnt, W)
     Ld, Rd, td = tnt.env(Le, qw), tnt.env(Re, qw), tnt.theta(th)
     td.qn[3] += 1
     out = tnt.theta_like(tnt.theta(th))

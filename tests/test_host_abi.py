@@ -106,6 +106,17 @@ def test_flop_counter_rejects_charge_violation(lib):
     assert lib.tnt_heff2_flops(Ld.ref, mpo.ref, mpo.ref, Rd.ref, th.ref, None) == -1
 
 
+@pytest.mark.parametrize("nmax,J,U,mu", [(1, 1.0, 0.0, 0.0), (2, 1.0, 2.0, 0.0),
+                                         (4, 0.7, 3.3, 0.4)])
+def test_library_mpo_equals_oracle_mpo(lib, nmax, J, U, mu):
+    # two independent constructions of Eq. (2)'s MPO; the oracle's is pinned to ED
+    Wl, ql = B.bose_hubbard_mpo(lib, nmax, J, U, mu)
+    Wo, qo = model.bh_mpo(nmax, J, U, mu)
+    np.testing.assert_array_equal(Wl, Wo)
+    assert list(ql) == list(qo)
+    assert (B.MPO_LEFT, B.MPO_RIGHT) == (model.MPO_LEFT, model.MPO_RIGHT)
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_trunc_select_matches_oracle(lib, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
