@@ -23,6 +23,13 @@ Ctx::~Ctx() {
   if (blas) destroy_blas(blas);
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
+  for (int i = 0; i < kSide; ++i) {
+    if (side[i]) (void)hipStreamSynchronize(side[i]);
+    if (side_blas[i]) destroy_blas(side_blas[i]);
+    if (side[i]) (void)hipStreamDestroy(side[i]);
+  }
+  for (auto& e : side_ev)
+    if (e) (void)hipEventDestroy(e);
 }
 
 void Hasher::add(const void* p, size_t n) {

@@ -94,6 +94,12 @@ struct Ctx {
   // shared H_eff workspaces (one operator runs at a time per context):
   // 0 = L.theta slabs, 1 = MPO-combined slabs, 2 = FP32 L copy, 3 = FP32 R copy
   DevBuf ws[4];
+  // side streams (default priority) with their own rocBLAS handles, used to
+  // run independent per-sector dense factorizations concurrently
+  static constexpr int kSide = 8;
+  hipStream_t side[kSide] = {};
+  void* side_blas[kSide] = {};
+  hipEvent_t side_ev[kSide + 1] = {};
   ~Ctx();
 };
 

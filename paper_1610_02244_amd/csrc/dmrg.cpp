@@ -5,6 +5,9 @@
 // theta and the SVD are FP64.
 #include "dmrg.h"
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -258,36 +261,109 @@ void build_boundaries(Ctx& c, EnvS& e) {
 }
 
 // ---------------------------------------------------------------------------
-// right-canonical form by exact SVDs (sites L..2), then unit norm
+// right-canonical form by Householder QR (sites L..2), then unit norm.
+// For each left sector q of site j, M_q (rows a, columns (s, b)) satisfies
+// M_q^+ = Q R (reduced, rocSOLVER geqrf + ungqr); site j keeps Q^+ (a right
+// isometry, k = min(rows, cols) rows) and R^+ is absorbed into site j-1.
 // ---------------------------------------------------------------------------
 void right_canonicalize(Ctx& c, MpsH& m) {
-  tnt_trunc_params exact{INT_MAX, TNT_ERR_2NORM, -1.0, -1.0, -1.0, 0};
+  rocblas_handle h = static_cast<rocblas_handle>(blas_handle(c));
   for (int j = m.L; j >= 2; --j) {
-    // site j as a one-site "theta": keys (q, 0, s), rows (a), columns (s, b)
-    ThetaH th;
-    th.d = m.d;
-    for (auto& kv : m.lay[j - 1].blocks) {
-      th.blocks[{kv.first.first, 0, kv.first.second}] = kv.second;
-      th.left[kv.first.first] = kv.second.rows;
-      th.right[kv.first.first + kv.first.second] = kv.second.cols;
+    const SiteH& S = m.lay[j - 1];
+    struct Sec { int q, R, C, k; int64_t zbase, tbase, rbase; std::vector<std::pair<int, int>> cols; };
+    std::map<int, Sec> secs;  // left charge -> sector
+    for (auto& kv : S.blocks) {
+      Sec& s = secs[kv.first.first];
+      s.q = kv.first.first;
+      s.R = kv.second.rows;
+      s.cols.push_back({kv.first.second, kv.second.cols});
     }
-    th.elems = th.extent = m.lay[j - 1].elems;
-    if (th.blocks.empty()) fail(TNT_E_STATE, "site " + std::to_string(j) + " has no block");
-    DevBuf us, site;
-    SvdOut r = svd_truncate_dev(c, th, m.re(j), m.im(j), exact, TNT_ABSORB_LEFT,
-                                [&](const SvdOut& o) {
-                                  us = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.A.elems) * 8);
-                                  site = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.B.elems) * 8);
-                                  FactorPlanes fp;
-                                  fp.a_re = us.as<double>();
-                                  fp.a_im = us.as<double>() + o.A.elems;
-                                  fp.b_re = site.as<double>();
-                                  fp.b_im = site.as<double>() + o.B.elems;
-                                  return fp;
-                                });
-    // new site j = V^+ with keys (m, s): the left bond sector m = q
-    const Bond newb = r.bond;
-    // absorb (U S)(q) into site j-1: A'(q', s') = A(q', s') US(q' + s')
+    if (secs.empty()) fail(TNT_E_STATE, "site " + std::to_string(j) + " has no block");
+    int64_t zs = 0, ts = 0, rs = 0;
+    for (auto& kv : secs) {
+      Sec& s = kv.second;
+      s.C = 0;
+      for (auto& cc : s.cols) s.C += cc.second;
+      s.k = std::min(s.R, s.C);
+      s.zbase = zs; zs += (int64_t)s.C * s.R;   // M^+ column-major (C x R)
+      s.tbase = ts; ts += s.k;                  // Householder scalars
+      s.rbase = rs; rs += (int64_t)s.R * s.k;   // R^+ (R x k) row-major
+    }
+    Bond newb;
+    for (auto& kv : secs) newb[kv.first] = kv.second.k;
+    // gather M^+ : Z[c + r C] = conj(M[r][c])
+    std::vector<GatherTask> gt;
+    int mr = 1, mc = 1;
+    for (auto& kv : secs) {
+      const Sec& s = kv.second;
+      int64_t co = 0;
+      for (auto& cc : s.cols) {
+        const BlockRef& b = S.blocks.at({s.q, cc.first});
+        gt.push_back(GatherTask{b.off, s.zbase + co, s.C, 1, b.rows, b.cols, 1, 0});
+        mr = std::max(mr, b.rows);
+        mc = std::max(mc, b.cols);
+        co += cc.second;
+      }
+    }
+    DevBuf gtab(&c.pool, gt.size() * sizeof(GatherTask));
+    TNT_HIP(hipMemcpyAsync(gtab.ptr, gt.data(), gt.size() * sizeof(GatherTask),
+                           hipMemcpyHostToDevice, c.stream));
+    DevBuf z(&c.pool, std::max<int64_t>(1, 2 * zs) * sizeof(double));
+    DevBuf tau(&c.pool, std::max<int64_t>(1, 2 * ts) * sizeof(double));
+    launch_gather_z(gtab.as<GatherTask>(), (int)gt.size(), mr, mc, m.re(j), m.im(j),
+                    z.as<double>(), c.stream);
+    auto* Z = reinterpret_cast<rocblas_double_complex*>(z.as<double>());
+    auto* T = reinterpret_cast<rocblas_double_complex*>(tau.as<double>());
+    for (auto& kv : secs) {
+      const Sec& s = kv.second;
+      if (rocsolver_zgeqrf(h, s.C, s.R, Z + s.zbase, s.C, T + s.tbase) != rocblas_status_success)
+        fail(TNT_E_HIP, "rocsolver_zgeqrf failed");
+    }
+    // R^+ (R x k, lower triangular) before Q overwrites the factor
+    std::vector<ScatterTask> st;
+    mr = mc = 1;
+    for (auto& kv : secs) {
+      const Sec& s = kv.second;
+      st.push_back(ScatterTask{s.zbase, s.C, 1, s.rbase, s.R, s.k, 1, 1});
+      mr = std::max(mr, s.R);
+      mc = std::max(mc, s.k);
+    }
+    DevBuf rbuf(&c.pool, std::max<int64_t>(1, 2 * rs) * sizeof(double));
+    double* rp = rbuf.as<double>();
+    DevBuf stab(&c.pool, (st.size() + S.blocks.size()) * sizeof(ScatterTask));
+    TNT_HIP(hipMemcpyAsync(stab.ptr, st.data(), st.size() * sizeof(ScatterTask),
+                           hipMemcpyHostToDevice, c.stream));
+    launch_scatter_z(stab.as<ScatterTask>(), (int)st.size(), mr, mc, z.as<double>(), rp, rp + rs,
+                     c.stream);
+    for (auto& kv : secs) {
+      const Sec& s = kv.second;
+      if (rocsolver_zungqr(h, s.C, s.k, s.k, Z + s.zbase, s.C, T + s.tbase) !=
+          rocblas_status_success)
+        fail(TNT_E_HIP, "rocsolver_zungqr failed");
+    }
+    // new site j = Q^+: block (q, s)[r, c] = conj(Q(coff + c, r))
+    SiteH Bn = make_site(newb, m.bonds[j], m.d);
+    std::vector<ScatterTask> sb;
+    mr = mc = 1;
+    for (auto& kv : secs) {
+      const Sec& s = kv.second;
+      int64_t co = 0;
+      for (auto& cc : s.cols) {
+        const BlockRef& b = Bn.blocks.at({s.q, cc.first});
+        sb.push_back(ScatterTask{s.zbase + co, s.C, 1, b.off, b.rows, b.cols, 1, 0});
+        mr = std::max(mr, b.rows);
+        mc = std::max(mc, b.cols);
+        co += cc.second;
+      }
+    }
+    DevBuf site(&c.pool, std::max<int64_t>(1, 2 * Bn.elems) * sizeof(double));
+    launch_fill_zero(site.ptr, ET_F64, 2 * Bn.elems, c.stream);  // blocks absent before stay zero
+    ScatterTask* sdev = stab.as<ScatterTask>() + st.size();
+    TNT_HIP(hipMemcpyAsync(sdev, sb.data(), sb.size() * sizeof(ScatterTask),
+                           hipMemcpyHostToDevice, c.stream));
+    launch_scatter_z(sdev, (int)sb.size(), mr, mc, z.as<double>(), site.as<double>(),
+                     site.as<double>() + Bn.elems, c.stream);
+    // absorb R^+ into site j-1: A'(q', s') = A(q', s') R^+(q' + s')
     const SiteH& Ao = m.lay[j - 2];
     SiteH An;
     int64_t off = 0;
@@ -302,23 +378,17 @@ void right_canonicalize(Ctx& c, MpsH& m) {
     HostGemm g;
     for (auto& kv : An.blocks) {
       const BlockRef& ob = Ao.blocks.at(kv.first);
-      const int qr = kv.first.first + kv.first.second;
-      const BlockRef& ub = r.A.blocks.at({qr, 0});
+      const Sec& s = secs.at(kv.first.first + kv.first.second);
       g.add_task(kv.second.off, kv.second.rows, kv.second.cols, kv.second.cols);
-      g.add_seg(ob.off, ob.cols, ub.off, ub.cols, ob.cols);
+      g.add_seg(ob.off, ob.cols, s.rbase, s.k, ob.cols);
     }
     g.finalize(default_tile_cfg(g, PATH_F64));
     DevTables t;
     t.upload(c, {&g}, {});
-    DevBuf nb(&c.pool, std::max<int64_t>(1, 2 * An.elems) * 8);
-    run_gemm(c, t.g[0], FORM_NN, PATH_F64, m.re(j - 1), m.im(j - 1), ET_F64, us.as<double>(),
-             us.as<double>() + r.A.elems, ET_F64, nb.as<double>(), nb.as<double>() + An.elems,
-             ET_F64);
+    DevBuf nb(&c.pool, std::max<int64_t>(1, 2 * An.elems) * sizeof(double));
+    run_gemm(c, t.g[0], FORM_NN, PATH_F64, m.re(j - 1), m.im(j - 1), ET_F64, rp, rp + rs, ET_F64,
+             nb.as<double>(), nb.as<double>() + An.elems, ET_F64);
     TNT_HIP(hipStreamSynchronize(c.stream));
-    // commit
-    SiteH Bn;
-    for (auto& kv : r.B.blocks) Bn.blocks[kv.first] = kv.second;
-    Bn.elems = r.B.elems;
     m.lay[j - 1] = Bn;
     m.dat[j - 1] = std::move(site);
     m.lay[j - 2] = An;

@@ -123,15 +123,28 @@ void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s);
 // Scatter from an interleaved complex matrix into row-major split-plane
 // blocks: dst(r, c) = f(src[src_off + r * rs + c * cs]) for r < rows,
 // c < cols, where f conjugates when `conj` is set (strides in complex
-// elements, possibly negative).
+// elements, possibly negative); with `lower` set, entries with c > r are
+// written as zero (the conjugate transpose of an upper-triangular factor).
 struct ScatterTask {
   int64_t src_off;
   int64_t rs, cs;
   int64_t dst_off;   // element offset in the destination planes
   int32_t rows, cols;
   int32_t conj;
+  int32_t lower;
+};
+// Gather row-major split-plane blocks into an interleaved complex matrix:
+// z[dst_off + r * drs + c * dcs] = f(src(r, c)).
+struct GatherTask {
+  int64_t src_off;   // element offset of the row-major block in the planes
+  int64_t dst_off;   // complex offset
+  int64_t drs, dcs;
+  int32_t rows, cols;
+  int32_t conj;
   int32_t pad;
 };
+void launch_gather_z(const GatherTask* t, int ntask, int maxrows, int maxcols,
+                     const double* re, const double* im, double* z, hipStream_t s);
 void launch_scatter_z(const ScatterTask* t, int ntask, int maxrows, int maxcols,
                       const double* src_z, double* re, double* im, hipStream_t s);
 // z[2k] = re[k], z[2k+1] = (conj ? -im[k] : im[k]) for k < n

@@ -45,6 +45,24 @@ static rocblas_handle blas(Ctx& c) {
   return h;
 }
 
+void* blas_handle(Ctx& c) { return blas(c); }
+
+// Lazily create the side streams (non-blocking, default priority) and their
+// rocBLAS handles.
+static void ensure_side(Ctx& c) {
+  if (c.side[0]) return;
+  for (int i = 0; i < Ctx::kSide; ++i) {
+    TNT_HIP(hipStreamCreateWithFlags(&c.side[i], hipStreamNonBlocking));
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success)
+      fail(TNT_E_HIP, "rocblas_create_handle failed");
+    if (rocblas_set_stream(h, c.side[i]) != rocblas_status_success)
+      fail(TNT_E_HIP, "rocblas_set_stream failed");
+    c.side_blas[i] = h;
+  }
+  for (auto& e : c.side_ev) TNT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+}
+
 double trunc_error(const double* lam, int n, int kind) {
   double s = 0;
   if (kind == TNT_ERR_1NORM) {
@@ -206,16 +224,42 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
   // the row-major buffer read column-major is G (absorb right) or conj(G) (left)
   launch_interleave(g, g + gsize, z.as<double>(), gsize, right ? 0 : 1, c.stream);
   // --- FP64 Hermitian eigendecompositions, one per sector -------------------
+  // The sectors are independent and each decomposition is a long chain of
+  // small launches, so they run concurrently on the side streams (largest
+  // first, greedy by n^3), forked from and joined back into the main stream.
   rocblas_handle h = blas(c);
+  ensure_side(c);
   double* W = ev.as<double>();
   double* E = W + esize;
-  for (size_t i = 0; i < secs.size(); ++i) {
-    const Sector& s = secs[i];
-    auto* A = reinterpret_cast<rocblas_double_complex*>(z.as<double>()) + s.gbase;
-    if (rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, s.n, A, s.n,
-                         W + s.ebase, E + s.ebase, info.as<rocblas_int>() + i) !=
-        rocblas_status_success)
-      fail(TNT_E_HIP, "rocsolver_zheevd failed");
+  {
+    std::vector<int> order(secs.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return secs[a].n > secs[b].n; });
+    double load[Ctx::kSide] = {};
+    bool used[Ctx::kSide] = {};
+    TNT_HIP(hipEventRecord(c.side_ev[Ctx::kSide], c.stream));
+    for (int i : order) {
+      const Sector& s = secs[i];
+      int k = 0;
+      for (int q = 1; q < Ctx::kSide; ++q)
+        if (load[q] < load[k]) k = q;
+      if (!used[k]) {
+        TNT_HIP(hipStreamWaitEvent(c.side[k], c.side_ev[Ctx::kSide], 0));
+        used[k] = true;
+      }
+      load[k] += (double)s.n * s.n * s.n + 1e6;
+      auto* A = reinterpret_cast<rocblas_double_complex*>(z.as<double>()) + s.gbase;
+      if (rocsolver_zheevd(static_cast<rocblas_handle>(c.side_blas[k]), rocblas_evect_original,
+                           rocblas_fill_upper, s.n, A, s.n, W + s.ebase, E + s.ebase,
+                           info.as<rocblas_int>() + i) != rocblas_status_success)
+        fail(TNT_E_HIP, "rocsolver_zheevd failed");
+    }
+    for (int k = 0; k < Ctx::kSide; ++k) {
+      if (!used[k]) continue;
+      TNT_HIP(hipEventRecord(c.side_ev[k], c.side[k]));
+      TNT_HIP(hipStreamWaitEvent(c.stream, c.side_ev[k], 0));
+    }
   }
   std::vector<double> mu(esize);
   std::vector<rocblas_int> hinfo(secs.size());
@@ -223,8 +267,26 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
   TNT_HIP(hipMemcpyAsync(hinfo.data(), info.ptr, secs.size() * sizeof(rocblas_int),
                          hipMemcpyDeviceToHost, c.stream));
   TNT_HIP(hipStreamSynchronize(c.stream));
-  for (auto v : hinfo)
-    if (v != 0) fail(TNT_E_HIP, "eigensolver did not converge in a sector");
+  // divide and conquer can fail on large clusters of (near-)zero eigenvalues;
+  // redo such a sector with the Jacobi eigensolver from the kept Gram planes
+  for (size_t i = 0; i < secs.size(); ++i) {
+    if (hinfo[i] == 0) continue;
+    const Sector& s = secs[i];
+    DevBuf rj(&c.pool, 64);
+    auto* A = reinterpret_cast<rocblas_double_complex*>(z.as<double>()) + s.gbase;
+    launch_interleave(g + s.gbase, g + gsize + s.gbase, z.as<double>() + 2 * s.gbase,
+                      (int64_t)s.n * s.n, right ? 0 : 1, c.stream);
+    if (rocsolver_zheevj(h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper,
+                         s.n, A, s.n, 0.0, rj.as<double>(), 100, rj.as<rocblas_int>() + 4,
+                         W + s.ebase, info.as<rocblas_int>() + i) != rocblas_status_success)
+      fail(TNT_E_HIP, "rocsolver_zheevj failed");
+    TNT_HIP(hipMemcpyAsync(mu.data() + s.ebase, W + s.ebase, s.n * sizeof(double),
+                           hipMemcpyDeviceToHost, c.stream));
+    TNT_HIP(hipMemcpyAsync(&hinfo[i], info.as<rocblas_int>() + i, sizeof(rocblas_int),
+                           hipMemcpyDeviceToHost, c.stream));
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    if (hinfo[i] != 0) fail(TNT_E_HIP, "eigensolver did not converge in a sector");
+  }
   double mumax = 0;
   int nmax = 1;
   for (double v : mu) {

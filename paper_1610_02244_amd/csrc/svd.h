@@ -30,6 +30,9 @@ struct FactorPlanes {
 };
 using FactorAlloc = std::function<FactorPlanes(const SvdOut&)>;
 
+// The context's rocBLAS handle (created on first use) bound to its stream.
+void* blas_handle(Ctx& c);
+
 // Selection of the kept count (host); see tnt_trunc_select.
 int trunc_select(const double* lam, int n, const tnt_trunc_params& p, double* eps);
 double trunc_error(const double* lam, int n, int kind);

@@ -322,11 +322,37 @@ __global__ void scatter_z_kernel(const ScatterTask* __restrict__ tasks,
   for (int r = blockIdx.y; r < t.rows; r += gridDim.y)
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < t.cols;
          c += gridDim.x * blockDim.x) {
-      const int64_t src = t.src_off + (int64_t)r * t.rs + (int64_t)c * t.cs;
       const int64_t dst = t.dst_off + (int64_t)r * t.cols + c;
+      if (t.lower && c > r) {
+        re[dst] = 0.0;
+        im[dst] = 0.0;
+        continue;
+      }
+      const int64_t src = t.src_off + (int64_t)r * t.rs + (int64_t)c * t.cs;
       re[dst] = z[2 * src];
       im[dst] = t.conj ? -z[2 * src + 1] : z[2 * src + 1];
     }
+}
+
+__global__ void gather_z_kernel(const GatherTask* __restrict__ tasks,
+                                const double* __restrict__ re, const double* __restrict__ im,
+                                double* __restrict__ z) {
+  const GatherTask t = tasks[blockIdx.z];
+  for (int r = blockIdx.y; r < t.rows; r += gridDim.y)
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < t.cols;
+         c += gridDim.x * blockDim.x) {
+      const int64_t src = t.src_off + (int64_t)r * t.cols + c;
+      const int64_t dst = t.dst_off + (int64_t)r * t.drs + (int64_t)c * t.dcs;
+      z[2 * dst] = re[src];
+      z[2 * dst + 1] = t.conj ? -im[src] : im[src];
+    }
+}
+
+void launch_gather_z(const GatherTask* t, int ntask, int maxrows, int maxcols,
+                     const double* re, const double* im, double* z, hipStream_t s) {
+  if (ntask <= 0) return;
+  dim3 grid((maxcols + 63) / 64, maxrows < 256 ? maxrows : 256, ntask);
+  hipLaunchKernelGGL(gather_z_kernel, grid, dim3(64), 0, s, t, re, im, z);
 }
 
 void launch_scatter_z(const ScatterTask* t, int ntask, int maxrows, int maxcols,
