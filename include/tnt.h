@@ -81,6 +81,12 @@ const char* tnt_last_error(tnt_ctx ctx);
 tnt_status tnt_sync(tnt_ctx ctx);
 /* Bytes currently held by the context's device pool (in use + cached). */
 int64_t tnt_pool_bytes(tnt_ctx ctx);
+/* Tile-shape autotuning of the H_eff grouped GEMMs (on by default): the
+ * first application of a new block structure times every candidate tile
+ * shape and caches the choice per shape bucket.  Results do not depend on
+ * the shape (the summation order over K is the same).  on = 0 disables
+ * tuning (the planner's default shape is used) and clears the cache. */
+tnt_status tnt_ctx_set_autotune(tnt_ctx ctx, int32_t on);
 
 /* ------------------------------------------------------------------------
  * Block tensors (appendix A.1.1)

@@ -151,6 +151,18 @@ int64_t tnt_pool_bytes(tnt_ctx ctx) {
   return ctx ? reinterpret_cast<Ctx*>(ctx)->pool.held() : -1;
 }
 
+tnt_status tnt_ctx_set_autotune(tnt_ctx ctx, int32_t on) {
+  TNT_API_BEGIN(ctx)
+  c.autotune = on ? 1 : 0;
+  if (!on) c.tune_cache.clear();
+  // cached plans keep the tile tables they were built with
+  if (c.plans) {
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    c.plans->heff.clear();
+  }
+  TNT_API_END
+}
+
 tnt_status tnt_heff2_apply(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_site* W1,
                            const tnt_mpo_site* W2, const tnt_btensor* R,
                            const tnt_btensor* theta, tnt_btensor* out, int32_t precision) {

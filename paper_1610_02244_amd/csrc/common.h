@@ -96,6 +96,9 @@ struct Ctx {
   DevBuf ws[4];
   // side streams (default priority) with their own rocBLAS handles, used to
   // run independent per-sector dense factorizations concurrently
+  // tile-shape decisions of the autotuner per shape bucket (0 = tuning off)
+  int autotune = 1;
+  std::map<uint64_t, int> tune_cache;
   static constexpr int kSide = 8;
   hipStream_t side[kSide] = {};
   void* side_blas[kSide] = {};

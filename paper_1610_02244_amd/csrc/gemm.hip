@@ -236,42 +236,51 @@ static void launch_t(const GemmLaunch& g, hipStream_t s) {
                      static_cast<TC*>(g.c_re), static_cast<TC*>(g.c_im));
 }
 
+// Launch with the tile shape the tile table was built for; a shape the
+// element type does not provide is refused (false), never substituted.
 template <typename T, typename TA, typename TB, typename TC, int FORM>
-static void launch_tiles(const GemmLaunch& g, hipStream_t s) {
+static bool launch_tiles(const GemmLaunch& g, hipStream_t s) {
   switch (g.tile_cfg) {
-    case 0: launch_t<T, TA, TB, TC, FORM, 64, 64>(g, s); break;
-    case 1: launch_t<T, TA, TB, TC, FORM, 32, 32>(g, s); break;
-    case 2: launch_t<T, TA, TB, TC, FORM, 128, 64>(g, s); break;
-    case 3: launch_t<T, TA, TB, TC, FORM, 64, 128>(g, s); break;
-    default:
-      if constexpr (sizeof(T) == 4) launch_t<T, TA, TB, TC, FORM, 128, 128>(g, s);
-      else launch_t<T, TA, TB, TC, FORM, 64, 64>(g, s);
-      break;
+    case 0: launch_t<T, TA, TB, TC, FORM, 64, 64>(g, s); return true;
+    case 1: launch_t<T, TA, TB, TC, FORM, 32, 32>(g, s); return true;
+    case 2: launch_t<T, TA, TB, TC, FORM, 128, 64>(g, s); return true;
+    case 3: launch_t<T, TA, TB, TC, FORM, 64, 128>(g, s); return true;
+    case 4:
+      if constexpr (sizeof(T) == 4) {
+        launch_t<T, TA, TB, TC, FORM, 128, 128>(g, s);
+        return true;
+      }
+      return false;
+    default: return false;
   }
 }
 
+bool gemm_cfg_valid(int cfg, GemmPath path) { return cfg >= 0 && cfg <= (path == PATH_F64 ? 3 : 4); }
+
 bool bf16x3_available() { return false; }
 
-void launch_grouped_gemm(const GemmLaunch& g, hipStream_t s) {
-  if (g.ntiles <= 0) return;
+bool launch_grouped_gemm(const GemmLaunch& g, hipStream_t s) {
+  if (g.ntiles <= 0) return true;
   if (g.path == PATH_F64) {
+    if (g.a_t != ET_F64 || g.b_t != ET_F64 || g.c_t != ET_F64) return false;
     switch (g.form) {
-      case FORM_NN: launch_tiles<double, double, double, double, FORM_NN>(g, s); break;
-      case FORM_NT: launch_tiles<double, double, double, double, FORM_NT>(g, s); break;
-      case FORM_CN: launch_tiles<double, double, double, double, FORM_CN>(g, s); break;
-      case FORM_cNT: launch_tiles<double, double, double, double, FORM_cNT>(g, s); break;
+      case FORM_NN: return launch_tiles<double, double, double, double, FORM_NN>(g, s);
+      case FORM_NT: return launch_tiles<double, double, double, double, FORM_NT>(g, s);
+      case FORM_CN: return launch_tiles<double, double, double, double, FORM_CN>(g, s);
+      case FORM_cNT: return launch_tiles<double, double, double, double, FORM_cNT>(g, s);
     }
-    return;
+    return false;
   }
+  if (g.path != PATH_F32) return false;
   // FP32 path: step 1 (NN: A f32 env copy, B f64 Krylov vector, C f32 slab)
   // and step 4 (NT: A f32 slab, B f32 env copy, C f64 Krylov vector).
-  if (g.form == FORM_NN && g.a_t == ET_F32 && g.b_t == ET_F64 && g.c_t == ET_F32) {
-    launch_tiles<float, float, double, float, FORM_NN>(g, s);
-  } else if (g.form == FORM_NT && g.a_t == ET_F32 && g.b_t == ET_F32 && g.c_t == ET_F64) {
-    launch_tiles<float, float, float, double, FORM_NT>(g, s);
-  } else if (g.form == FORM_NN && g.a_t == ET_F32 && g.b_t == ET_F32 && g.c_t == ET_F32) {
-    launch_tiles<float, float, float, float, FORM_NN>(g, s);
-  }
+  if (g.form == FORM_NN && g.a_t == ET_F32 && g.b_t == ET_F64 && g.c_t == ET_F32)
+    return launch_tiles<float, float, double, float, FORM_NN>(g, s);
+  if (g.form == FORM_NT && g.a_t == ET_F32 && g.b_t == ET_F32 && g.c_t == ET_F64)
+    return launch_tiles<float, float, float, double, FORM_NT>(g, s);
+  if (g.form == FORM_NN && g.a_t == ET_F32 && g.b_t == ET_F32 && g.c_t == ET_F32)
+    return launch_tiles<float, float, float, float, FORM_NN>(g, s);
+  return false;
 }
 
 }  // namespace tnt

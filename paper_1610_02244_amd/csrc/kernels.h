@@ -73,7 +73,10 @@ struct GemmLaunch {
 void gemm_tile_dims(int cfg, int* bm, int* bn);
 int gemm_num_tile_cfgs();
 
-void launch_grouped_gemm(const GemmLaunch& g, hipStream_t s);
+// false when the (path, operand types, form, tile shape) combination is not
+// built; nothing is launched then.
+bool launch_grouped_gemm(const GemmLaunch& g, hipStream_t s);
+bool gemm_cfg_valid(int cfg, GemmPath path);
 bool bf16x3_available();
 
 void launch_combine(const CombTask* tasks, const CombTerm* terms, const int2* chunks,

@@ -13,6 +13,21 @@ namespace tnt {
 // ---------------------------------------------------------------------------
 void HostGemm::finalize(int cfg) {
   tile_cfg = cfg;
+  tiles = build_tiles(cfg);
+  var_cfg.clear();
+  var_tiles.clear();
+}
+
+void HostGemm::add_variant(int cfg) {
+  if (cfg == tile_cfg) return;
+  for (int v : var_cfg)
+    if (v == cfg) return;
+  var_cfg.push_back(cfg);
+  var_tiles.push_back(build_tiles(cfg));
+}
+
+std::vector<int2> HostGemm::build_tiles(int cfg) const {
+  std::vector<int2> tiles;
   int BM, BN;
   gemm_tile_dims(cfg, &BM, &BN);
   const int nt = (int)tasks.size();
@@ -46,6 +61,27 @@ void HostGemm::finalize(int cfg) {
   for (size_t s = 0; s < slots; ++s)
     for (int x = 0; x < 8; ++x)
       if (s < bins[x].size()) tiles[s * 8 + x] = bins[x][s];
+  return tiles;
+}
+
+std::vector<int> tile_candidates(GemmPath path) {
+  if (path == PATH_F64) return {0, 1, 2, 3};
+  return {0, 1, 2, 3, 4};
+}
+
+uint64_t tune_bucket(const HostGemm& h, GemmPath path, int which) {
+  double wsum = 0, dsum = 0;
+  for (const GemmTask& t : h.tasks) {
+    double k = 0;
+    for (int s = 0; s < t.nseg; ++s) k += h.segs[t.seg0 + s].K;
+    const double f = (double)t.M * t.N * k;
+    wsum += f;
+    dsum += f * std::min(t.M, t.N);
+  }
+  const int typ = wsum > 0 ? (int)std::lround(4.0 * std::log2(std::max(1.0, dsum / wsum))) : 0;
+  const int lf = wsum > 0 ? (int)std::lround(std::log2(wsum)) : 0;
+  return ((uint64_t)path << 48) | ((uint64_t)which << 40) | ((uint64_t)(typ & 0xffff) << 16) |
+         (uint64_t)(lf & 0xffff);
 }
 
 void HostComb::finalize() {
@@ -81,13 +117,16 @@ void DevTables::upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
                        const std::vector<const HostComb*>& cs) {
   size_t total = 0;
   auto add = [&](size_t bytes) { size_t o = total; total = align256(total + bytes); return o; };
-  struct GO { size_t t, s, l; };
+  struct GO { size_t t, s, l; std::vector<size_t> v; };
   struct CO { size_t t, m, c; };
   std::vector<GO> go;
   std::vector<CO> co;
-  for (auto* h : gs)
-    go.push_back({add(h->tasks.size() * sizeof(GemmTask)), add(h->segs.size() * sizeof(GemmSeg)),
-                  add(h->tiles.size() * sizeof(int2))});
+  for (auto* h : gs) {
+    GO o{add(h->tasks.size() * sizeof(GemmTask)), add(h->segs.size() * sizeof(GemmSeg)),
+         add(h->tiles.size() * sizeof(int2)), {}};
+    for (auto& vt : h->var_tiles) o.v.push_back(add(vt.size() * sizeof(int2)));
+    go.push_back(o);
+  }
   for (auto* h : cs)
     co.push_back({add(h->tasks.size() * sizeof(CombTask)),
                   add(h->terms.size() * sizeof(CombTerm)), add(h->chunks.size() * sizeof(int2))});
@@ -98,6 +137,9 @@ void DevTables::upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
     if (!h->tasks.empty()) memcpy(&host[go[i].t], h->tasks.data(), h->tasks.size() * sizeof(GemmTask));
     if (!h->segs.empty()) memcpy(&host[go[i].s], h->segs.data(), h->segs.size() * sizeof(GemmSeg));
     if (!h->tiles.empty()) memcpy(&host[go[i].l], h->tiles.data(), h->tiles.size() * sizeof(int2));
+    for (size_t v = 0; v < h->var_tiles.size(); ++v)
+      if (!h->var_tiles[v].empty())
+        memcpy(&host[go[i].v[v]], h->var_tiles[v].data(), h->var_tiles[v].size() * sizeof(int2));
   }
   for (size_t i = 0; i < cs.size(); ++i) {
     auto* h = cs[i];
@@ -110,11 +152,22 @@ void DevTables::upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
   char* base = buf.as<char>();
   g.clear();
   c.clear();
-  for (size_t i = 0; i < gs.size(); ++i)
-    g.push_back(G{reinterpret_cast<const GemmTask*>(base + go[i].t),
-                  reinterpret_cast<const GemmSeg*>(base + go[i].s),
-                  reinterpret_cast<const int2*>(base + go[i].l), (int)gs[i]->tiles.size(),
-                  gs[i]->tile_cfg});
+  for (size_t i = 0; i < gs.size(); ++i) {
+    G x{};
+    x.tasks = reinterpret_cast<const GemmTask*>(base + go[i].t);
+    x.segs = reinterpret_cast<const GemmSeg*>(base + go[i].s);
+    x.tiles[0] = reinterpret_cast<const int2*>(base + go[i].l);
+    x.ntiles[0] = (int)gs[i]->tiles.size();
+    x.cfg[0] = gs[i]->tile_cfg;
+    x.nvar = 1;
+    for (size_t v = 0; v < gs[i]->var_tiles.size() && x.nvar < 8; ++v, ++x.nvar) {
+      x.tiles[x.nvar] = reinterpret_cast<const int2*>(base + go[i].v[v]);
+      x.ntiles[x.nvar] = (int)gs[i]->var_tiles[v].size();
+      x.cfg[x.nvar] = gs[i]->var_cfg[v];
+    }
+    x.sel = 0;
+    g.push_back(x);
+  }
   for (size_t i = 0; i < cs.size(); ++i)
     c.push_back(C{reinterpret_cast<const CombTask*>(base + co[i].t),
                   reinterpret_cast<const CombTerm*>(base + co[i].m),
@@ -124,9 +177,26 @@ void DevTables::upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
 void run_gemm(Ctx& ctx, const DevTables::G& g, GemmForm form, GemmPath path, const void* are,
               const void* aim, ElemType at, const void* bre, const void* bim, ElemType bt,
               void* cre, void* cim, ElemType ct) {
-  GemmLaunch L{g.tasks, g.segs, g.tiles, g.ntiles, g.cfg, are, aim, at, bre, bim, bt,
-               cre,     cim,    ct,      form,     path};
-  launch_grouped_gemm(L, ctx.stream);
+  run_gemm_variant(ctx, g, g.sel, form, path, are, aim, at, bre, bim, bt, cre, cim, ct);
+}
+
+void run_gemm_variant(Ctx& ctx, const DevTables::G& g, int v, GemmForm form, GemmPath path,
+                      const void* are, const void* aim, ElemType at, const void* bre,
+                      const void* bim, ElemType bt, void* cre, void* cim, ElemType ct) {
+  if (v < 0 || v >= g.nvar) fail(TNT_E_STATE, "tile-table variant out of range");
+  GemmLaunch L{g.tasks, g.segs, g.tiles[v], g.ntiles[v], g.cfg[v], are, aim, at,
+               bre,     bim,    bt,         cre,         cim,        ct,  form, path};
+  if (!launch_grouped_gemm(L, ctx.stream))
+    fail(TNT_E_STATE, "grouped GEMM variant not available (path " + std::to_string(path) +
+                          ", tile shape " + std::to_string(g.cfg[v]) + ")");
+}
+
+// index of a tile table usable by `path` (the selected one if valid)
+static int valid_variant(const DevTables::G& g, GemmPath path) {
+  if (gemm_cfg_valid(g.cfg[g.sel], path)) return g.sel;
+  for (int v = 0; v < g.nvar; ++v)
+    if (gemm_cfg_valid(g.cfg[v], path)) return v;
+  fail(TNT_E_STATE, "no tile table valid for this precision");
 }
 
 void run_comb(Ctx& ctx, const DevTables::C& c, const void* sre, const void* sim, void* dre,
@@ -232,8 +302,22 @@ void HeffOp::build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const 
   precision = prec;
   plan = build_heff_plan(L, W1, W2, R, th, out);
   const GemmPath path = prec == TNT_FP64 ? PATH_F64 : PATH_F32;
-  plan.step1.finalize(default_tile_cfg(plan.step1, path));
-  plan.step4.finalize(default_tile_cfg(plan.step4, path));
+  // tile shape: a cached tuning decision for this shape bucket, else the
+  // default plus every candidate for the first application to time
+  bool tune = false;
+  auto setup = [&](HostGemm& h, int which) {
+    auto it = c.tune_cache.find(tune_bucket(h, path, which));
+    h.finalize(it != c.tune_cache.end() ? it->second : default_tile_cfg(h, path));
+    if (it == c.tune_cache.end() && c.autotune) {
+      for (int cfg : tile_candidates(path)) h.add_variant(cfg);
+      tune = true;
+    }
+    // the FP64 refinement of an FP32 operator needs a shape FP64 provides
+    if (path != PATH_F64 && !gemm_cfg_valid(h.tile_cfg, PATH_F64)) h.add_variant(0);
+  };
+  setup(plan.step1, 1);
+  setup(plan.step4, 4);
+  tuned = !tune;
   tab.upload(c, {&plan.step1, &plan.step4}, {&plan.mpo});
   L_ext = L.extent;
   R_ext = R.extent;
@@ -255,47 +339,94 @@ void HeffOp::bind_envs(const void* lre, const void* lim, const void* rre, const 
   }
 }
 
-void HeffOp::apply(const double* xre, const double* xim, double* yre, double* yim, int prec,
-                   bool timed) {
+void HeffOp::launch_step(int step, int v, bool fp64, const double* xre, const double* xim,
+                         double* yre, double* yim) {
   Ctx& c = *ctx;
-  auto mark = [&](int i) {
-    if (timed) TNT_HIP(hipEventRecord(c.ev[i], c.stream));
-  };
-  if (prec == TNT_FP64 || precision == TNT_FP64) {
-    // FP64 (also the refinement matvec of an FP32 operator: FP64 environments)
-    c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(double));
-    c.ws[1].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(double));
+  if (fp64) {
     double* a = c.ws[0].as<double>();
     double* b = c.ws[1].as<double>();
-    mark(2);
-    run_gemm(c, tab.g[0], FORM_NN, PATH_F64, L_re, L_im, ET_F64, xre, xim, ET_F64, a,
-             a + plan.t1_elems, ET_F64);
-    mark(3);
-    run_comb(c, tab.c[0], a, a + plan.t1_elems, b, b + plan.t3_elems, ET_F64);
-    mark(4);
-    run_gemm(c, tab.g[1], FORM_NT, PATH_F64, b, b + plan.t3_elems, ET_F64, R_re, R_im, ET_F64,
-             yre, yim, ET_F64);
-    mark(5);
+    if (step == 1)
+      run_gemm_variant(c, tab.g[0], v, FORM_NN, PATH_F64, L_re, L_im, ET_F64, xre, xim, ET_F64,
+                       a, a + plan.t1_elems, ET_F64);
+    else
+      run_gemm_variant(c, tab.g[1], v, FORM_NT, PATH_F64, b, b + plan.t3_elems, ET_F64, R_re,
+                       R_im, ET_F64, yre, yim, ET_F64);
     return;
   }
-  c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(float));
-  c.ws[1].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(float));
   float* a = c.ws[0].as<float>();
   float* b = c.ws[1].as<float>();
   const float* lf = c.ws[2].as<float>();
   const float* rf = c.ws[3].as<float>();
-  const GemmPath path = prec == TNT_BF16X3 ? PATH_BF16X3 : PATH_F32;
+  const GemmPath path = precision == TNT_BF16X3 ? PATH_BF16X3 : PATH_F32;
+  if (step == 1)
+    run_gemm_variant(c, tab.g[0], v, FORM_NN, path, lf, lf + L_ext, ET_F32, xre, xim, ET_F64, a,
+                     a + plan.t1_elems, ET_F32);
+  else
+    run_gemm_variant(c, tab.g[1], v, FORM_NT, path, b, b + plan.t3_elems, ET_F32, rf,
+                     rf + R_ext, ET_F32, yre, yim, ET_F64);
+}
+
+void HeffOp::apply(const double* xre, const double* xim, double* yre, double* yim, int prec,
+                   bool timed) {
+  Ctx& c = *ctx;
+  const bool fp64 = prec == TNT_FP64 || precision == TNT_FP64;
+  const size_t es = fp64 ? sizeof(double) : sizeof(float);
+  c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * es);
+  c.ws[1].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t3_elems) * es);
+  if (!tuned && !fp64) autotune(xre, xim, yre, yim, prec);
+  if (!tuned && fp64 && precision == TNT_FP64) autotune(xre, xim, yre, yim, prec);
+  auto mark = [&](int i) {
+    if (timed) TNT_HIP(hipEventRecord(c.ev[i], c.stream));
+  };
+  // FP64 (also the refinement matvec of an FP32 operator, on FP64 environments)
+  const GemmPath p = fp64 ? PATH_F64 : PATH_F32;
+  const int v1 = valid_variant(tab.g[0], p), v4 = valid_variant(tab.g[1], p);
   mark(2);
-  run_gemm(c, tab.g[0], FORM_NN, path, lf, lf + L_ext, ET_F32, xre, xim, ET_F64, a,
-           a + plan.t1_elems, ET_F32);
+  launch_step(1, v1, fp64, xre, xim, yre, yim);
   mark(3);
-  run_comb(c, tab.c[0], a, a + plan.t1_elems, b, b + plan.t3_elems, ET_F32);
+  if (fp64)
+    run_comb(c, tab.c[0], c.ws[0].as<double>(), c.ws[0].as<double>() + plan.t1_elems,
+             c.ws[1].as<double>(), c.ws[1].as<double>() + plan.t3_elems, ET_F64);
+  else
+    run_comb(c, tab.c[0], c.ws[0].as<float>(), c.ws[0].as<float>() + plan.t1_elems,
+             c.ws[1].as<float>(), c.ws[1].as<float>() + plan.t3_elems, ET_F32);
   mark(4);
-  run_gemm(c, tab.g[1], FORM_NT, path, b, b + plan.t3_elems, ET_F32, rf, rf + R_ext, ET_F32, yre,
-           yim, ET_F64);
+  launch_step(4, v4, fp64, xre, xim, yre, yim);
   mark(5);
 }
 
-void HeffOp::autotune(const double*, const double*, double*, double*) {}
+void HeffOp::autotune(const double* xre, const double* xim, double* yre, double* yim, int prec) {
+  Ctx& c = *ctx;
+  tuned = true;
+  const bool fp64 = precision == TNT_FP64;
+  const GemmPath path = fp64 ? PATH_F64 : PATH_F32;
+  (void)prec;
+  // candidates run on the operator's real operands; step 4 reads whatever
+  // the slab workspace holds (in bounds; values do not affect timing) and
+  // the caller's apply overwrites every output afterwards
+  for (int step : {1, 4}) {
+    DevTables::G& g = tab.g[step == 1 ? 0 : 1];
+    if (g.nvar <= 1) continue;
+    int best = g.sel;
+    float best_ms = 1e30f;
+    for (int v = 0; v < g.nvar; ++v) {
+      if (!gemm_cfg_valid(g.cfg[v], path)) continue;
+      launch_step(step, v, fp64, xre, xim, yre, yim);  // warm-up
+      TNT_HIP(hipEventRecord(c.ev[6], c.stream));
+      launch_step(step, v, fp64, xre, xim, yre, yim);
+      launch_step(step, v, fp64, xre, xim, yre, yim);
+      TNT_HIP(hipEventRecord(c.ev[7], c.stream));
+      TNT_HIP(hipEventSynchronize(c.ev[7]));
+      float ms = 0;
+      TNT_HIP(hipEventElapsedTime(&ms, c.ev[6], c.ev[7]));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    g.sel = best;
+    c.tune_cache[tune_bucket(step == 1 ? plan.step1 : plan.step4, path, step)] = g.cfg[best];
+  }
+}
 
 }  // namespace tnt

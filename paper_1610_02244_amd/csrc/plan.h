@@ -14,8 +14,11 @@ namespace tnt {
 struct HostGemm {
   std::vector<GemmTask> tasks;
   std::vector<GemmSeg> segs;
-  std::vector<int2> tiles;  // built by finalize
+  std::vector<int2> tiles;  // built by finalize (the default tile shape)
   int tile_cfg = 0;
+  // tile tables of further candidate shapes (autotuning), built by add_variant
+  std::vector<int> var_cfg;
+  std::vector<std::vector<int2>> var_tiles;
   double flops = 0;         // 8 * sum M N K (complex MACs)
 
   int add_task(int64_t c_off, int M, int N, int ldc) {
@@ -32,6 +35,9 @@ struct HostGemm {
   // bins by greedy cost balancing (largest first); block b of the launch
   // runs on XCD b % 8 and takes slot b / 8 of that bin (empty slots exit).
   void finalize(int cfg);
+  // Tile table of another candidate shape (kept beside the default one).
+  void add_variant(int cfg);
+  std::vector<int2> build_tiles(int cfg) const;
 };
 
 // Host task list of one combine launch.
@@ -56,7 +62,17 @@ struct HostComb {
 struct DevTables {
   DevBuf buf;
   std::vector<char> host;  // kept alive until the tables are dropped
-  struct G { const GemmTask* tasks; const GemmSeg* segs; const int2* tiles; int ntiles; int cfg; };
+  // one grouped GEMM: its tasks and one tile table per candidate shape;
+  // `sel` picks the table a launch uses
+  struct G {
+    const GemmTask* tasks;
+    const GemmSeg* segs;
+    const int2* tiles[8];
+    int ntiles[8];
+    int cfg[8];
+    int nvar = 0;
+    int sel = 0;
+  };
   struct C { const CombTask* tasks; const CombTerm* terms; const int2* chunks; int nchunks; };
   std::vector<G> g;
   std::vector<C> c;
@@ -67,11 +83,19 @@ struct DevTables {
 void run_gemm(Ctx& ctx, const DevTables::G& g, GemmForm form, GemmPath path,
               const void* are, const void* aim, ElemType at, const void* bre, const void* bim,
               ElemType bt, void* cre, void* cim, ElemType ct);
+void run_gemm_variant(Ctx& ctx, const DevTables::G& g, int v, GemmForm form, GemmPath path,
+                      const void* are, const void* aim, ElemType at, const void* bre,
+                      const void* bim, ElemType bt, void* cre, void* cim, ElemType ct);
 void run_comb(Ctx& ctx, const DevTables::C& c, const void* sre, const void* sim, void* dre,
               void* dim, ElemType t);
 
 // Default tile shape for a task list (used when no tuned choice exists).
 int default_tile_cfg(const HostGemm& h, GemmPath path);
+// Candidate tile shapes of a path.
+std::vector<int> tile_candidates(GemmPath path);
+// Shape bucket of a task list for the tuning cache (path, flop-weighted
+// typical block dimension, log2 of the flop count).
+uint64_t tune_bucket(const HostGemm& h, GemmPath path, int which);
 
 // ---------------------------------------------------------------------------
 // The two-site H_eff plan: step 1 (L . theta), MPO combination, step 4 (. R)
@@ -110,8 +134,14 @@ struct HeffOp {
   // ev[4]/ev[5] the step-4 launch.
   void apply(const double* xre, const double* xim, double* yre, double* yim, int prec,
              bool timed = false);
-  // re-select tile shapes by timing each candidate on (x -> y)
-  void autotune(const double* xre, const double* xim, double* yre, double* yim);
+  // Pick the tile shape of each grouped GEMM by timing every candidate on
+  // (x -> y) (results do not depend on the shape: every shape sums K in the
+  // same order); decisions are cached per shape bucket in the context.
+  void autotune(const double* xre, const double* xim, double* yre, double* yim, int prec);
+  bool tuned = false;
+  // one grouped-GEMM launch of step 1 or 4 with tile table v
+  void launch_step(int step, int v, bool fp64, const double* xre, const double* xim,
+                   double* yre, double* yim);
 };
 
 }  // namespace tnt

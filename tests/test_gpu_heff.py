@@ -103,6 +103,24 @@ def test_heff_fp64_deterministic(tnt):
         assert np.array_equal(a[k], b[k])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_heff_autotuned_equals_default_tiles(tnt, prec):
+    """Every tile shape sums K in the same order: tuned and default results
+    are bitwise identical."""
+    left, right, nmax = bonds_of("cfg3")
+    W, qw, Le, Re, th = make_case(left, right, nmax, seed=41)
+    try:
+        tnt.set_autotune(False)
+        a = run_gpu(tnt, W, qw, Le, Re, th, prec)
+        tnt.set_autotune(True)
+        b = run_gpu(tnt, W, qw, Le, Re, th, prec)   # tunes on first use
+        c = run_gpu(tnt, W, qw, Le, Re, th, prec)   # tuned choice from the cache
+    finally:
+        tnt.set_autotune(True)
+    for k in a:
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+
+
 def test_heff_full_size_sampled(tnt):
     """chi = 1024 middle bond: compare the output blocks of two sectors exactly."""
     left, right, nmax = bonds_of("cfg3")
