@@ -46,16 +46,46 @@ def make_chain(tnt, B, spec):
     return mps, env
 
 
-def run_sweeps(tnt, torch, mps, env, spec, precision, warmup, steps):
+class Roctx:
+    """roctx range around the timed region (a no-op without libroctx64)."""
+
+    def __init__(self):
+        import ctypes
+        self.lib = None
+        for p in ("/opt/rocm/lib/libroctx64.so", "libroctx64.so"):
+            try:
+                self.lib = ctypes.CDLL(p)
+                self.lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+                break
+            except OSError:
+                continue
+
+    def push(self, name):
+        if self.lib:
+            self.lib.roctxRangePushA(name.encode())
+
+    def pop(self):
+        if self.lib:
+            self.lib.roctxRangePop()
+
+
+TIMED_RANGE = "tnt_bench_timed"
+
+
+def run_sweeps(tnt, torch, mps, env, spec, precision, warmup, steps, roctx=None):
     kw = dict(kmax=spec.lanczos_steps, precision=precision, rel_tol=spec.rel_cutoff)
     for i in range(warmup):
         r = tnt.sweep(mps, env, spec.chi, **kw)
         log(f"  warmup sweep {i + 1} [{precision}]: E = {r['energy']:.12f} ({r['seconds_total']:.2f}s)")
     torch.cuda.synchronize()
+    if roctx:
+        roctx.push(TIMED_RANGE)
     t0 = time.perf_counter()
     res = [tnt.sweep(mps, env, spec.chi, **kw) for _ in range(steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    if roctx:
+        roctx.pop()
     for i, r in enumerate(res):
         log(f"  timed sweep {i + 1} [{precision}]: E = {r['energy']:.12f} ({r['seconds_total']:.2f}s)")
     return res, dt
@@ -133,6 +163,47 @@ def traffic_for(precision):
         return None
 
 
+def summarize_trace(root):
+    """Per-kernel statistics of the dispatches inside the timed roctx range,
+    from the CSV files of `rocprofv3 --kernel-trace --marker-trace
+    --output-format csv -d ROOT`."""
+    import csv
+    kfiles, mfiles = [], []
+    for dp, _, fs in os.walk(root):
+        for f in fs:
+            if f.endswith("kernel_trace.csv"):
+                kfiles.append(os.path.join(dp, f))
+            elif f.endswith("marker_api_trace.csv"):
+                mfiles.append(os.path.join(dp, f))
+    t0 = t1 = None
+    for mf in mfiles:
+        with open(mf) as f:
+            for row in csv.DictReader(f):
+                if any(TIMED_RANGE in str(v) for v in row.values()):
+                    t0, t1 = int(row["Start_Timestamp"]), int(row["End_Timestamp"])
+    if t0 is None:
+        raise SystemExit("timed roctx range not found in the marker trace")
+    stats = {}
+    for kf in kfiles:
+        with open(kf) as f:
+            for row in csv.DictReader(f):
+                s, e = int(row["Start_Timestamp"]), int(row["End_Timestamp"])
+                if s < t0 or e > t1:
+                    continue
+                st = stats.setdefault(row["Kernel_Name"], [0, 0])
+                st[0] += 1
+                st[1] += e - s
+    top = sorted(stats.items(), key=lambda kv: -kv[1][1])
+    gemm = [(k, v) for k, v in stats.items() if "grouped_gemm_kernel<float" in k]
+    gc = sum(v[0] for _, v in gemm)
+    gt = sum(v[1] for _, v in gemm)
+    return {"range_ns": t1 - t0, "kernel_ns_total": sum(v[1] for v in stats.values()),
+            "fp32_grouped_gemm": {"launches": gc, "total_ns": gt,
+                                  "avg_ns": gt / gc if gc else None},
+            "top": [{"kernel": k[:160], "calls": v[0], "total_ms": v[1] / 1e6,
+                     "avg_us": v[1] / v[0] / 1e3} for k, v in top[:25]]}
+
+
 def golden_energy(config, total_sweeps):
     names = {("cfg1", 2): "cfg1", ("cfg2", 1): "cfg2", ("cfg2", 2): "cfg2_2sweeps"}
     case = names.get((config, total_sweeps))
@@ -154,7 +225,12 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="print timed-region kernel statistics of a rocprofv3 CSV trace and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(json.dumps(summarize_trace(args.summarize_trace), indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X and has no "
               "multi-GPU mode (--gpus must be 1)", file=sys.stderr)
@@ -170,7 +246,8 @@ def main():
         f"precision={args.precision} warmup={args.warmup} steps={args.steps}")
 
     mps, env = make_chain(tnt, B, spec)
-    res, dt = run_sweeps(tnt, torch, mps, env, spec, args.precision, args.warmup, args.steps)
+    res, dt = run_sweeps(tnt, torch, mps, env, spec, args.precision, args.warmup, args.steps,
+                         roctx=Roctx())
     flops = sum(r["matvec_flops"] for r in res)
     value = flops / dt / 1e12
     gemm_flops = sum(r["gemm_flops"] for r in res)
