@@ -1,23 +1,31 @@
 // Grouped split-complex GEMM on CDNA4 matrix cores.
 //
 // Every tensor contraction of the two-site DMRG step (H_eff . theta, the
-// environment updates, theta formation) is a list of independent complex
-// block products C[M x N] = sum_seg op(A_seg) op(B_seg) whose sizes follow
-// the U(1) sectors (1 .. ~300 per side at chi = 1024).  One launch covers a
-// whole list: each workgroup owns one BM x BN output tile of one task and
-// walks that task's K-segments in order, so every output element is written
-// by exactly one workgroup with a fixed summation order (bitwise
-// reproducible, no atomics).
+// environment updates, theta formation, Gram matrices of the SVD step) is a
+// list of independent complex block products C[M x N] = sum_seg op(A_seg)
+// op(B_seg) whose sizes follow the U(1) sectors (1 .. ~300 per side at
+// chi = 1024).  One launch covers a whole list: each workgroup owns one
+// BM x BN output tile of one task and walks that task's K-segments in order,
+// so every output element is written by exactly one workgroup with a fixed
+// summation order (bitwise reproducible, no atomics).
 //
 // Complex data live in separate re/im planes.  A complex tile product is four
 // real MFMA products accumulated into two real accumulators:
 //   Cr += Ar Br - Ai Bi ,  Ci += Ar Bi + Ai Br.
-// Operand permutes (row- or column-major blocks, conjugation) are folded
-// into the global->LDS loaders; LDS holds both operands K-major so every
-// MFMA fragment read is 16 consecutive elements per k row.
+// Operand permutes (row- or column-major blocks, conjugation, FP64 -> FP32)
+// are folded into the global->LDS loaders.
+//
+// LDS layout: each operand row (an m of A or an n of B) holds one K-chunk of
+// 16 elements in the permuted order pos(k) = 4 (k mod 4) + k / 4, plus 4
+// elements of padding.  MFMA number kk of a chunk takes k = 4 kk + slot for
+// the operand slot held by lane group slot = lane / 16, so the four values a
+// lane needs for the chunk's four MFMAs are contiguous: one 128-bit LDS read
+// per operand row and plane.  A loader thread owns a (row, k mod 4) residue
+// and writes its four values with one 128-bit LDS store.  The k order of the
+// accumulation is the natural one (chunk by chunk, k = 0, 1, 2, ...).
 //
 // gfx950 MFMA lane layouts used (16x16x4, 64 lanes):
-//   A operand: lane l holds A[l % 16][l / 16];  B: B[l / 16][l % 16];
+//   A operand: lane l holds A[l % 16][slot l / 16];  B: B[slot l / 16][l % 16];
 //   f32 result register r of lane l: C[4 (l / 16) + r][l % 16];
 //   f64 result register r of lane l: C[4 r + l / 16][l % 16].
 #include "kernels.h"
@@ -30,6 +38,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <typename T> struct Mma;
 template <> struct Mma<float> {
   typedef f32x4 acc_t;
+  typedef f32x4 quad_t;
   __device__ static inline acc_t run(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -37,6 +46,7 @@ template <> struct Mma<float> {
 };
 template <> struct Mma<double> {
   typedef f64x4 acc_t;
+  typedef f64x4 quad_t;
   __device__ static inline acc_t run(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -44,8 +54,63 @@ template <> struct Mma<double> {
 };
 
 constexpr int NT = 256;  // 4 waves, arranged 2 x 2 over the output tile
+constexpr int BK = 16;   // K per chunk
+constexpr int KP = 20;   // LDS row length: 16 permuted k + 4 padding
 
-template <typename T, typename TA, typename TB, typename TC, int FORM, int BM, int BN, int BK>
+// Loader of one operand: rows = BR (BM for A, BN for B), residues j = k mod 4.
+// CONTIG: consecutive k are adjacent in memory (then consecutive threads take
+// consecutive residues of a row); otherwise consecutive threads take
+// consecutive rows (k is strided and rows are adjacent).
+template <typename T, typename TS, int BR, bool CONTIG, bool CONJ>
+struct Loader {
+  static constexpr int ITEMS = 4 * BR;
+  static constexpr int PER = (ITEMS + NT - 1) / NT;
+  T v[PER][2][4];
+  // ld_row: element distance between rows; ld_k: between consecutive k
+  __device__ inline void load(const TS* __restrict__ re, const TS* __restrict__ im, int64_t off,
+                              int64_t ld_row, int64_t ld_k, int r0, int rows, int k0, int K,
+                              int tid) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int item = tid + e * NT;
+      const int r = CONTIG ? item / 4 : item % BR;
+      const int j = CONTIG ? item % 4 : item / BR;
+      const bool rv = item < ITEMS && r0 + r < rows;
+      const int64_t base = off + (int64_t)(r0 + r) * ld_row;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + j + 4 * i;
+        T a = 0, b = 0;
+        if (rv && k < K) {
+          const int64_t idx = base + (int64_t)k * ld_k;
+          a = (T)re[idx];
+          b = (T)im[idx];
+          if (CONJ) b = -b;
+        }
+        v[e][0][i] = a;
+        v[e][1][i] = b;
+      }
+    }
+  }
+  __device__ inline void store(T (*S)[BR][KP], int tid) const {
+    using quad_t = typename Mma<T>::quad_t;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int item = tid + e * NT;
+      if (item >= ITEMS) continue;
+      const int r = CONTIG ? item / 4 : item % BR;
+      const int j = CONTIG ? item % 4 : item / BR;
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        quad_t q;
+        q[0] = v[e][p][0]; q[1] = v[e][p][1]; q[2] = v[e][p][2]; q[3] = v[e][p][3];
+        *reinterpret_cast<quad_t*>(&S[p][r][4 * j]) = q;
+      }
+    }
+  }
+};
+
+template <typename T, typename TA, typename TB, typename TC, int FORM, int BM, int BN>
 __global__ __launch_bounds__(NT) void grouped_gemm_kernel(
     const GemmTask* __restrict__ tasks, const GemmSeg* __restrict__ segs,
     const int2* __restrict__ tiles, int ntiles, const TA* __restrict__ Are,
@@ -54,19 +119,20 @@ __global__ __launch_bounds__(NT) void grouped_gemm_kernel(
   constexpr bool TRANS_A = (FORM == FORM_CN);
   constexpr bool CONJ_A = (FORM == FORM_CN || FORM == FORM_cNT);
   constexpr bool TRANS_B = (FORM == FORM_NT || FORM == FORM_cNT);
-  constexpr int PAD = 16 / sizeof(T) * 4;  // 16 floats / 8 doubles of row padding
-  constexpr int EA = BM * BK / NT;         // A elements per thread per chunk
-  constexpr int EB = BK * BN / NT;
+  // FP32 tiles double-buffer the LDS (one barrier per chunk); FP64 tiles
+  // would not fit two stages at useful occupancy and use one
+  constexpr int STAGES = sizeof(T) == 4 ? 2 : 1;
   constexpr int FM = BM / 32, FN = BN / 32;  // 16x16 fragments per wave
-  static_assert(EA >= 1 && EB >= 1 && NT % BK == 0 && NT % BM == 0 && NT % BN == 0, "tile");
   using acc_t = typename Mma<T>::acc_t;
+  using quad_t = typename Mma<T>::quad_t;
 
-  __shared__ T As[2][BK][BM + PAD];
-  __shared__ T Bs[2][BK][BN + PAD];
+  __shared__ __attribute__((aligned(32))) T As[STAGES][2][BM][KP];
+  __shared__ __attribute__((aligned(32))) T Bs[STAGES][2][BN][KP];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int frow = lane & 15, slot = lane >> 4;
 
   // The tile table is laid out by the planner so that block b (which the
   // dispatcher places on XCD b % 8) takes slot b / 8 of that XCD's bin: tasks
@@ -86,77 +152,65 @@ __global__ __launch_bounds__(NT) void grouped_gemm_kernel(
 #pragma unroll
       for (int r = 0; r < 4; ++r) { accR[i][j][r] = 0; accI[i][j][r] = 0; }
 
-  T ra[2][EA], rb[2][EB];  // register staging of the next chunk (re, im)
-
-  // load one BK-chunk of segment `sg` starting at k0 into registers
+  // A (M x K): stored row-major M x K (k contiguous), or K x M for FORM_CN
+  // B (K x N): stored row-major K x N (rows n strided), or N x K (k contiguous)
+  Loader<T, TA, BM, !TRANS_A, CONJ_A> la;
+  Loader<T, TB, BN, TRANS_B, false> lb;
   auto load = [&](const GemmSeg& sg, int k0) {
-    const int K = sg.K;
-#pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      int m, k;
-      if (TRANS_A) { m = tid % BM; k = tid / BM + e * (NT / BM); }
-      else { k = tid % BK; m = tid / BK + e * (NT / BK); }
-      const int gm = m0 + m, gk = k0 + k;
-      T vr = 0, vi = 0;
-      if (gm < M && gk < K) {
-        const int64_t idx = TRANS_A ? sg.a_off + (int64_t)gk * sg.lda + gm
-                                    : sg.a_off + (int64_t)gm * sg.lda + gk;
-        vr = (T)Are[idx];
-        vi = (T)Aim[idx];
-        if (CONJ_A) vi = -vi;
-      }
-      ra[0][e] = vr; ra[1][e] = vi;
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      int n, k;
-      if (TRANS_B) { k = tid % BK; n = tid / BK + e * (NT / BK); }
-      else { n = tid % BN; k = tid / BN + e * (NT / BN); }
-      const int gn = n0 + n, gk = k0 + k;
-      T vr = 0, vi = 0;
-      if (gn < N && gk < K) {
-        const int64_t idx = TRANS_B ? sg.b_off + (int64_t)gn * sg.ldb + gk
-                                    : sg.b_off + (int64_t)gk * sg.ldb + gn;
-        vr = (T)Bre[idx];
-        vi = (T)Bim[idx];
-      }
-      rb[0][e] = vr; rb[1][e] = vi;
-    }
+    la.load(Are, Aim, sg.a_off, TRANS_A ? 1 : sg.lda, TRANS_A ? sg.lda : 1, m0, M, k0, sg.K, tid);
+    lb.load(Bre, Bim, sg.b_off, TRANS_B ? sg.ldb : 1, TRANS_B ? 1 : sg.ldb, n0, N, k0, sg.K, tid);
   };
-  auto store = [&]() {
+  auto store = [&](int st) {
+    la.store(As[st], tid);
+    lb.store(Bs[st], tid);
+  };
+  auto compute = [&](int st, int kvalid) {
+    quad_t ar[FM], ai[FM], nai[FM], br[FN], bi[FN];
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      int m, k;
-      if (TRANS_A) { m = tid % BM; k = tid / BM + e * (NT / BM); }
-      else { k = tid % BK; m = tid / BK + e * (NT / BK); }
-      As[0][k][m] = ra[0][e];
-      As[1][k][m] = ra[1][e];
+    for (int i = 0; i < FM; ++i) {
+      ar[i] = *reinterpret_cast<const quad_t*>(&As[st][0][wm + 16 * i + frow][4 * slot]);
+      ai[i] = *reinterpret_cast<const quad_t*>(&As[st][1][wm + 16 * i + frow][4 * slot]);
+      nai[i] = -ai[i];
     }
 #pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      int n, k;
-      if (TRANS_B) { k = tid % BK; n = tid / BK + e * (NT / BK); }
-      else { n = tid % BN; k = tid / BN + e * (NT / BN); }
-      Bs[0][k][n] = rb[0][e];
-      Bs[1][k][n] = rb[1][e];
+    for (int j = 0; j < FN; ++j) {
+      br[j] = *reinterpret_cast<const quad_t*>(&Bs[st][0][wn + 16 * j + frow][4 * slot]);
+      bi[j] = *reinterpret_cast<const quad_t*>(&Bs[st][1][wn + 16 * j + frow][4 * slot]);
+    }
+    const int nkk = (kvalid + 3) >> 2;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      if (kk < nkk) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            accR[i][j] = Mma<T>::run(ar[i][kk], br[j][kk], accR[i][j]);
+            accR[i][j] = Mma<T>::run(nai[i][kk], bi[j][kk], accR[i][j]);
+            accI[i][j] = Mma<T>::run(ar[i][kk], bi[j][kk], accI[i][j]);
+            accI[i][j] = Mma<T>::run(ai[i][kk], br[j][kk], accI[i][j]);
+          }
+      }
     }
   };
 
   // walk the chunks (segment, k0) of this task in order
-  int s = 0, k0 = 0;
   const int nseg = tk.nseg;
+  int s = 0;
   GemmSeg cur;
   if (nseg > 0) {
     cur = segs[tk.seg0];
-    // skip empty segments
     while (cur.K <= 0 && ++s < nseg) cur = segs[tk.seg0 + s];
   }
-  if (s < nseg) load(cur, 0);
+  if (s < nseg) {
+    load(cur, 0);
+    store(0);
+    __syncthreads();
+  }
+  int k0 = 0, st = 0;
   while (s < nseg) {
     const int kvalid = min(BK, cur.K - k0);
-    store();
-    __syncthreads();
-    // advance to the next chunk and prefetch it while this one computes
+    // next chunk: prefetched into registers while this one computes
     int ns = s, nk0 = k0 + BK;
     GemmSeg nxt = cur;
     if (nk0 >= cur.K) {
@@ -168,34 +222,18 @@ __global__ __launch_bounds__(NT) void grouped_gemm_kernel(
         ++ns;
       }
     }
-    if (ns < nseg) load(nxt, nk0);
-
-    const int nkk = (kvalid + 3) >> 2;
-    for (int kk = 0; kk < nkk; ++kk) {
-      const int kr = kk * 4 + (lane >> 4);
-      T ar[FM], ai[FM], nai[FM], br[FN], bi[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) {
-        ar[i] = As[0][kr][wm + i * 16 + (lane & 15)];
-        ai[i] = As[1][kr][wm + i * 16 + (lane & 15)];
-        nai[i] = -ai[i];
-      }
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        br[j] = Bs[0][kr][wn + j * 16 + (lane & 15)];
-        bi[j] = Bs[1][kr][wn + j * 16 + (lane & 15)];
-      }
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          accR[i][j] = Mma<T>::run(ar[i], br[j], accR[i][j]);
-          accR[i][j] = Mma<T>::run(nai[i], bi[j], accR[i][j]);
-          accI[i][j] = Mma<T>::run(ar[i], bi[j], accI[i][j]);
-          accI[i][j] = Mma<T>::run(ai[i], br[j], accI[i][j]);
-        }
+    const bool more = ns < nseg;
+    if (more) load(nxt, nk0);
+    compute(st, kvalid);
+    if (STAGES == 1) {
+      __syncthreads();
+      if (more) store(0);
+      __syncthreads();
+    } else {
+      if (more) store(st ^ 1);
+      __syncthreads();
+      st ^= 1;
     }
-    __syncthreads();
     s = ns; k0 = nk0; cur = nxt;
   }
 
@@ -207,7 +245,7 @@ __global__ __launch_bounds__(NT) void grouped_gemm_kernel(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm + i * 16 + Mma<T>::row(lane, r);
-        const int gn = n0 + wn + j * 16 + (lane & 15);
+        const int gn = n0 + wn + j * 16 + frow;
         if (gm < M && gn < N) {
           const int64_t idx = tk.c_off + (int64_t)gm * tk.ldc + gn;
           Cre[idx] = (TC)accR[i][j][r];
@@ -228,8 +266,7 @@ int gemm_num_tile_cfgs() { return 5; }
 
 template <typename T, typename TA, typename TB, typename TC, int FORM, int BM, int BN>
 static void launch_t(const GemmLaunch& g, hipStream_t s) {
-  constexpr int BK = 16;
-  hipLaunchKernelGGL((grouped_gemm_kernel<T, TA, TB, TC, FORM, BM, BN, BK>), dim3(g.ntiles),
+  hipLaunchKernelGGL((grouped_gemm_kernel<T, TA, TB, TC, FORM, BM, BN>), dim3(g.ntiles),
                      dim3(NT), 0, s, g.tasks, g.segs, g.tiles, g.ntiles,
                      static_cast<const TA*>(g.a_re), static_cast<const TA*>(g.a_im),
                      static_cast<const TB*>(g.b_re), static_cast<const TB*>(g.b_im),
