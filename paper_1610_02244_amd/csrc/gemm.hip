@@ -9,9 +9,12 @@
 // so every output element is written by exactly one workgroup with a fixed
 // summation order (bitwise reproducible, no atomics).
 //
-// Complex data live in separate re/im planes.  A complex tile product is four
-// real MFMA products accumulated into two real accumulators:
-//   Cr += Ar Br - Ai Bi ,  Ci += Ar Bi + Ai Br.
+// Complex data live in separate re/im planes.  A complex tile product takes
+// three real MFMA products (Gauss's form) accumulated separately over K:
+//   P1 += Ar Br,  P2 += Ai Bi,  P3 += (Ar + Ai)(Br + Bi),
+// and the epilogue forms Cr = P1 - P2, Ci = P3 - P1 - P2.  This issues 3/4
+// of the MFMA work of the schoolbook form; the error stays of the order of
+// the working precision times |A||B| (normwise).
 // Operand permutes (row- or column-major blocks, conjugation, FP64 -> FP32)
 // are folded into the global->LDS loaders.
 //
@@ -144,13 +147,16 @@ __global__ __launch_bounds__(NT) void grouped_gemm_kernel(
   const int m0 = (td.y & 0xffff) * BM, n0 = (td.y >> 16) * BN;
   const int M = tk.M, N = tk.N;
 
-  acc_t accR[FM][FN], accI[FM][FN];
+  // three real products per complex product (Gauss):
+  //   P1 = Ar Br,  P2 = Ai Bi,  P3 = (Ar + Ai)(Br + Bi);
+  //   Cr = P1 - P2,  Ci = P3 - P1 - P2
+  acc_t acc1[FM][FN], acc2[FM][FN], acc3[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) { accR[i][j][r] = 0; accI[i][j][r] = 0; }
+      for (int r = 0; r < 4; ++r) { acc1[i][j][r] = 0; acc2[i][j][r] = 0; acc3[i][j][r] = 0; }
 
   // A (M x K): stored row-major M x K (k contiguous), or K x M for FORM_CN
   // B (K x N): stored row-major K x N (rows n strided), or N x K (k contiguous)
@@ -164,18 +170,27 @@ __global__ __launch_bounds__(NT) void grouped_gemm_kernel(
     la.store(As[st], tid);
     lb.store(Bs[st], tid);
   };
+  // 16x16 fragments lying wholly outside the block are skipped (uniform per
+  // wave), so ragged edges cost 16-granular padding, not tile-granular
+  const int fm_live = min(FM, max(0, (M - m0 - wm + 15) >> 4));
+  const int fn_live = min(FN, max(0, (N - n0 - wn + 15) >> 4));
   auto compute = [&](int st, int kvalid) {
-    quad_t ar[FM], ai[FM], nai[FM], br[FN], bi[FN];
+    quad_t ar[FM], ai[FM], as[FM], br[FN], bi[FN], bs[FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
-      ar[i] = *reinterpret_cast<const quad_t*>(&As[st][0][wm + 16 * i + frow][4 * slot]);
-      ai[i] = *reinterpret_cast<const quad_t*>(&As[st][1][wm + 16 * i + frow][4 * slot]);
-      nai[i] = -ai[i];
+      if (i < fm_live) {
+        ar[i] = *reinterpret_cast<const quad_t*>(&As[st][0][wm + 16 * i + frow][4 * slot]);
+        ai[i] = *reinterpret_cast<const quad_t*>(&As[st][1][wm + 16 * i + frow][4 * slot]);
+        as[i] = ar[i] + ai[i];
+      }
     }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      br[j] = *reinterpret_cast<const quad_t*>(&Bs[st][0][wn + 16 * j + frow][4 * slot]);
-      bi[j] = *reinterpret_cast<const quad_t*>(&Bs[st][1][wn + 16 * j + frow][4 * slot]);
+      if (j < fn_live) {
+        br[j] = *reinterpret_cast<const quad_t*>(&Bs[st][0][wn + 16 * j + frow][4 * slot]);
+        bi[j] = *reinterpret_cast<const quad_t*>(&Bs[st][1][wn + 16 * j + frow][4 * slot]);
+        bs[j] = br[j] + bi[j];
+      }
     }
     const int nkk = (kvalid + 3) >> 2;
 #pragma unroll
@@ -185,10 +200,11 @@ __global__ __launch_bounds__(NT) void grouped_gemm_kernel(
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j) {
-            accR[i][j] = Mma<T>::run(ar[i][kk], br[j][kk], accR[i][j]);
-            accR[i][j] = Mma<T>::run(nai[i][kk], bi[j][kk], accR[i][j]);
-            accI[i][j] = Mma<T>::run(ar[i][kk], bi[j][kk], accI[i][j]);
-            accI[i][j] = Mma<T>::run(ai[i][kk], br[j][kk], accI[i][j]);
+            if (i < fm_live && j < fn_live) {
+              acc1[i][j] = Mma<T>::run(ar[i][kk], br[j][kk], acc1[i][j]);
+              acc2[i][j] = Mma<T>::run(ai[i][kk], bi[j][kk], acc2[i][j]);
+              acc3[i][j] = Mma<T>::run(as[i][kk], bs[j][kk], acc3[i][j]);
+            }
           }
       }
     }
@@ -248,8 +264,9 @@ __global__ __launch_bounds__(NT) void grouped_gemm_kernel(
         const int gn = n0 + wn + j * 16 + frow;
         if (gm < M && gn < N) {
           const int64_t idx = tk.c_off + (int64_t)gm * tk.ldc + gn;
-          Cre[idx] = (TC)accR[i][j][r];
-          Cim[idx] = (TC)accI[i][j][r];
+          const T p1 = acc1[i][j][r], p2 = acc2[i][j][r];
+          Cre[idx] = (TC)(p1 - p2);
+          Cim[idx] = (TC)(acc3[i][j][r] - p1 - p2);
         }
       }
 }
