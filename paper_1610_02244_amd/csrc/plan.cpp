@@ -65,8 +65,12 @@ std::vector<int2> HostGemm::build_tiles(int cfg) const {
 }
 
 std::vector<int> tile_candidates(GemmPath path) {
-  if (path == PATH_F64) return {0, 1, 2, 3};
+  if (path != PATH_F32) return {0, 1, 2, 3};
   return {0, 1, 2, 3, 4};
+}
+
+GemmPath gemm_path(int precision) {
+  return precision == TNT_FP64 ? PATH_F64 : precision == TNT_BF16X3 ? PATH_BF16X3 : PATH_F32;
 }
 
 uint64_t tune_bucket(const HostGemm& h, GemmPath path, int which) {
@@ -301,7 +305,7 @@ void HeffOp::build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const 
   ctx = &c;
   precision = prec;
   plan = build_heff_plan(L, W1, W2, R, th, out);
-  const GemmPath path = prec == TNT_FP64 ? PATH_F64 : PATH_F32;
+  const GemmPath path = gemm_path(prec);
   // tile shape: a cached tuning decision for this shape bucket, else the
   // default plus every candidate for the first application to time
   bool tune = false;
@@ -357,7 +361,7 @@ void HeffOp::launch_step(int step, int v, bool fp64, const double* xre, const do
   float* b = c.ws[1].as<float>();
   const float* lf = c.ws[2].as<float>();
   const float* rf = c.ws[3].as<float>();
-  const GemmPath path = precision == TNT_BF16X3 ? PATH_BF16X3 : PATH_F32;
+  const GemmPath path = gemm_path(precision);
   if (step == 1)
     run_gemm_variant(c, tab.g[0], v, FORM_NN, path, lf, lf + L_ext, ET_F32, xre, xim, ET_F64, a,
                      a + plan.t1_elems, ET_F32);
@@ -378,8 +382,9 @@ void HeffOp::apply(const double* xre, const double* xim, double* yre, double* yi
   auto mark = [&](int i) {
     if (timed) TNT_HIP(hipEventRecord(c.ev[i], c.stream));
   };
-  // FP64 (also the refinement matvec of an FP32 operator, on FP64 environments)
-  const GemmPath p = fp64 ? PATH_F64 : PATH_F32;
+  // FP64 (also the refinement matvec of a reduced-precision operator, on
+  // FP64 environments)
+  const GemmPath p = fp64 ? PATH_F64 : gemm_path(precision);
   const int v1 = valid_variant(tab.g[0], p), v4 = valid_variant(tab.g[1], p);
   mark(2);
   launch_step(1, v1, fp64, xre, xim, yre, yim);
@@ -399,7 +404,7 @@ void HeffOp::autotune(const double* xre, const double* xim, double* yre, double*
   Ctx& c = *ctx;
   tuned = true;
   const bool fp64 = precision == TNT_FP64;
-  const GemmPath path = fp64 ? PATH_F64 : PATH_F32;
+  const GemmPath path = gemm_path(precision);
   (void)prec;
   // candidates run on the operator's real operands; step 4 reads whatever
   // the slab workspace holds (in bounds; values do not affect timing) and

@@ -93,6 +93,8 @@ void run_comb(Ctx& ctx, const DevTables::C& c, const void* sre, const void* sim,
 int default_tile_cfg(const HostGemm& h, GemmPath path);
 // Candidate tile shapes of a path.
 std::vector<int> tile_candidates(GemmPath path);
+// GEMM path of a TNT_FP64 / TNT_FP32 / TNT_BF16X3 operator
+GemmPath gemm_path(int precision);
 // Shape bucket of a task list for the tuning cache (path, flop-weighted
 // typical block dimension, log2 of the flop count).
 uint64_t tune_bucket(const HostGemm& h, GemmPath path, int which);

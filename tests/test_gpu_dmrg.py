@@ -5,7 +5,8 @@ the device: right-canonicalisation, environments, theta formation, Lanczos,
 truncated SVD and environment updates.  The oracle's per-bond energies for
 the same inputs are stored in tests/golden/sweep_*.json (written by
 tests/golden/make_golden.py, oracle only).  Bars: FP64 |dE/E| <= 1e-10 per
-bond; FP32-MFMA matvecs |dE/E| <= 1e-9 at the end of the last sweep.
+bond; FP32-MFMA and BF16x3 matvecs |dE/E| <= 1e-9 at the end of the last
+sweep (the refinement matvec and everything outside Lanczos are FP64).
 """
 import json
 import os
@@ -68,13 +69,14 @@ def test_sweep_cfg1_exact_reaches_ed(tnt):
     assert res[-1]["energy"] == pytest.approx(e_ed, abs=1e-10)
 
 
-def test_sweep_fp32_cfg1(tnt):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_sweep_fp32_cfg1(tnt, precision):
     g = golden("cfg1")
-    res, mps, _ = gpu_sweeps(tnt, g, "fp32")
+    res, mps, _ = gpu_sweeps(tnt, g, precision)
     e = res[-1]["bond_E"][-1]
     er = g["sweeps"][-1]["E"][-1]
     rel = abs(e - er) / abs(er)
-    print(f"  [sweep fp32 cfg1] |dE/E| = {rel:.2e}")
+    print(f"  [sweep {precision} cfg1] |dE/E| = {rel:.2e}")
     assert rel <= 1e-9
 
 
@@ -108,7 +110,7 @@ def test_sweep_cfg2_first_bonds(tnt):
     assert list(res[0]["bond_chi"][:12]) == g["sweeps"][0]["chi"][:12]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_sweep_cfg2_converged(tnt, precision):
     g = golden("cfg2_4sweeps")
     print(f"[sweep cfg2 x4 {precision}]", flush=True)

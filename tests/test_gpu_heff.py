@@ -3,7 +3,11 @@
 Inputs are seeded synthetic blocks (synth); the oracle and the HIP library
 each compute H_eff . theta on the same arrays.  Bars (normwise relative
 error over all blocks): FP64 <= 1e-12; FP32-MFMA <= 2e-6 (FP32 rounding of
-operands and sums over K <= ~4 * 300 terms).
+operands and sums over K <= ~4 * 300 terms); BF16x3 <= 1e-4: each operand
+is split as hi + lo with a residual <= 2^-16 |x| and the lo*lo term is
+dropped, so one real product is off by <= 3 * 2^-16 relative; the two GEMM
+stages (L . theta, then . R on re-split slabs) give <= 6 * 2^-16 = 9.2e-5
+elementwise in the |A||B| sense, and the normwise error is below that.
 """
 import numpy as np
 import pytest
@@ -83,6 +87,21 @@ def test_heff_fp64_parity(tnt, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+def test_heff_bf16x3_parity(tnt, name):
+    left, right, nmax = CASES[name]
+    print(f"[heff bf16x3] case={name}", flush=True)
+    W, qw, Le, Re, th = make_case(left, right, nmax, seed=29)
+    ref = oheff.heff2_block(Le, W[0], W[0], Re, th, left, right, qw, nmax + 1)
+    got = run_gpu(tnt, W, qw, Le, Re, th, "bf16x3")
+    assert set(got) == set(ref)
+    err = rel_err(got, ref)
+    print(f"  rel err bf16x3 = {err:.3e}")
+    assert err <= 1e-4
+    # the split-product arithmetic really ran: FP32 would be ~100x closer
+    assert err >= 1e-7
+
+
+@pytest.mark.parametrize("name", list(CASES))
 def test_heff_fp32_parity(tnt, name):
     left, right, nmax = CASES[name]
     print(f"[heff fp32] case={name}", flush=True)
@@ -103,7 +122,7 @@ def test_heff_fp64_deterministic(tnt):
         assert np.array_equal(a[k], b[k])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_heff_autotuned_equals_default_tiles(tnt, prec):
     """Every tile shape sums K in the same order: tuned and default results
     are bitwise identical."""
@@ -129,7 +148,7 @@ def test_heff_full_size_sampled(tnt):
     qs = sorted(left)
     pick = {qs[0], qs[len(qs) // 2]}
     ref = oheff.heff2_block(Le, W[0], W[0], Re, th, left, right, qw, nmax + 1, out_sectors=pick)
-    for prec, bar in (("fp64", 1e-12), ("fp32", 2e-6)):
+    for prec, bar in (("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 1e-4)):
         got = run_gpu(tnt, W, qw, Le, Re, th, prec)
         sel = {k: ref[k] for k in ref if k[0] in pick}
         err = rel_err(got, sel)

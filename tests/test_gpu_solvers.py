@@ -71,8 +71,9 @@ def test_lanczos_fp64_parity(tnt, name):
     assert ov == pytest.approx(1.0, abs=1e-11)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("name", list(LCASES))
-def test_lanczos_fp32_energy(tnt, name):
+def test_lanczos_fp32_energy(tnt, name, precision):
     from paper_1610_02244_amd import binding as B
     left, right, nmax = LCASES[name]
     W, qw, Le, Re, th, params = herm_case(left, right, nmax, seed=4)
@@ -80,9 +81,9 @@ def test_lanczos_fp32_energy(tnt, name):
     mpo = gpu_mpo(tnt, params)
     td = tnt.theta(th, keys)
     res = tnt.lanczos_ground(tnt.env(Le, qw), mpo, mpo, tnt.env(Re, qw), td, kmax=20,
-                             precision="fp32")
+                             precision=precision)
     rel = abs(res["E"] - ref["E"]) / abs(ref["E"])
-    print(f"  [lanczos fp32] {name}: |dE/E| = {rel:.3e}")
+    print(f"  [lanczos {precision}] {name}: |dE/E| = {rel:.3e}")
     assert rel <= 1e-5
 
 
