@@ -185,7 +185,7 @@ int64_t tnt_heff2_flops(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt_
                         const tnt_btensor* R, const tnt_btensor* theta, int64_t* parts) {
   try {
     HeffArgs a = parse_heff_args(L, W1, W2, R, theta, nullptr);
-    HeffPlan p = build_heff_plan(a.L, a.w1, a.w2, a.R, a.th, a.th);
+    HeffPlan p = build_heff_plan(a.L, a.w1, a.w2, a.R, a.th, a.th, false);
     if (parts) {
       parts[0] = p.flops_step1;
       parts[1] = p.flops_mpo;

@@ -92,8 +92,9 @@ struct Ctx {
   hipEvent_t ev[8] = {};
   int num_cu = 256;
   // shared H_eff workspaces (one operator runs at a time per context):
-  // 0 = L.theta slabs, 1 = MPO-combined slabs, 2 = FP32 L copy, 3 = FP32 R copy
-  DevBuf ws[4];
+  // 0 = L.theta slabs, 1 = MPO-combined slabs, 2 / 3 = packed L / R copies,
+  // 4 = packed theta
+  DevBuf ws[5];
   // side streams (default priority) with their own rocBLAS handles, used to
   // run independent per-sector dense factorizations concurrently
   // tile-shape decisions of the autotuner per shape bucket (0 = tuning off)

@@ -1,4 +1,4 @@
-// Grouped split-complex GEMM on CDNA4 matrix cores.
+// Grouped split-complex FP64 GEMM on CDNA4 matrix cores, any operand form.
 //
 // Every tensor contraction of the two-site DMRG step (H_eff . theta, the
 // environment updates, theta formation, Gram matrices of the SVD step) is a
@@ -7,7 +7,9 @@
 // chi = 1024).  One launch covers a whole list: each workgroup owns one
 // BM x BN output tile of one task and walks that task's K-segments in order,
 // so every output element is written by exactly one workgroup with a fixed
-// summation order (bitwise reproducible, no atomics).
+// summation order (bitwise reproducible, no atomics).  This kernel serves
+// the FP64 path in all four operand forms; the reduced-precision H_eff
+// paths run on packed operands (gemm_packed.hip).
 //
 // Complex data live in separate re/im planes.  A complex tile product takes
 // three real MFMA products (Gauss's form) accumulated separately over K:
@@ -15,48 +17,21 @@
 // and the epilogue forms Cr = P1 - P2, Ci = P3 - P1 - P2.  This issues 3/4
 // of the MFMA work of the schoolbook form; the error stays of the order of
 // the working precision times |A||B| (normwise).
-// Operand permutes (row- or column-major blocks, conjugation, FP64 -> FP32)
-// are folded into the global->LDS loaders.
+// Operand permutes (row- or column-major blocks, conjugation) are folded
+// into the global->LDS loaders.
 //
 // LDS layout: each operand row (an m of A or an n of B) holds one K-chunk of
 // 16 elements in the permuted order pos(k) = 4 (k mod 4) + k / 4, plus 4
 // elements of padding.  MFMA number kk of a chunk takes k = 4 kk + slot for
 // the operand slot held by lane group slot = lane / 16, so the four values a
-// lane needs for the chunk's four MFMAs are contiguous: one 128-bit LDS read
-// per operand row and plane.  A loader thread owns a (row, k mod 4) residue
-// and writes its four values with one 128-bit LDS store.  The k order of the
+// lane needs for the chunk's four MFMAs are contiguous: one LDS read per
+// operand row and plane.  A loader thread owns a (row, k mod 4) residue and
+// writes its four values with one LDS store.  The k order of the
 // accumulation is the natural one (chunk by chunk, k = 0, 1, 2, ...).
-//
-// gfx950 MFMA lane layouts used (16x16x4, 64 lanes):
-//   A operand: lane l holds A[l % 16][slot l / 16];  B: B[slot l / 16][l % 16];
-//   f32 result register r of lane l: C[4 (l / 16) + r][l % 16];
-//   f64 result register r of lane l: C[4 r + l / 16][l % 16].
-#include "kernels.h"
+#include "mfma.h"
 
 namespace tnt {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mma;
-template <> struct Mma<float> {
-  typedef f32x4 acc_t;
-  typedef f32x4 quad_t;
-  __device__ static inline acc_t run(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-template <> struct Mma<double> {
-  typedef f64x4 acc_t;
-  typedef f64x4 quad_t;
-  __device__ static inline acc_t run(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  __device__ static inline int row(int lane, int r) { return 4 * r + (lane >> 4); }
-};
-
-constexpr int NT = 256;  // 4 waves, arranged 2 x 2 over the output tile
 constexpr int BK = 16;   // K per chunk
 constexpr int KP = 20;   // LDS row length: 16 permuted k + 4 padding
 
@@ -112,57 +87,6 @@ struct Loader {
     }
   }
 };
-
-// Walks the K-chunks (segment, k0) of one task in summation order.  The
-// next chunk is fetched into registers (load) while the current LDS stage is
-// consumed (compute); store moves the registers into a stage.  With two
-// stages the chunks alternate between them and one barrier per chunk
-// suffices; with one stage the store waits for every wave's compute.
-template <int BK, int STAGES, typename Load, typename Store, typename Compute>
-__device__ inline void walk_chunks(const GemmSeg* __restrict__ segs, int seg0, int nseg,
-                                   Load& load, Store& store, Compute& compute) {
-  int s = 0;
-  GemmSeg cur;
-  if (nseg > 0) {
-    cur = segs[seg0];
-    while (cur.K <= 0 && ++s < nseg) cur = segs[seg0 + s];
-  }
-  if (s < nseg) {
-    load(cur, 0);
-    store(0);
-    __syncthreads();
-  }
-  int k0 = 0, st = 0;
-  while (s < nseg) {
-    const int kvalid = min(BK, cur.K - k0);
-    int ns = s, nk0 = k0 + BK;
-    GemmSeg nxt = cur;
-    if (nk0 >= cur.K) {
-      nk0 = 0;
-      ++ns;
-      while (ns < nseg) {
-        nxt = segs[seg0 + ns];
-        if (nxt.K > 0) break;
-        ++ns;
-      }
-    }
-    const bool more = ns < nseg;
-    if (more) load(nxt, nk0);
-    compute(st, kvalid);
-    if (STAGES == 1) {
-      __syncthreads();
-      if (more) store(0);
-      __syncthreads();
-    } else {
-      if (more) store(st ^ 1);
-      __syncthreads();
-      st ^= 1;
-    }
-    s = ns;
-    k0 = nk0;
-    cur = nxt;
-  }
-}
 
 template <typename T, typename TA, typename TB, typename TC, int FORM, int BM, int BN>
 __global__ __launch_bounds__(NT) void grouped_gemm_kernel(
@@ -281,192 +205,6 @@ __global__ __launch_bounds__(NT) void grouped_gemm_kernel(
       }
 }
 
-// ---------------------------------------------------------------------------
-// BF16x3 split products.  Each FP32 operand value x is split into two bf16
-// values hi = bf16(x), lo = bf16(x - hi) (round to nearest even; x - hi is
-// exact in FP32), so x = hi + lo up to about 2^-16 |x|.  A real product is
-// approximated by hi*hi + hi*lo + lo*hi (the lo*lo term, of relative size
-// 2^-16, is dropped), each on the bf16 matrix cores with FP32 accumulation.
-// The schoolbook complex form is used here: its four real products read the
-// four split planes (re hi, re lo, im hi, im lo) already in LDS, where the
-// Gauss form would need two more planes for the sums; accumulators
-//   P1 += Ar Br,  P2 += Ai Bi,  P3 += Ar Bi + Ai Br;  Cr = P1 - P2, Ci = P3.
-//
-// gfx950 16x16x32 bf16 MFMA: A lane l holds A[l % 16][8 (l / 16) + e] for
-// e = 0..7, B lane l holds B[8 (l / 16) + e][l % 16]; the FP32 result has the
-// 16x16x4 f32 layout.  The LDS row of an operand holds the 32 k of a chunk
-// in natural order plus 8 bf16 of padding (80-byte rows), so each lane reads
-// its 8 values of a plane with one 128-bit LDS read.
-// ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-constexpr int BKX = 32;  // K per chunk: one bf16 MFMA step
-constexpr int KPX = 40;  // LDS row length in bf16 (32 k + 8 padding)
-
-__device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
-}
-
-// Loader of one operand for the BF16x3 kernel: item = (row, group j of 8
-// consecutive k); CONTIG as in Loader.  Values are held in FP32 until the
-// store splits them into the four bf16 planes.
-template <typename TS, int BR, bool CONTIG, bool CONJ>
-struct LoaderX3 {
-  static constexpr int ITEMS = 4 * BR;
-  static constexpr int PER = (ITEMS + NT - 1) / NT;
-  float v[PER][2][8];
-  __device__ inline void load(const TS* __restrict__ re, const TS* __restrict__ im, int64_t off,
-                              int64_t ld_row, int64_t ld_k, int r0, int rows, int k0, int K,
-                              int tid) {
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int item = tid + e * NT;
-      const int r = CONTIG ? item / 4 : item % BR;
-      const int j = CONTIG ? item % 4 : item / BR;
-      const bool rv = item < ITEMS && r0 + r < rows;
-      const int64_t base = off + (int64_t)(r0 + r) * ld_row;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + 8 * j + i;
-        float a = 0, b = 0;
-        if (rv && k < K) {
-          const int64_t idx = base + (int64_t)k * ld_k;
-          a = (float)re[idx];
-          b = (float)im[idx];
-          if (CONJ) b = -b;
-        }
-        v[e][0][i] = a;
-        v[e][1][i] = b;
-      }
-    }
-  }
-  __device__ inline void store(__bf16 (*S)[BR][KPX], int tid) const {
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int item = tid + e * NT;
-      if (item >= ITEMS) continue;
-      const int r = CONTIG ? item / 4 : item % BR;
-      const int j = CONTIG ? item % 4 : item / BR;
-#pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        bf16x8 hi, lo;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          __bf16 h, l;
-          split_bf16(v[e][p][i], h, l);
-          hi[i] = h;
-          lo[i] = l;
-        }
-        *reinterpret_cast<bf16x8*>(&S[2 * p][r][8 * j]) = hi;
-        *reinterpret_cast<bf16x8*>(&S[2 * p + 1][r][8 * j]) = lo;
-      }
-    }
-  }
-};
-
-template <typename TA, typename TB, typename TC, int FORM, int BM, int BN>
-__global__ __launch_bounds__(NT) void grouped_gemm_x3_kernel(
-    const GemmTask* __restrict__ tasks, const GemmSeg* __restrict__ segs,
-    const int2* __restrict__ tiles, int ntiles, const TA* __restrict__ Are,
-    const TA* __restrict__ Aim, const TB* __restrict__ Bre, const TB* __restrict__ Bim,
-    TC* __restrict__ Cre, TC* __restrict__ Cim) {
-  constexpr bool TRANS_A = (FORM == FORM_CN);
-  constexpr bool CONJ_A = (FORM == FORM_CN || FORM == FORM_cNT);
-  constexpr bool TRANS_B = (FORM == FORM_NT || FORM == FORM_cNT);
-  // two LDS stages while they fit two workgroups per CU
-  constexpr int STAGES = (BM + BN <= 128) ? 2 : 1;
-  constexpr int FM = BM / 32, FN = BN / 32;
-
-  __shared__ __attribute__((aligned(16))) __bf16 As[STAGES][4][BM][KPX];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[STAGES][4][BN][KPX];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
-  const int frow = lane & 15, slot = lane >> 4;
-
-  if ((int)blockIdx.x >= ntiles) return;
-  const int2 td = tiles[blockIdx.x];
-  if (td.x < 0) return;
-  const GemmTask tk = tasks[td.x];
-  const int m0 = (td.y & 0xffff) * BM, n0 = (td.y >> 16) * BN;
-  const int M = tk.M, N = tk.N;
-
-  f32x4 acc1[FM][FN], acc2[FM][FN], acc3[FM][FN];
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) { acc1[i][j][r] = 0; acc2[i][j][r] = 0; acc3[i][j][r] = 0; }
-
-  LoaderX3<TA, BM, !TRANS_A, CONJ_A> la;
-  LoaderX3<TB, BN, TRANS_B, false> lb;
-  auto load = [&](const GemmSeg& sg, int k0) {
-    la.load(Are, Aim, sg.a_off, TRANS_A ? 1 : sg.lda, TRANS_A ? sg.lda : 1, m0, M, k0, sg.K, tid);
-    lb.load(Bre, Bim, sg.b_off, TRANS_B ? sg.ldb : 1, TRANS_B ? 1 : sg.ldb, n0, N, k0, sg.K, tid);
-  };
-  auto store = [&](int st) {
-    la.store(As[st], tid);
-    lb.store(Bs[st], tid);
-  };
-  const int fm_live = min(FM, max(0, (M - m0 - wm + 15) >> 4));
-  const int fn_live = min(FN, max(0, (N - n0 - wn + 15) >> 4));
-  // k beyond the segment is zero in LDS, so a partial chunk needs no guard
-  auto compute = [&](int st, int) {
-    bf16x8 a[FM][4], b[FN][4];
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-      if (i < fm_live)
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-          a[i][p] = *reinterpret_cast<const bf16x8*>(&As[st][p][wm + 16 * i + frow][8 * slot]);
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-      if (j < fn_live)
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-          b[j][p] = *reinterpret_cast<const bf16x8*>(&Bs[st][p][wn + 16 * j + frow][8 * slot]);
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        if (i < fm_live && j < fn_live) {
-          // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo
-#define X3(acc, pa, pb)                                                              \
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][pa], b[j][pb], acc, 0, 0, 0); \
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][pa], b[j][pb + 1], acc, 0, 0, 0); \
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][pa + 1], b[j][pb], acc, 0, 0, 0);
-          X3(acc1[i][j], 0, 0)
-          X3(acc2[i][j], 2, 2)
-          X3(acc3[i][j], 0, 2)
-          X3(acc3[i][j], 2, 0)
-#undef X3
-        }
-      }
-  };
-
-  walk_chunks<BKX, STAGES>(segs, tk.seg0, tk.nseg, load, store, compute);
-
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + i * 16 + Mma<float>::row(lane, r);
-        const int gn = n0 + wn + j * 16 + frow;
-        if (gm < M && gn < N) {
-          const int64_t idx = tk.c_off + (int64_t)gm * tk.ldc + gn;
-          Cre[idx] = (TC)(acc1[i][j][r] - acc2[i][j][r]);
-          Cim[idx] = (TC)acc3[i][j][r];
-        }
-      }
-}
-
-// ---------------------------------------------------------------------------
-
 static const int kTileDims[][2] = {{64, 64}, {32, 32}, {128, 64}, {64, 128}, {128, 128}};
 
 void gemm_tile_dims(int cfg, int* bm, int* bn) {
@@ -475,25 +213,17 @@ void gemm_tile_dims(int cfg, int* bm, int* bn) {
 }
 int gemm_num_tile_cfgs() { return 5; }
 
-// T: MFMA element type (double, float), or __bf16 for the BF16x3 kernel
 template <typename T, typename TA, typename TB, typename TC, int FORM, int BM, int BN>
 static void launch_t(const GemmLaunch& g, hipStream_t s) {
-  if constexpr (sizeof(T) == 2)
-    hipLaunchKernelGGL((grouped_gemm_x3_kernel<TA, TB, TC, FORM, BM, BN>), dim3(g.ntiles),
-                       dim3(NT), 0, s, g.tasks, g.segs, g.tiles, g.ntiles,
-                       static_cast<const TA*>(g.a_re), static_cast<const TA*>(g.a_im),
-                       static_cast<const TB*>(g.b_re), static_cast<const TB*>(g.b_im),
-                       static_cast<TC*>(g.c_re), static_cast<TC*>(g.c_im));
-  else
-    hipLaunchKernelGGL((grouped_gemm_kernel<T, TA, TB, TC, FORM, BM, BN>), dim3(g.ntiles),
-                       dim3(NT), 0, s, g.tasks, g.segs, g.tiles, g.ntiles,
-                       static_cast<const TA*>(g.a_re), static_cast<const TA*>(g.a_im),
-                       static_cast<const TB*>(g.b_re), static_cast<const TB*>(g.b_im),
-                       static_cast<TC*>(g.c_re), static_cast<TC*>(g.c_im));
+  hipLaunchKernelGGL((grouped_gemm_kernel<T, TA, TB, TC, FORM, BM, BN>), dim3(g.ntiles),
+                     dim3(NT), 0, s, g.tasks, g.segs, g.tiles, g.ntiles,
+                     static_cast<const TA*>(g.a_re), static_cast<const TA*>(g.a_im),
+                     static_cast<const TB*>(g.b_re), static_cast<const TB*>(g.b_im),
+                     static_cast<TC*>(g.c_re), static_cast<TC*>(g.c_im));
 }
 
 // Launch with the tile shape the tile table was built for; a shape the
-// element type does not provide is refused (false), never substituted.
+// kernel does not provide is refused (false), never substituted.
 template <typename T, typename TA, typename TB, typename TC, int FORM>
 static bool launch_tiles(const GemmLaunch& g, hipStream_t s) {
   switch (g.tile_cfg) {
@@ -501,52 +231,27 @@ static bool launch_tiles(const GemmLaunch& g, hipStream_t s) {
     case 1: launch_t<T, TA, TB, TC, FORM, 32, 32>(g, s); return true;
     case 2: launch_t<T, TA, TB, TC, FORM, 128, 64>(g, s); return true;
     case 3: launch_t<T, TA, TB, TC, FORM, 64, 128>(g, s); return true;
-    case 4:
-      if constexpr (sizeof(T) == 4) {
-        launch_t<T, TA, TB, TC, FORM, 128, 128>(g, s);
-        return true;
-      }
-      return false;
     default: return false;
   }
 }
 
-// 128 x 128 tiles exist for the FP32 kernel only (FP64 and BF16x3 would spill)
+// 128 x 128 tiles exist for the packed FP32 kernel only (the FP64 and BF16x3
+// kernels would spill registers at that size)
 bool gemm_cfg_valid(int cfg, GemmPath path) { return cfg >= 0 && cfg <= (path == PATH_F32 ? 4 : 3); }
 
 bool bf16x3_available() { return true; }
 
+// FP64 grouped GEMM in any operand form (the reduced-precision paths run on
+// packed operands, launch_packed_gemm)
 bool launch_grouped_gemm(const GemmLaunch& g, hipStream_t s) {
   if (g.ntiles <= 0) return true;
-  if (g.path == PATH_F64) {
-    if (g.a_t != ET_F64 || g.b_t != ET_F64 || g.c_t != ET_F64) return false;
-    switch (g.form) {
-      case FORM_NN: return launch_tiles<double, double, double, double, FORM_NN>(g, s);
-      case FORM_NT: return launch_tiles<double, double, double, double, FORM_NT>(g, s);
-      case FORM_CN: return launch_tiles<double, double, double, double, FORM_CN>(g, s);
-      case FORM_cNT: return launch_tiles<double, double, double, double, FORM_cNT>(g, s);
-    }
-    return false;
+  if (g.path != PATH_F64 || g.a_t != ET_F64 || g.b_t != ET_F64 || g.c_t != ET_F64) return false;
+  switch (g.form) {
+    case FORM_NN: return launch_tiles<double, double, double, double, FORM_NN>(g, s);
+    case FORM_NT: return launch_tiles<double, double, double, double, FORM_NT>(g, s);
+    case FORM_CN: return launch_tiles<double, double, double, double, FORM_CN>(g, s);
+    case FORM_cNT: return launch_tiles<double, double, double, double, FORM_cNT>(g, s);
   }
-  if (g.path == PATH_BF16X3) {
-    // the same operand layouts as the FP32 path
-    if (g.form == FORM_NN && g.a_t == ET_F32 && g.b_t == ET_F64 && g.c_t == ET_F32)
-      return launch_tiles<__bf16, float, double, float, FORM_NN>(g, s);
-    if (g.form == FORM_NT && g.a_t == ET_F32 && g.b_t == ET_F32 && g.c_t == ET_F64)
-      return launch_tiles<__bf16, float, float, double, FORM_NT>(g, s);
-    if (g.form == FORM_NN && g.a_t == ET_F32 && g.b_t == ET_F32 && g.c_t == ET_F32)
-      return launch_tiles<__bf16, float, float, float, FORM_NN>(g, s);
-    return false;
-  }
-  if (g.path != PATH_F32) return false;
-  // FP32 path: step 1 (NN: A f32 env copy, B f64 Krylov vector, C f32 slab)
-  // and step 4 (NT: A f32 slab, B f32 env copy, C f64 Krylov vector).
-  if (g.form == FORM_NN && g.a_t == ET_F32 && g.b_t == ET_F64 && g.c_t == ET_F32)
-    return launch_tiles<float, float, double, float, FORM_NN>(g, s);
-  if (g.form == FORM_NT && g.a_t == ET_F32 && g.b_t == ET_F32 && g.c_t == ET_F64)
-    return launch_tiles<float, float, float, double, FORM_NT>(g, s);
-  if (g.form == FORM_NN && g.a_t == ET_F32 && g.b_t == ET_F32 && g.c_t == ET_F32)
-    return launch_tiles<float, float, float, float, FORM_NN>(g, s);
   return false;
 }
 

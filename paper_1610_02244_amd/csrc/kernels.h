@@ -69,6 +69,66 @@ struct GemmLaunch {
   GemmPath path;
 };
 
+// ---------------------------------------------------------------------------
+// Packed operands of the reduced-precision H_eff paths.  Every block is
+// row-major with the contracted index k contiguous, its row stride a
+// multiple of 8 elements, its offset a multiple of 8 and its padding columns
+// zero, so a loader moves 16 aligned bytes per row and plane in one
+// instruction.  A packed buffer holds its planes back to back with a common
+// plane stride (elements, a multiple of 8):
+//   PK_F32:    float  planes (re, im);
+//   PK_BF16X3: bf16   planes (re hi, re lo, im hi, im lo) of the split
+//              x = hi + lo, hi = bf16(x), lo = bf16(x - hi).
+// ---------------------------------------------------------------------------
+enum PackFmt { PK_F32 = 0, PK_BF16X3 = 1 };
+inline int pack_planes(PackFmt f) { return f == PK_F32 ? 2 : 4; }
+inline int pack_elem_bytes(PackFmt f) { return f == PK_F32 ? 4 : 2; }
+inline int64_t pad8(int64_t x) { return (x + 7) & ~int64_t(7); }
+
+// One block copied from FP64 split planes into a packed buffer:
+// dst(r, c) = src(c, r) if trans else src(r, c), for r < rows, c < cols of
+// the destination; columns cols .. dld-1 are written as zero.
+struct PackTask {
+  int64_t src_off, dst_off;
+  int32_t rows, cols;
+  int32_t sld, dld;
+  int32_t trans;
+  int32_t pad;
+};
+constexpr int PACK_TILE = 32;  // destination tile edge of the pack kernel
+// tiles[i] = (task, tile row | tile col << 16)
+void launch_pack(const PackTask* tasks, const int2* tiles, int ntiles, const double* sre,
+                 const double* sim, void* dst, int64_t plane, PackFmt f, hipStream_t s);
+
+// One slab of the packed MPO combination: dst(r, c) = sum_t coef_t
+// src_t[r * cols + c] (FP32 sources, unpadded) for c < cols, zero for
+// cols <= c < dld; chunks of COMB_CHUNK destination elements.
+struct CombPTask {
+  int64_t dst_off;
+  int32_t rows, cols, dld;
+  int32_t term0, nterm;
+  int32_t pad;
+};
+void launch_combine_packed(const CombPTask* tasks, const CombTerm* terms, const int2* chunks,
+                           int32_t nchunks, const float* src_re, const float* src_im, void* dst,
+                           int64_t plane, PackFmt f, hipStream_t s);
+
+// Grouped GEMM on packed operands: C = A B^T, A (M x K) and B (N x K) both
+// packed (lda, ldb are the packed row strides); C written as TC planes.
+struct PackedLaunch {
+  const GemmTask* tasks;
+  const GemmSeg* segs;
+  const int2* tiles;
+  int32_t ntiles;
+  int32_t tile_cfg;
+  const void* a; int64_t a_plane;
+  const void* b; int64_t b_plane;
+  void* c_re; void* c_im; ElemType c_t;
+  PackFmt fmt;
+};
+// false when the format / tile shape / output type is not built
+bool launch_packed_gemm(const PackedLaunch& g, hipStream_t s);
+
 // Tile shapes available to the planner: returns BM, BN for a config id.
 void gemm_tile_dims(int cfg, int* bm, int* bn);
 int gemm_num_tile_cfgs();

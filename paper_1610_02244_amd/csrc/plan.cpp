@@ -96,6 +96,27 @@ void HostComb::finalize() {
   }
 }
 
+void HostCombP::finalize() {
+  chunks.clear();
+  for (int i = 0; i < (int)tasks.size(); ++i) {
+    const int64_t total = (int64_t)tasks[i].rows * tasks[i].dld;
+    const int n = (int)((total + COMB_CHUNK - 1) / COMB_CHUNK);
+    for (int c = 0; c < n; ++c) chunks.push_back(int2{i, c});
+  }
+}
+
+int64_t HostPack::add(int64_t src_off, int rows, int cols, int sld, bool trans) {
+  const int dld = (int)pad8(cols);
+  const int64_t off = elems;
+  const int ti = (int)tasks.size();
+  tasks.push_back(PackTask{src_off, off, rows, cols, sld, dld, trans ? 1 : 0, 0});
+  const int tr = (rows + PACK_TILE - 1) / PACK_TILE, tc = (dld + PACK_TILE - 1) / PACK_TILE;
+  for (int a = 0; a < tr; ++a)
+    for (int b = 0; b < tc; ++b) tiles.push_back(int2{ti, a | (b << 16)});
+  elems += (int64_t)rows * dld;  // rows * dld is a multiple of 8
+  return off;
+}
+
 int default_tile_cfg(const HostGemm& h, GemmPath path) {
   // flop-weighted typical output dimension
   double wsum = 0, dsum = 0;
@@ -118,7 +139,9 @@ int default_tile_cfg(const HostGemm& h, GemmPath path) {
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 void DevTables::upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
-                       const std::vector<const HostComb*>& cs) {
+                       const std::vector<const HostComb*>& cs,
+                       const std::vector<const HostCombP*>& cps,
+                       const std::vector<const HostPack*>& pks) {
   size_t total = 0;
   auto add = [&](size_t bytes) { size_t o = total; total = align256(total + bytes); return o; };
   struct GO { size_t t, s, l; std::vector<size_t> v; };
@@ -134,6 +157,14 @@ void DevTables::upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
   for (auto* h : cs)
     co.push_back({add(h->tasks.size() * sizeof(CombTask)),
                   add(h->terms.size() * sizeof(CombTerm)), add(h->chunks.size() * sizeof(int2))});
+  std::vector<CO> cpo;
+  for (auto* h : cps)
+    cpo.push_back({add(h->tasks.size() * sizeof(CombPTask)),
+                   add(h->terms.size() * sizeof(CombTerm)), add(h->chunks.size() * sizeof(int2))});
+  struct PO { size_t t, l; };
+  std::vector<PO> po;
+  for (auto* h : pks)
+    po.push_back({add(h->tasks.size() * sizeof(PackTask)), add(h->tiles.size() * sizeof(int2))});
   total = std::max<size_t>(total, 256);
   host.assign(total, 0);
   for (size_t i = 0; i < gs.size(); ++i) {
@@ -151,11 +182,26 @@ void DevTables::upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
     if (!h->terms.empty()) memcpy(&host[co[i].m], h->terms.data(), h->terms.size() * sizeof(CombTerm));
     if (!h->chunks.empty()) memcpy(&host[co[i].c], h->chunks.data(), h->chunks.size() * sizeof(int2));
   }
+  auto put = [&](size_t at, const void* src, size_t bytes) {
+    if (bytes) memcpy(&host[at], src, bytes);
+  };
+  for (size_t i = 0; i < cps.size(); ++i) {
+    auto* h = cps[i];
+    put(cpo[i].t, h->tasks.data(), h->tasks.size() * sizeof(CombPTask));
+    put(cpo[i].m, h->terms.data(), h->terms.size() * sizeof(CombTerm));
+    put(cpo[i].c, h->chunks.data(), h->chunks.size() * sizeof(int2));
+  }
+  for (size_t i = 0; i < pks.size(); ++i) {
+    put(po[i].t, pks[i]->tasks.data(), pks[i]->tasks.size() * sizeof(PackTask));
+    put(po[i].l, pks[i]->tiles.data(), pks[i]->tiles.size() * sizeof(int2));
+  }
   buf = DevBuf(&ctx.pool, total);
   TNT_HIP(hipMemcpyAsync(buf.ptr, host.data(), total, hipMemcpyHostToDevice, ctx.stream));
   char* base = buf.as<char>();
   g.clear();
   c.clear();
+  cp.clear();
+  p.clear();
   for (size_t i = 0; i < gs.size(); ++i) {
     G x{};
     x.tasks = reinterpret_cast<const GemmTask*>(base + go[i].t);
@@ -176,6 +222,14 @@ void DevTables::upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
     c.push_back(C{reinterpret_cast<const CombTask*>(base + co[i].t),
                   reinterpret_cast<const CombTerm*>(base + co[i].m),
                   reinterpret_cast<const int2*>(base + co[i].c), (int)cs[i]->chunks.size()});
+  for (size_t i = 0; i < cps.size(); ++i)
+    cp.push_back(CP{reinterpret_cast<const CombPTask*>(base + cpo[i].t),
+                    reinterpret_cast<const CombTerm*>(base + cpo[i].m),
+                    reinterpret_cast<const int2*>(base + cpo[i].c), (int)cps[i]->chunks.size()});
+  for (size_t i = 0; i < pks.size(); ++i)
+    p.push_back(P{reinterpret_cast<const PackTask*>(base + po[i].t),
+                  reinterpret_cast<const int2*>(base + po[i].l), (int)pks[i]->tiles.size(),
+                  pks[i]->elems});
 }
 
 void run_gemm(Ctx& ctx, const DevTables::G& g, GemmForm form, GemmPath path, const void* are,
@@ -212,8 +266,21 @@ void run_comb(Ctx& ctx, const DevTables::C& c, const void* sre, const void* sim,
 // H_eff plan
 // ---------------------------------------------------------------------------
 HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const EnvH& R,
-                         const ThetaH& th, const ThetaH& out) {
+                         const ThetaH& th, const ThetaH& out, bool packed) {
   HeffPlan P;
+  P.packed = packed;
+  // packed operand copies: every L and R block as stored, theta blocks
+  // transposed (K = dim(q_a) becomes the contiguous index)
+  std::map<std::pair<int, int>, int64_t> lp_off, rp_off;
+  std::map<std::array<int, 3>, int64_t> xp_off;
+  if (packed) {
+    for (auto& b : L.blocks)
+      lp_off[b.first] = P.Lp.add(b.second.off, b.second.rows, b.second.cols, b.second.cols, false);
+    for (auto& b : R.blocks)
+      rp_off[b.first] = P.Rp.add(b.second.off, b.second.rows, b.second.cols, b.second.cols, false);
+    for (auto& b : th.blocks)
+      xp_off[b.first] = P.Xp.add(b.second.off, b.second.cols, b.second.rows, b.second.cols, true);
+  }
   const int D = W1.D, d = th.d;
   const Bond& left = th.left;
   const Bond& right = th.right;
@@ -260,6 +327,10 @@ HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const En
     const BlockRef& tb = th.blocks.at({qa, s1, s2});
     P.step1.add_task(off, M, N, N);
     P.step1.add_seg(lb.off, lb.cols, tb.off, tb.cols, K);
+    if (packed) {
+      P.step1p.add_task(off, M, N, N);
+      P.step1p.add_seg(lp_off.at({w, qa}), (int)pad8(K), xp_off.at({qa, s1, s2}), (int)pad8(K), K);
+    }
     P.flops_step1 += 8LL * M * N * K;
     off += (int64_t)M * N;
   }
@@ -267,21 +338,31 @@ HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const En
   // MPO combination: one T3 slab per live (u, output block)
   off = 0;
   std::map<std::array<int, 4>, int64_t> t3_off;  // (u, qa', s1', s2') -> offset
+  std::map<std::array<int, 4>, int64_t> t3p_off;  // the same slabs, packed
+  int64_t offp = 0;
   for (auto& sl : live) {
     const int M = left.at(sl.okey[0]), N = right.at(sl.qb);
     t3_off[{sl.u, sl.okey[0], sl.okey[1], sl.okey[2]}] = off;
     P.mpo.add_task(off, M * N);
     for (auto& t : sl.terms) P.mpo.add_term(t1_off.at({t.w, t.qa, t.s1, t.s2}), t.c);
+    if (packed) {
+      t3p_off[{sl.u, sl.okey[0], sl.okey[1], sl.okey[2]}] = offp;
+      P.mpop.add_task(offp, M, N, (int)pad8(N));
+      for (auto& t : sl.terms) P.mpop.add_term(t1_off.at({t.w, t.qa, t.s1, t.s2}), t.c);
+      offp += (int64_t)M * pad8(N);
+    }
     P.flops_mpo += 4LL * (int64_t)sl.terms.size() * M * N;
     off += (int64_t)M * N;
   }
   P.t3_elems = off;
+  P.t3p_elems = offp;
   // step 4 tasks: one per output block, K concatenated over live u
   for (auto& ob : out.blocks) {
     const int qap = ob.first[0], s1p = ob.first[1], s2p = ob.first[2];
     const int qbp = qap + s1p + s2p;
     const int M = ob.second.rows, N = ob.second.cols;
     P.step4.add_task(ob.second.off, M, N, N);
+    if (packed) P.step4p.add_task(ob.second.off, M, N, N);
     P.out_keys.push_back(ob.first);
     for (int u = 0; u < D; ++u) {
       auto it = t3_off.find({u, qap, s1p, s2p});
@@ -290,10 +371,14 @@ HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const En
       const BlockRef& rb = R.blocks.at({u, qb});
       const int K = right.at(qb);
       P.step4.add_seg(it->second, K, rb.off, rb.cols, K);
+      if (packed)
+        P.step4p.add_seg(t3p_off.at({u, qap, s1p, s2p}), (int)pad8(K), rp_off.at({u, qb}),
+                         (int)pad8(K), K);
       P.flops_step4 += 8LL * M * N * K;
     }
   }
   P.mpo.finalize();
+  if (packed) P.mpop.finalize();
   return P;
 }
 
@@ -304,25 +389,33 @@ void HeffOp::build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const 
                    const ThetaH& th, const ThetaH& out, int prec) {
   ctx = &c;
   precision = prec;
-  plan = build_heff_plan(L, W1, W2, R, th, out);
-  const GemmPath path = gemm_path(prec);
+  const bool packed = prec != TNT_FP64;
+  plan = build_heff_plan(L, W1, W2, R, th, out, packed);
   // tile shape: a cached tuning decision for this shape bucket, else the
-  // default plus every candidate for the first application to time
+  // default, plus every candidate for the first application to time when
+  // `tunable` (the operator's own precision)
   bool tune = false;
-  auto setup = [&](HostGemm& h, int which) {
+  auto setup = [&](HostGemm& h, int which, GemmPath path, bool tunable) {
     auto it = c.tune_cache.find(tune_bucket(h, path, which));
     h.finalize(it != c.tune_cache.end() ? it->second : default_tile_cfg(h, path));
-    if (it == c.tune_cache.end() && c.autotune) {
+    if (tunable && it == c.tune_cache.end() && c.autotune) {
       for (int cfg : tile_candidates(path)) h.add_variant(cfg);
       tune = true;
     }
-    // the FP64 refinement of an FP32 operator needs a shape FP64 provides
-    if (path != PATH_F64 && !gemm_cfg_valid(h.tile_cfg, PATH_F64)) h.add_variant(0);
   };
-  setup(plan.step1, 1);
-  setup(plan.step4, 4);
+  // FP64 tables: the FP64 operator, or the FP64 refinement of a
+  // reduced-precision one
+  setup(plan.step1, 1, PATH_F64, !packed);
+  setup(plan.step4, 4, PATH_F64, !packed);
+  if (packed) {
+    setup(plan.step1p, 1, gemm_path(prec), true);
+    setup(plan.step4p, 4, gemm_path(prec), true);
+    tab.upload(c, {&plan.step1, &plan.step4, &plan.step1p, &plan.step4p}, {&plan.mpo},
+               {&plan.mpop}, {&plan.Lp, &plan.Rp, &plan.Xp});
+  } else {
+    tab.upload(c, {&plan.step1, &plan.step4}, {&plan.mpo});
+  }
   tuned = !tune;
-  tab.upload(c, {&plan.step1, &plan.step4}, {&plan.mpo});
   L_ext = L.extent;
   R_ext = R.extent;
 }
@@ -331,16 +424,15 @@ void HeffOp::bind_envs(const void* lre, const void* lim, const void* rre, const 
   Ctx& c = *ctx;
   L_re = static_cast<const double*>(lre); L_im = static_cast<const double*>(lim);
   R_re = static_cast<const double*>(rre); R_im = static_cast<const double*>(rim);
-  if (precision != TNT_FP64) {
-    c.ws[2].ensure(&c.pool, std::max<int64_t>(1, 2 * L_ext) * sizeof(float));
-    c.ws[3].ensure(&c.pool, std::max<int64_t>(1, 2 * R_ext) * sizeof(float));
-    float* lf = c.ws[2].as<float>();
-    float* rf = c.ws[3].as<float>();
-    launch_convert(L_re, ET_F64, lf, ET_F32, L_ext, c.stream);
-    launch_convert(L_im, ET_F64, lf + L_ext, ET_F32, L_ext, c.stream);
-    launch_convert(R_re, ET_F64, rf, ET_F32, R_ext, c.stream);
-    launch_convert(R_im, ET_F64, rf + R_ext, ET_F32, R_ext, c.stream);
-  }
+  if (!plan.packed) return;
+  const PackFmt f = fmt();
+  const int64_t pb = (int64_t)pack_planes(f) * pack_elem_bytes(f);
+  c.ws[2].ensure(&c.pool, std::max<int64_t>(16, plan.Lp.elems * pb));
+  c.ws[3].ensure(&c.pool, std::max<int64_t>(16, plan.Rp.elems * pb));
+  const DevTables::P& lp = tab.p[0];
+  const DevTables::P& rp = tab.p[1];
+  launch_pack(lp.tasks, lp.tiles, lp.ntiles, L_re, L_im, c.ws[2].ptr, lp.elems, f, c.stream);
+  launch_pack(rp.tasks, rp.tiles, rp.ntiles, R_re, R_im, c.ws[3].ptr, rp.elems, f, c.stream);
 }
 
 void HeffOp::launch_step(int step, int v, bool fp64, const double* xre, const double* xim,
@@ -357,60 +449,86 @@ void HeffOp::launch_step(int step, int v, bool fp64, const double* xre, const do
                        R_im, ET_F64, yre, yim, ET_F64);
     return;
   }
-  float* a = c.ws[0].as<float>();
-  float* b = c.ws[1].as<float>();
-  const float* lf = c.ws[2].as<float>();
-  const float* rf = c.ws[3].as<float>();
-  const GemmPath path = gemm_path(precision);
-  if (step == 1)
-    run_gemm_variant(c, tab.g[0], v, FORM_NN, path, lf, lf + L_ext, ET_F32, xre, xim, ET_F64, a,
-                     a + plan.t1_elems, ET_F32);
-  else
-    run_gemm_variant(c, tab.g[1], v, FORM_NT, path, b, b + plan.t3_elems, ET_F32, rf,
-                     rf + R_ext, ET_F32, yre, yim, ET_F64);
+  // packed path: step 1 Lp . Xp^T -> FP32 T1 slabs; step 4 T3p . Rp^T -> y
+  const DevTables::G& g = tab.g[step == 1 ? 2 : 3];
+  if (v < 0 || v >= g.nvar) fail(TNT_E_STATE, "tile-table variant out of range");
+  float* t1 = c.ws[0].as<float>();
+  PackedLaunch L{};
+  L.tasks = g.tasks;
+  L.segs = g.segs;
+  L.tiles = g.tiles[v];
+  L.ntiles = g.ntiles[v];
+  L.tile_cfg = g.cfg[v];
+  L.fmt = fmt();
+  if (step == 1) {
+    L.a = c.ws[2].ptr; L.a_plane = plan.Lp.elems;
+    L.b = c.ws[4].ptr; L.b_plane = plan.Xp.elems;
+    L.c_re = t1; L.c_im = t1 + plan.t1_elems; L.c_t = ET_F32;
+  } else {
+    L.a = c.ws[1].ptr; L.a_plane = plan.t3p_elems;
+    L.b = c.ws[3].ptr; L.b_plane = plan.Rp.elems;
+    L.c_re = yre; L.c_im = yim; L.c_t = ET_F64;
+  }
+  if (!launch_packed_gemm(L, c.stream))
+    fail(TNT_E_STATE, "packed GEMM variant not available (tile shape " + std::to_string(g.cfg[v]) +
+                          ")");
 }
 
 void HeffOp::apply(const double* xre, const double* xim, double* yre, double* yim, int prec,
                    bool timed) {
   Ctx& c = *ctx;
-  const bool fp64 = prec == TNT_FP64 || precision == TNT_FP64;
-  const size_t es = fp64 ? sizeof(double) : sizeof(float);
-  c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * es);
-  c.ws[1].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t3_elems) * es);
-  if (!tuned && !fp64) autotune(xre, xim, yre, yim, prec);
-  if (!tuned && fp64 && precision == TNT_FP64) autotune(xre, xim, yre, yim, prec);
   auto mark = [&](int i) {
     if (timed) TNT_HIP(hipEventRecord(c.ev[i], c.stream));
   };
-  // FP64 (also the refinement matvec of a reduced-precision operator, on
-  // FP64 environments)
-  const GemmPath p = fp64 ? PATH_F64 : gemm_path(precision);
-  const int v1 = valid_variant(tab.g[0], p), v4 = valid_variant(tab.g[1], p);
-  mark(2);
-  launch_step(1, v1, fp64, xre, xim, yre, yim);
-  mark(3);
-  if (fp64)
+  // FP64: the FP64 operator, or the refinement matvec of a reduced-precision
+  // operator (on the FP64 environments)
+  if (prec == TNT_FP64 || !plan.packed) {
+    c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(double));
+    c.ws[1].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(double));
+    if (!tuned && !plan.packed) autotune(xre, xim, yre, yim, prec);
+    const int v1 = valid_variant(tab.g[0], PATH_F64), v4 = valid_variant(tab.g[1], PATH_F64);
+    mark(2);
+    launch_step(1, v1, true, xre, xim, yre, yim);
+    mark(3);
     run_comb(c, tab.c[0], c.ws[0].as<double>(), c.ws[0].as<double>() + plan.t1_elems,
              c.ws[1].as<double>(), c.ws[1].as<double>() + plan.t3_elems, ET_F64);
-  else
-    run_comb(c, tab.c[0], c.ws[0].as<float>(), c.ws[0].as<float>() + plan.t1_elems,
-             c.ws[1].as<float>(), c.ws[1].as<float>() + plan.t3_elems, ET_F32);
+    mark(4);
+    launch_step(4, v4, true, xre, xim, yre, yim);
+    mark(5);
+    return;
+  }
+  const PackFmt f = fmt();
+  const int64_t pb = (int64_t)pack_planes(f) * pack_elem_bytes(f);
+  c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(float));
+  c.ws[1].ensure(&c.pool, std::max<int64_t>(16, plan.t3p_elems * pb));
+  c.ws[4].ensure(&c.pool, std::max<int64_t>(16, plan.Xp.elems * pb));
+  const DevTables::P& xp = tab.p[2];
+  launch_pack(xp.tasks, xp.tiles, xp.ntiles, xre, xim, c.ws[4].ptr, xp.elems, f, c.stream);
+  if (!tuned) autotune(xre, xim, yre, yim, prec);
+  const DevTables::CP& cp = tab.cp[0];
+  mark(2);
+  launch_step(1, tab.g[2].sel, false, xre, xim, yre, yim);
+  mark(3);
+  launch_combine_packed(cp.tasks, cp.terms, cp.chunks, cp.nchunks, c.ws[0].as<float>(),
+                        c.ws[0].as<float>() + plan.t1_elems, c.ws[1].ptr, plan.t3p_elems, f,
+                        c.stream);
   mark(4);
-  launch_step(4, v4, fp64, xre, xim, yre, yim);
+  launch_step(4, tab.g[3].sel, false, xre, xim, yre, yim);
   mark(5);
 }
 
 void HeffOp::autotune(const double* xre, const double* xim, double* yre, double* yim, int prec) {
   Ctx& c = *ctx;
   tuned = true;
-  const bool fp64 = precision == TNT_FP64;
+  const bool fp64 = !plan.packed;
   const GemmPath path = gemm_path(precision);
   (void)prec;
   // candidates run on the operator's real operands; step 4 reads whatever
   // the slab workspace holds (in bounds; values do not affect timing) and
   // the caller's apply overwrites every output afterwards
   for (int step : {1, 4}) {
-    DevTables::G& g = tab.g[step == 1 ? 0 : 1];
+    const int gi = (fp64 ? 0 : 2) + (step == 1 ? 0 : 1);
+    DevTables::G& g = tab.g[gi];
     if (g.nvar <= 1) continue;
     int best = g.sel;
     float best_ms = 1e30f;
@@ -430,7 +548,9 @@ void HeffOp::autotune(const double* xre, const double* xim, double* yre, double*
       }
     }
     g.sel = best;
-    c.tune_cache[tune_bucket(step == 1 ? plan.step1 : plan.step4, path, step)] = g.cfg[best];
+    const HostGemm& h = fp64 ? (step == 1 ? plan.step1 : plan.step4)
+                             : (step == 1 ? plan.step1p : plan.step4p);
+    c.tune_cache[tune_bucket(h, path, step)] = g.cfg[best];
   }
 }
 

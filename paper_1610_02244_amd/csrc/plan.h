@@ -58,6 +58,32 @@ struct HostComb {
   void finalize();
 };
 
+// Host task list of one packed MPO combination (kernels.h CombPTask).
+struct HostCombP {
+  std::vector<CombPTask> tasks;
+  std::vector<CombTerm> terms;
+  std::vector<int2> chunks;
+  void add_task(int64_t dst_off, int rows, int cols, int dld) {
+    tasks.push_back(CombPTask{dst_off, rows, cols, dld, (int)terms.size(), 0, 0});
+  }
+  void add_term(int64_t src_off, double coef) {
+    terms.push_back(CombTerm{src_off, coef});
+    tasks.back().nterm++;
+  }
+  void finalize();
+};
+
+// Pack tasks of one packed operand (kernels.h PackTask) and their tiles.
+struct HostPack {
+  std::vector<PackTask> tasks;
+  std::vector<int2> tiles;
+  int64_t elems = 0;  // plane stride in elements (a multiple of 8)
+  // destination block rows x cols (row stride pad8(cols)) from a source
+  // block at src_off with leading dimension sld, read transposed if `trans`;
+  // returns the destination offset
+  int64_t add(int64_t src_off, int rows, int cols, int sld, bool trans);
+};
+
 // Device copy of several host task lists in one allocation.
 struct DevTables {
   DevBuf buf;
@@ -74,10 +100,16 @@ struct DevTables {
     int sel = 0;
   };
   struct C { const CombTask* tasks; const CombTerm* terms; const int2* chunks; int nchunks; };
+  struct CP { const CombPTask* tasks; const CombTerm* terms; const int2* chunks; int nchunks; };
+  struct P { const PackTask* tasks; const int2* tiles; int ntiles; int64_t elems; };
   std::vector<G> g;
   std::vector<C> c;
+  std::vector<CP> cp;
+  std::vector<P> p;
   void upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
-              const std::vector<const HostComb*>& cs);
+              const std::vector<const HostComb*>& cs,
+              const std::vector<const HostCombP*>& cps = {},
+              const std::vector<const HostPack*>& pks = {});
 };
 
 void run_gemm(Ctx& ctx, const DevTables::G& g, GemmForm form, GemmPath path,
@@ -106,17 +138,26 @@ struct HeffPlan {
   HostGemm step1, step4;
   HostComb mpo;
   int64_t t1_elems = 0, t3_elems = 0;
+  // reduced-precision path on packed operands (built when `packed`):
+  // step 1 = Lp . Xp^T (Xp: theta packed transposed) into FP32 T1 slabs,
+  // the combination writes packed T3 slabs, step 4 = T3p . Rp^T
+  bool packed = false;
+  HostGemm step1p, step4p;
+  HostCombP mpop;
+  HostPack Lp, Rp, Xp;
+  int64_t t3p_elems = 0;
   int64_t flops_step1 = 0, flops_mpo = 0, flops_step4 = 0;
   int64_t flops() const { return flops_step1 + flops_mpo + flops_step4; }
   std::vector<std::array<int, 3>> out_keys;
 };
 
 HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const EnvH& R,
-                         const ThetaH& th, const ThetaH& out);
+                         const ThetaH& th, const ThetaH& out, bool packed);
 
 // A ready-to-apply H_eff operator on one bond: the plan and its device
-// tables.  Intermediate slabs and FP32 environment copies live in the
-// context's shared workspaces (Ctx::ws), sized on use.
+// tables.  Intermediate slabs and packed operand copies live in the
+// context's shared workspaces (Ctx::ws), sized on use: ws[0] T1 slabs,
+// ws[1] T3 slabs, ws[2] / ws[3] packed L / R, ws[4] packed theta.
 struct HeffOp {
   Ctx* ctx = nullptr;
   HeffPlan plan;
@@ -129,8 +170,9 @@ struct HeffOp {
   // plan + device tables + workspaces for these block structures
   void build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const EnvH& R,
              const ThetaH& th, const ThetaH& out, int prec);
-  // point at the environments' FP64 planes (and refresh the FP32 copies)
+  // point at the environments' FP64 planes (and refresh the packed copies)
   void bind_envs(const void* lre, const void* lim, const void* rre, const void* rim);
+  PackFmt fmt() const { return precision == TNT_BF16X3 ? PK_BF16X3 : PK_F32; }
   // y = H_eff x with x, y in the theta / out layouts given at build (FP64 planes).
   // With `timed`, events ev[2]/ev[3] bracket the step-1 GEMM launch and
   // ev[4]/ev[5] the step-4 launch.
