@@ -9,10 +9,11 @@ algorithmic flops of every matvec the sweeps performed / timed wall time.
 
 Default workload: L = 32, N = 32, nmax = 4 (d = 5), J = 1, U = 4, chi = 256
 (seeded random MPS), matvecs on FP32 MFMA; Krylov vectors, SVD, energies and
-environments in FP64.  Also reported: the same sweeps on the FP64 GPU path,
-single-matvec rates at the middle bond, the energy error against the
-oracle's stored sweep energies, the grouped-GEMM roofline figure and the
-CPU oracle timed on a bounded sample.
+environments in FP64.  Also reported: the same sweeps on the FP64 and the
+BF16x3 GPU paths, single-matvec rates at the middle bond of this chain and
+of the chi = 1024 chain (L = 64), the energy errors against the oracle's
+stored sweep energies, the grouped-GEMM roofline figure and the CPU oracle
+timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2]
 """
@@ -91,8 +92,10 @@ def run_sweeps(tnt, torch, mps, env, spec, precision, warmup, steps, roctx=None)
     return res, dt
 
 
-def matvec_rates(tnt, B, torch, spec, reps=20):
-    """Single H_eff applications at the middle bond (seeded synthetic L, R, theta)."""
+def matvec_rates(tnt, B, torch, spec, precs=("fp64", "fp32", "bf16x3"), reps=20):
+    """Single H_eff applications at the middle bond (seeded synthetic L, R,
+    theta): `reps` back-to-back tnt_heff2_apply calls between two events on
+    the library's stream (torch's current stream), per precision."""
     import synth
     W, qw = tnt.bose_hubbard_mpo(spec.nmax, spec.J, spec.U, spec.mu)
     left, right, Le, Re, th = synth.middle_bond_inputs(spec, qw)
@@ -101,21 +104,22 @@ def matvec_rates(tnt, B, torch, spec, reps=20):
     out = tnt.theta_like(td)
     flops, parts = tnt.heff2_flops(Ld, mpo, mpo, Rd, td)
     rates = {}
-    for prec in ("fp64", "fp32"):
-        for _ in range(3):
+    for prec in precs:
+        for _ in range(3):   # plan, tile-shape tuning, warm caches
             tnt.heff2_apply(Ld, mpo, mpo, Rd, td, out, prec)
-        ts = []
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
             tnt.heff2_apply(Ld, mpo, mpo, Rd, td, out, prec)
-            e1.record()
-            e1.synchronize()
-            ts.append(e0.elapsed_time(e1) * 1e-3)
-        ts.sort()
-        med = ts[len(ts) // 2]
-        rates[prec] = {"median_s": med, "tflops": flops / med / 1e12}
-    return {"flops": int(flops), "parts": [int(x) for x in parts], **rates}
+        e1.record()
+        e1.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / reps
+        rates[prec] = {"s": t, "tflops": flops / t / 1e12,
+                       "frac_fp32_peak": flops / t / 1e12 / PEAK["fp32"]}
+    del Ld, Rd, td, out
+    return {"chi": spec.chi, "bond": f"middle bond of L={spec.L}",
+            "flops": int(flops), "parts": [int(x) for x in parts], **rates}
 
 
 def cpu_baseline(spec, budget_s=12.0):
@@ -150,7 +154,7 @@ def traffic_for(precision):
     """HBM bytes per grouped-GEMM launch from the committed PMC summary, if the
     kernel source is unchanged since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "gemm_traffic.json")
-    src = os.path.join(ROOT, "paper_1610_02244_amd", "csrc", "gemm.hip")
+    src = os.path.join(ROOT, "paper_1610_02244_amd", "csrc", "gemm_packed.hip")
     try:
         with open(path) as f:
             t = json.load(f)
@@ -194,11 +198,11 @@ def summarize_trace(root):
                 st[0] += 1
                 st[1] += e - s
     top = sorted(stats.items(), key=lambda kv: -kv[1][1])
-    gemm = [(k, v) for k, v in stats.items() if "grouped_gemm_kernel<float" in k]
+    gemm = [(k, v) for k, v in stats.items() if "packed_gemm_kernel<0" in k]
     gc = sum(v[0] for _, v in gemm)
     gt = sum(v[1] for _, v in gemm)
     return {"range_ns": t1 - t0, "kernel_ns_total": sum(v[1] for v in stats.values()),
-            "fp32_grouped_gemm": {"launches": gc, "total_ns": gt,
+            "fp32_packed_gemm": {"launches": gc, "total_ns": gt,
                                   "avg_ns": gt / gc if gc else None},
             "top": [{"kernel": k[:160], "calls": v[0], "total_ms": v[1] / 1e6,
                      "avg_us": v[1] / v[0] / 1e3} for k, v in top[:25]]}
@@ -224,6 +228,9 @@ def main():
     ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path sweeps")
+    ap.add_argument("--no-bf16x3", action="store_true", help="skip the BF16x3-path sweeps")
+    ap.add_argument("--no-chi1024", action="store_true",
+                    help="skip the single-matvec timing at the chi = 1024 middle bond")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="print timed-region kernel statistics of a rocprofv3 CSV trace and exit")
@@ -270,11 +277,26 @@ def main():
                 "speedup_fp32_over_fp64_sweep": (dt64 / dt)}
         del env64, mps64
 
+    bf = None
+    if not args.no_bf16x3 and args.precision != "bf16x3":
+        mpsb, envb = make_chain(tnt, B, spec)
+        rb, dtb = run_sweeps(tnt, torch, mpsb, envb, spec, "bf16x3", args.warmup, args.steps)
+        fb = sum(r["matvec_flops"] for r in rb)
+        bf = {"sweep_s": dtb / args.steps, "matvec_tflops": fb / dtb / 1e12,
+              "matvec_device_s": sum(r["seconds_matvec"] for r in rb) / args.steps,
+              "energy": rb[-1]["energy"],
+              "rel_err_vs_oracle": (abs(rb[-1]["energy"] - e_ref) / abs(e_ref)) if e_ref else None}
+        del envb, mpsb
+
     mv = matvec_rates(tnt, B, torch, spec)
+    mv_big = None
+    if not args.no_chi1024 and spec.chi < 1024:
+        mv_big = matvec_rates(tnt, B, torch, synth.CONFIGS["cfg3"])
     peak = PEAK[args.precision]
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic_for(args.precision),
-            "kernel": f"grouped_gemm_kernel ({args.precision}, H_eff steps 1 and 4)",
+            "kernel": ("grouped_gemm_kernel (FP64)" if args.precision == "fp64" else
+                       f"packed_gemm_kernel ({args.precision})") + ", H_eff steps 1 and 4",
             "launches": int(launches),
             "avg_launch_s": gemm_s / launches if launches else None,
             "avg_flops_per_launch": gemm_flops / launches if launches else None}
@@ -299,7 +321,8 @@ def main():
                    "rel_err_vs_oracle": (abs(e_final - e_ref) / abs(e_ref)) if e_ref else None,
                    "max_residual": max(r["max_residual"] for r in res),
                    "max_trunc_eps": max(r["max_eps"] for r in res)},
-        "fp64_path": fp64, "single_matvec_middle_bond": mv,
+        "fp64_path": fp64, "bf16x3_path": bf, "single_matvec_middle_bond": mv,
+        "single_matvec_chi1024": mv_big,
     }
     print(json.dumps(line), flush=True)
 

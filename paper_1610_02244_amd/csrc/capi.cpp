@@ -10,8 +10,49 @@
 namespace tnt {
 
 struct PlanCache {
+  // operators by the hash of their parsed block structures
   std::unordered_map<uint64_t, std::shared_ptr<HeffOp>> heff;
+  // the same operators by the hash of the raw host descriptors they were
+  // parsed and validated from (skips the parse for a repeated call)
+  std::unordered_map<uint64_t, std::shared_ptr<HeffOp>> raw;
 };
+
+// Word-wise hash of the raw host metadata of an H_eff call: every field the
+// parse reads (labels, extents, offsets, capacities, dtypes, MPO arrays).
+static void raw_add(uint64_t& h, const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  auto mix = [&](uint64_t w) {
+    h ^= w + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
+    h *= 0xff51afd7ed558ccdULL;
+  };
+  size_t i = 0;
+  for (; i + 8 <= n; i += 8) {
+    uint64_t w;
+    memcpy(&w, b + i, 8);
+    mix(w);
+  }
+  uint64_t w = 0;
+  if (i < n) memcpy(&w, b + i, n - i);
+  mix(w ^ (uint64_t)n);
+}
+static void raw_btensor(uint64_t& h, const tnt_btensor* t) {
+  if (!t || t->nblocks < 0 || t->rank < 0 || (t->nblocks > 0 && (!t->qn || !t->extent || !t->offset)))
+    fail(TNT_E_ARG, "invalid block-tensor descriptor");
+  const int32_t hdr[3] = {t->rank, t->nblocks, t->dtype};
+  raw_add(h, hdr, sizeof(hdr));
+  raw_add(h, &t->capacity, sizeof(t->capacity));
+  raw_add(h, t->qn, sizeof(int32_t) * (size_t)t->nblocks * t->rank);
+  raw_add(h, t->extent, sizeof(int32_t) * (size_t)t->nblocks * t->rank);
+  raw_add(h, t->offset, sizeof(int64_t) * (size_t)t->nblocks);
+}
+static void raw_mpo(uint64_t& h, const tnt_mpo_site* m) {
+  if (!m || !m->bond_charge || !m->W || m->d <= 0 || m->D <= 0 || m->d > 64 || m->D > 64)
+    fail(TNT_E_ARG, "invalid MPO descriptor");
+  const int32_t hdr[2] = {m->d, m->D};
+  raw_add(h, hdr, sizeof(hdr));
+  raw_add(h, m->bond_charge, sizeof(int32_t) * m->D);
+  raw_add(h, m->W, sizeof(double) * (size_t)m->D * m->D * m->d * m->d);
+}
 
 void destroy_blas(void* h);  // svd.cpp
 
@@ -99,6 +140,7 @@ std::shared_ptr<HeffOp> cached_heff(Ctx& c, const HeffArgs& a, int prec) {
   if (c.plans->heff.size() >= 1024) {
     TNT_HIP(hipStreamSynchronize(c.stream));
     c.plans->heff.clear();
+    c.plans->raw.clear();
   }
   auto op = std::make_shared<HeffOp>();
   op->build(c, a.L, a.w1, a.w2, a.R, a.th, a.out, prec);
@@ -159,6 +201,7 @@ tnt_status tnt_ctx_set_autotune(tnt_ctx ctx, int32_t on) {
   if (c.plans) {
     TNT_HIP(hipStreamSynchronize(c.stream));
     c.plans->heff.clear();
+    c.plans->raw.clear();
   }
   TNT_API_END
 }
@@ -169,11 +212,29 @@ tnt_status tnt_heff2_apply(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_site
   TNT_API_BEGIN(ctx)
   check_precision(precision);
   if (!out) fail(TNT_E_ARG, "null out");
-  HeffArgs a = parse_heff_args(L, W1, W2, R, theta, out);
-  if (L->dtype != TNT_DT_F64 || R->dtype != TNT_DT_F64 || theta->dtype != TNT_DT_F64 ||
-      out->dtype != TNT_DT_F64)
-    fail(TNT_E_ARG, "L, R, theta and out must be FP64 planes");
-  auto op = cached_heff(c, a, precision);
+  uint64_t rh = 0x243f6a8885a308d3ULL ^ (uint64_t)precision;
+  raw_btensor(rh, L);
+  raw_btensor(rh, R);
+  raw_btensor(rh, theta);
+  raw_btensor(rh, out);
+  raw_mpo(rh, W1);
+  raw_mpo(rh, W2);
+  if (!c.plans) c.plans = new PlanCache();
+  std::shared_ptr<HeffOp> op;
+  auto hit = c.plans->raw.find(rh);
+  if (hit != c.plans->raw.end()) {
+    op = hit->second;  // the same descriptors were parsed and validated before
+    for (const tnt_btensor* t : {L, R, theta, (const tnt_btensor*)out})
+      if (!t->re || !t->im) fail(TNT_E_ARG, "null plane");
+  } else {
+    HeffArgs a = parse_heff_args(L, W1, W2, R, theta, out);
+    if (L->dtype != TNT_DT_F64 || R->dtype != TNT_DT_F64 || theta->dtype != TNT_DT_F64 ||
+        out->dtype != TNT_DT_F64)
+      fail(TNT_E_ARG, "L, R, theta and out must be FP64 planes");
+    op = cached_heff(c, a, precision);
+    if (c.plans->raw.size() >= 1024) c.plans->raw.clear();
+    c.plans->raw[rh] = op;
+  }
   op->bind_envs(L->re, L->im, R->re, R->im);
   op->apply(static_cast<const double*>(theta->re), static_cast<const double*>(theta->im),
             static_cast<double*>(out->re), static_cast<double*>(out->im), precision);

@@ -157,13 +157,16 @@ def test_heff_full_size_sampled(tnt):
 
 
 def test_heff_rejects_charge_violation(tnt):
+    """A descriptor edited in place after a successful call is parsed again
+    (the library caches operators by descriptor content, not by address)."""
     from paper_1610_02244_amd import binding as B
     left, right, nmax = CASES["tiny"]
     W, qw, Le, Re, th = make_case(left, right, nmax, seed=1)
     mpo = gpu_mpo(tnt, W)
     Ld, Rd, td = tnt.env(Le, qw), tnt.env(Re, qw), tnt.theta(th)
+    ok = tnt.theta_like(td)
+    tnt.heff2_apply(Ld, mpo, mpo, Rd, td, ok, "fp32")
     td.qn[3] += 1
-    out = tnt.theta_like(tnt.theta(th))
     with pytest.raises(B.TntError) as ei:
-        tnt.heff2_apply(Ld, mpo, mpo, Rd, td, out, "fp64")
+        tnt.heff2_apply(Ld, mpo, mpo, Rd, td, ok, "fp32")
     assert ei.value.code == -3
