@@ -88,6 +88,15 @@ int64_t tnt_pool_bytes(tnt_ctx ctx);
  * tuning (the planner's default shape is used) and clears the cache. */
 tnt_status tnt_ctx_set_autotune(tnt_ctx ctx, int32_t on);
 
+/* HIP-graph execution of the Lanczos recurrence (off by default).  With
+ * on = 1, tnt_lanczos_ground and the sweeps record the k matvec +
+ * re-orthogonalisation steps of a bond once into a HIP graph (kept with the
+ * cached operator, re-recorded when a workspace it uses was reallocated)
+ * and replay it with one launch; results are identical to the eager path.
+ * The sweeps then report no per-matvec device times (seconds_matvec,
+ * seconds_gemm and gemm_launches stay 0).  Errors: TNT_E_ARG. */
+tnt_status tnt_ctx_set_graphs(tnt_ctx ctx, int32_t on);
+
 /* ------------------------------------------------------------------------
  * Block tensors (appendix A.1.1)
  *

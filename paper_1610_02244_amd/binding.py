@@ -91,6 +91,7 @@ SIGNATURES = {
     "tnt_sync": (C.c_int32, [P]),
     "tnt_pool_bytes": (C.c_int64, [P]),
     "tnt_ctx_set_autotune": (C.c_int32, [P, C.c_int32]),
+    "tnt_ctx_set_graphs": (C.c_int32, [P, C.c_int32]),
     "tnt_mpo_bose_hubbard": (C.c_int32, [C.c_int32, C.c_double, C.c_double, C.c_double, F64P,
                                          I32P]),
     "tnt_heff2_apply": (C.c_int32, [P, C.POINTER(BTensor), C.POINTER(MpoSite),
@@ -316,6 +317,9 @@ class Tnt:
 
     def set_autotune(self, on: bool):
         self._check("tnt_ctx_set_autotune", self.lib.tnt_ctx_set_autotune(self.ctx, int(on)))
+
+    def set_graphs(self, on: bool):
+        self._check("tnt_ctx_set_graphs", self.lib.tnt_ctx_set_graphs(self.ctx, int(on)))
 
     def heff2_apply(self, L, W1, W2, R, theta, out, precision="fp64"):
         code = self.lib.tnt_heff2_apply(self.ctx, L.ref, W1.ref, W2.ref, R.ref, theta.ref,

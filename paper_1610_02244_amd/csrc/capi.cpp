@@ -64,6 +64,9 @@ Ctx::~Ctx() {
   if (blas) destroy_blas(blas);
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : step_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (gstream) (void)hipStreamDestroy(gstream);
   for (int i = 0; i < kSide; ++i) {
     if (side[i]) (void)hipStreamSynchronize(side[i]);
     if (side_blas[i]) destroy_blas(side_blas[i]);
@@ -203,6 +206,12 @@ tnt_status tnt_ctx_set_autotune(tnt_ctx ctx, int32_t on) {
     c.plans->heff.clear();
     c.plans->raw.clear();
   }
+  TNT_API_END
+}
+
+tnt_status tnt_ctx_set_graphs(tnt_ctx ctx, int32_t on) {
+  TNT_API_BEGIN(ctx)
+  c.graphs = on ? 1 : 0;
   TNT_API_END
 }
 

@@ -90,6 +90,8 @@ struct Ctx {
   void* blas = nullptr;    // rocblas_handle, created on first SVD
   PlanCache* plans = nullptr;
   hipEvent_t ev[8] = {};
+  // per-step timing events of the Lanczos recurrence (grown on demand)
+  std::vector<hipEvent_t> step_ev;
   int num_cu = 256;
   // shared H_eff workspaces (one operator runs at a time per context):
   // 0 = L.theta slabs, 1 = MPO-combined slabs, 2 / 3 = packed L / R copies,
@@ -99,6 +101,11 @@ struct Ctx {
   // run independent per-sector dense factorizations concurrently
   // tile-shape decisions of the autotuner per shape bucket (0 = tuning off)
   int autotune = 1;
+  // Lanczos recurrence replayed from a HIP graph (tnt_ctx_set_graphs); the
+  // recording runs on a stream of its own (the context's stream may be the
+  // null stream, which cannot be recorded)
+  int graphs = 0;
+  hipStream_t gstream = nullptr;
   std::map<uint64_t, int> tune_cache;
   static constexpr int kSide = 8;
   hipStream_t side[kSide] = {};

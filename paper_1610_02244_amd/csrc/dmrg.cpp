@@ -437,7 +437,8 @@ void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats&
       K.reserve(c, p.lanczos.kmax, th.elems);
       Timers tm;
       const double tl0 = now_s();
-      LanczosOut lo = lanczos_run(c, *op, K, theta.as<double>(), p.lanczos, &tm);
+      LanczosOut lo =
+          lanczos_run(c, *op, K, theta.as<double>(), p.lanczos, c.graphs ? nullptr : &tm);
       const double tl1 = now_s();
       st.t_matvec += tm.matvec_s;
       st.t_lanczos += (tl1 - tl0) - tm.matvec_s;

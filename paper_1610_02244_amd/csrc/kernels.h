@@ -175,6 +175,13 @@ void launch_axpy2(const double* v1, const double* a_dev, const double* v0,
 // dst = src / sqrt(*nrm2_dev)
 void launch_normalize_copy(const double* src, double* dst, int64_t n, const double* nrm2_dev,
                            hipStream_t s);
+// dst = src * (*scale_dev)
+void launch_scale_copy(const double* src, double* dst, int64_t n, const double* scale_dev,
+                       hipStream_t s);
+// beta = sqrt(*nrm2); scale = 1 / beta, or 0 at breakdown (beta <= tol *
+// max(1, |*alpha0|), or not finite); one thread
+void launch_lanczos_beta(const double* nrm2_dev, const double* alpha0_dev, double tol,
+                         double* beta_dev, double* scale_dev, hipStream_t s);
 // out = sum_i y_i V_i (real y on the host copy uploaded to y_dev)
 void launch_combine_basis(const double* V, int64_t ld, int k, const double* y_dev,
                           double* out, int64_t n, hipStream_t s);

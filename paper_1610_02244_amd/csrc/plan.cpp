@@ -474,11 +474,35 @@ void HeffOp::launch_step(int step, int v, bool fp64, const double* xre, const do
                           ")");
 }
 
+HeffOp::~HeffOp() {
+  if (graph.exec) (void)hipGraphExecDestroy(graph.exec);
+}
+
+void HeffOp::prepare(const double* xre, const double* xim, double* yre, double* yim, int prec) {
+  Ctx& c = *ctx;
+  if (prec == TNT_FP64 || !plan.packed) {
+    c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(double));
+    c.ws[1].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(double));
+    if (!tuned && !plan.packed) autotune(xre, xim, yre, yim, prec);
+    return;
+  }
+  const PackFmt f = fmt();
+  const int64_t pb = (int64_t)pack_planes(f) * pack_elem_bytes(f);
+  c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(float));
+  c.ws[1].ensure(&c.pool, std::max<int64_t>(16, plan.t3p_elems * pb));
+  c.ws[4].ensure(&c.pool, std::max<int64_t>(16, plan.Xp.elems * pb));
+  if (!tuned) {
+    const DevTables::P& xp = tab.p[2];
+    launch_pack(xp.tasks, xp.tiles, xp.ntiles, xre, xim, c.ws[4].ptr, xp.elems, f, c.stream);
+    autotune(xre, xim, yre, yim, prec);
+  }
+}
+
 void HeffOp::apply(const double* xre, const double* xim, double* yre, double* yim, int prec,
-                   bool timed) {
+                   const hipEvent_t* tev) {
   Ctx& c = *ctx;
   auto mark = [&](int i) {
-    if (timed) TNT_HIP(hipEventRecord(c.ev[i], c.stream));
+    if (tev) TNT_HIP(hipEventRecord(tev[i - 2], c.stream));
   };
   // FP64: the FP64 operator, or the refinement matvec of a reduced-precision
   // operator (on the FP64 environments)

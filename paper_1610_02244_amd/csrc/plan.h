@@ -174,10 +174,21 @@ struct HeffOp {
   void bind_envs(const void* lre, const void* lim, const void* rre, const void* rim);
   PackFmt fmt() const { return precision == TNT_BF16X3 ? PK_BF16X3 : PK_F32; }
   // y = H_eff x with x, y in the theta / out layouts given at build (FP64 planes).
-  // With `timed`, events ev[2]/ev[3] bracket the step-1 GEMM launch and
-  // ev[4]/ev[5] the step-4 launch.
+  // With `tev` (4 events), tev[0]/tev[1] bracket the step-1 GEMM launch and
+  // tev[2]/tev[3] the step-4 launch.
   void apply(const double* xre, const double* xim, double* yre, double* yim, int prec,
-             bool timed = false);
+             const hipEvent_t* tev = nullptr);
+  // Everything apply may need before it can run without host interaction
+  // (workspaces sized, tile shapes tuned), so that a sequence of applies can
+  // be captured into a HIP graph.
+  void prepare(const double* xre, const double* xim, double* yre, double* yim, int prec);
+  // Captured Lanczos recurrence of this operator (lanczos.cpp), valid while
+  // every buffer it references keeps its address.
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> key;
+  } graph;
+  ~HeffOp();
   // Pick the tile shape of each grouped GEMM by timing every candidate on
   // (x -> y) (results do not depend on the shape: every shape sums K in the
   // same order); decisions are cached per shape bucket in the context.

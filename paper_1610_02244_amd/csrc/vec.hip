@@ -265,6 +265,40 @@ void launch_normalize_copy(const double* src, double* dst, int64_t n, const doub
                      2 * n, nrm2_dev);
 }
 
+// dst = src * (*scale)
+__global__ void scale_copy_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                  int64_t n2, const double* __restrict__ scale) {
+  const double f = *scale;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i] * f;
+}
+
+void launch_scale_copy(const double* src, double* dst, int64_t n, const double* scale_dev,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(scale_copy_kernel, dim3(grid_for(2 * n)), dim3(256), 0, s, src, dst, 2 * n,
+                     scale_dev);
+}
+
+// beta = sqrt(|w|^2); the next basis vector is w / beta unless beta falls to
+// the breakdown tolerance tol * max(1, |alpha_0|) (or is not finite): then
+// its scale is 0 and every later Krylov vector stays zero.
+__global__ void lanczos_beta_kernel(const double* __restrict__ nrm2,
+                                    const double* __restrict__ alpha0, double tol,
+                                    double* __restrict__ beta, double* __restrict__ scale) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double b = sqrt(*nrm2);
+  *beta = b;
+  const double thr = tol * fmax(1.0, fabs(*alpha0));
+  *scale = (b > thr && b < INFINITY) ? 1.0 / b : 0.0;
+}
+
+void launch_lanczos_beta(const double* nrm2_dev, const double* alpha0_dev, double tol,
+                         double* beta_dev, double* scale_dev, hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_beta_kernel, dim3(1), dim3(64), 0, s, nrm2_dev, alpha0_dev, tol,
+                     beta_dev, scale_dev);
+}
+
 __global__ void combine_basis_kernel(const double* __restrict__ V, int64_t ld, int k,
                                      const double* __restrict__ y, double* __restrict__ out,
                                      int64_t n2) {

@@ -80,6 +80,21 @@ def test_sweep_fp32_cfg1(tnt, precision):
     assert rel <= 1e-9
 
 
+def test_sweep_graph_mode_matches_eager(tnt):
+    """Sweeps with the Lanczos recurrence replayed from HIP graphs reproduce
+    the eager sweeps bitwise (cfg1, FP32 matvecs)."""
+    g = golden("cfg1")
+    ref, _, _ = gpu_sweeps(tnt, g, "fp32")
+    try:
+        tnt.set_graphs(True)
+        got, _, _ = gpu_sweeps(tnt, g, "fp32")
+    finally:
+        tnt.set_graphs(False)
+    for a, b in zip(ref, got):
+        assert list(a["bond_E"]) == list(b["bond_E"])
+        assert list(a["bond_chi"]) == list(b["bond_chi"])
+
+
 def test_canonical_state_norm_and_density(tnt):
     """After a sweep the returned MPS is normalised and holds N bosons."""
     from oracle import dmrg as odmrg

@@ -87,6 +87,38 @@ def test_lanczos_fp32_energy(tnt, name, precision):
     assert rel <= 1e-5
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_lanczos_graph_replays_match_eager(tnt, precision):
+    """The recurrence replayed from a HIP graph gives bitwise the eager
+    result, on every replay (eager work and synchronisations in between)."""
+    left, right, nmax = LCASES["cfg2_like"]
+    W, qw, Le, Re, th, params = herm_case(left, right, nmax, seed=9)
+    keys = sorted(th)
+    mpo = gpu_mpo(tnt, params)
+    Ld, Rd = tnt.env(Le, qw), tnt.env(Re, qw)
+
+    def run():
+        td = tnt.theta(th, keys)
+        r = tnt.lanczos_ground(Ld, mpo, mpo, Rd, td, kmax=20, precision=precision)
+        return r, tnt.download(td)
+
+    ref, psi_ref = run()
+    try:
+        tnt.set_graphs(True)
+        for rep in range(3):
+            got, psi = run()
+            print(f"  [graph {precision}] replay {rep}: E = {got['E']:.15f}", flush=True)
+            assert got["E"] == ref["E"] and got["E_ritz"] == ref["E_ritz"]
+            assert got["steps"] == ref["steps"]
+            for k in psi_ref:
+                assert np.array_equal(psi[k], psi_ref[k])
+            tnt.heff2_apply(Ld, mpo, mpo, Rd, tnt.theta(th, keys),
+                            tnt.theta_like(tnt.theta(th, keys)), "fp64")
+            tnt.sync()
+    finally:
+        tnt.set_graphs(False)
+
+
 SCASE_L = {10: 6, 11: 17, 12: 9, 13: 2}
 SCASE_R = {12: 4, 13: 11, 14: 15, 15: 8, 16: 1}
 
