@@ -161,6 +161,17 @@ tnt_status tnt_heff2_apply(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_site
                            const tnt_mpo_site* W2, const tnt_btensor* R,
                            const tnt_btensor* theta, tnt_btensor* out, int32_t precision);
 
+/* n independent applications (arrays of n operands, each with the meaning
+ * of tnt_heff2_apply: different chains, bonds and block structures) packed
+ * into one grouped launch per contraction step.  Inputs are gathered into a
+ * batch vector and results scattered back; out[i] gets exactly what
+ * tnt_heff2_apply would write.  Blocks until the copies are done.
+ * Errors as for tnt_heff2_apply (the first failing instance decides). */
+tnt_status tnt_heff2_apply_batched(tnt_ctx ctx, int32_t n, const tnt_btensor* const* L,
+                                   const tnt_mpo_site* const* W1, const tnt_mpo_site* const* W2,
+                                   const tnt_btensor* const* R, const tnt_btensor* const* theta,
+                                   tnt_btensor* const* out, int32_t precision);
+
 /* Algorithmic FLOP count of one tnt_heff2_apply on these block structures
  * (host only, no device access).  Counting rule: a complex multiply-add is
  * 8 flops, a real-times-complex term 4 flops per element; step 1 (L.theta
@@ -183,7 +194,7 @@ int64_t tnt_heff2_flops(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt_
  * Returns TNT_W_NOCONV when residual > resid_tol (> 0) after kmax steps.
  * ------------------------------------------------------------------------ */
 typedef struct {
-  int32_t kmax;        /* Krylov steps (>= 1, <= 256)          */
+  int32_t kmax;        /* Krylov steps (1 .. 32)                */
   int32_t precision;   /* TNT_FP64 | TNT_FP32 | TNT_BF16X3      */
   double beta_tol;     /* breakdown tolerance (e.g. 1e-12)      */
   double resid_tol;    /* <= 0: never warn                      */
@@ -200,6 +211,21 @@ tnt_status tnt_lanczos_ground(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_s
                               const tnt_mpo_site* W2, const tnt_btensor* R,
                               tnt_btensor* theta, const tnt_lanczos_params* p,
                               tnt_lanczos_result* r);
+
+/* The same for n independent problems at once (different chains, bonds,
+ * block structures; arrays of n operands with the meaning above, one
+ * parameter set for all, r[n] results).  Every recurrence step applies all n
+ * operators with one grouped launch per contraction step, and the vector
+ * work (dots, re-orthogonalisation, normalisation) runs segmented per
+ * instance; each instance follows the single-problem recurrence (its own
+ * step count min(kmax, dim), breakdown, Ritz vector and FP64 refinement).
+ * Returns TNT_W_NOCONV when any instance misses resid_tol.  Errors as for
+ * tnt_lanczos_ground (the first failing instance decides). */
+tnt_status tnt_lanczos_ground_batched(tnt_ctx ctx, int32_t n, const tnt_btensor* const* L,
+                                      const tnt_mpo_site* const* W1,
+                                      const tnt_mpo_site* const* W2, const tnt_btensor* const* R,
+                                      tnt_btensor* const* theta, const tnt_lanczos_params* p,
+                                      tnt_lanczos_result* r);
 
 /* ------------------------------------------------------------------------
  * Truncated SVD of theta (appendix B.1.2).
@@ -340,6 +366,18 @@ typedef struct {
  * `mps` and `env`.  Blocks until done. */
 tnt_status tnt_dmrg_sweep(tnt_ctx ctx, tnt_mps mps, tnt_env env, const tnt_sweep_params* p,
                           tnt_sweep_result* r);
+
+/* One sweep of each of n independent chains (different L, chi, couplings):
+ * the chains advance in lockstep, one bond update per chain per step, and
+ * the Lanczos problems of all chains active at a step run as one batch
+ * (tnt_lanczos_ground_batched); theta formation, SVD-truncate and the
+ * environment update stay per chain.  p[i] and r[i] per chain (truncation
+ * and record arrays may differ; the Lanczos parameters must agree, else
+ * TNT_E_ARG).  Each chain ends exactly as tnt_dmrg_sweep would leave it,
+ * up to rounding.  The timing fields of every r[i] are totals of the whole
+ * batch.  Blocks until done. */
+tnt_status tnt_dmrg_sweep_batched(tnt_ctx ctx, int32_t n, const tnt_mps* mps, const tnt_env* env,
+                                  const tnt_sweep_params* p, tnt_sweep_result* r);
 
 #ifdef __cplusplus
 }

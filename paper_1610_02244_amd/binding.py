@@ -121,6 +121,21 @@ SIGNATURES = {
                                    C.POINTER(P)]),
     "tnt_env_destroy": (None, [P]),
     "tnt_dmrg_sweep": (C.c_int32, [P, P, P, C.POINTER(SweepParams), C.POINTER(SweepResult)]),
+    "tnt_dmrg_sweep_batched": (C.c_int32, [P, C.c_int32, C.POINTER(P), C.POINTER(P),
+                                           C.POINTER(SweepParams), C.POINTER(SweepResult)]),
+    "tnt_heff2_apply_batched": (C.c_int32, [P, C.c_int32, C.POINTER(C.POINTER(BTensor)),
+                                            C.POINTER(C.POINTER(MpoSite)),
+                                            C.POINTER(C.POINTER(MpoSite)),
+                                            C.POINTER(C.POINTER(BTensor)),
+                                            C.POINTER(C.POINTER(BTensor)),
+                                            C.POINTER(C.POINTER(BTensor)), C.c_int32]),
+    "tnt_lanczos_ground_batched": (C.c_int32, [P, C.c_int32, C.POINTER(C.POINTER(BTensor)),
+                                               C.POINTER(C.POINTER(MpoSite)),
+                                               C.POINTER(C.POINTER(MpoSite)),
+                                               C.POINTER(C.POINTER(BTensor)),
+                                               C.POINTER(C.POINTER(BTensor)),
+                                               C.POINTER(LanczosParams),
+                                               C.POINTER(LanczosResult)]),
 }
 
 
@@ -405,6 +420,64 @@ class Tnt:
     def mps(self, bonds, sites, d):
         """Upload a block MPS (bonds[0..L] sector dicts, sites[0..L-1] block dicts)."""
         return Mps(self, bonds, sites, d)
+
+    @staticmethod
+    def _ptr_array(ctype, objs):
+        arr = (C.POINTER(ctype) * len(objs))()
+        for i, o in enumerate(objs):
+            arr[i] = C.pointer(o.c)
+        return arr
+
+    def heff2_apply_batched(self, Ls, W1s, W2s, Rs, thetas, outs, precision="fp64"):
+        """n independent H_eff applications in one batch (lists of descriptors)."""
+        n = len(thetas)
+        args = [self._ptr_array(BTensor, Ls), self._ptr_array(MpoSite, W1s),
+                self._ptr_array(MpoSite, W2s), self._ptr_array(BTensor, Rs),
+                self._ptr_array(BTensor, thetas), self._ptr_array(BTensor, outs)]
+        code = self.lib.tnt_heff2_apply_batched(self.ctx, n, *args, PRECISIONS[precision])
+        return self._check("tnt_heff2_apply_batched", code)
+
+    def lanczos_ground_batched(self, Ls, W1s, W2s, Rs, thetas, kmax=20, precision="fp64",
+                               beta_tol=1e-12, resid_tol=-1.0):
+        """Batched Lanczos: one result dict per instance; thetas are updated in place."""
+        n = len(thetas)
+        p = LanczosParams(kmax, PRECISIONS[precision], beta_tol, resid_tol)
+        rs = (LanczosResult * n)()
+        args = [self._ptr_array(BTensor, Ls), self._ptr_array(MpoSite, W1s),
+                self._ptr_array(MpoSite, W2s), self._ptr_array(BTensor, Rs),
+                self._ptr_array(BTensor, thetas)]
+        code = self.lib.tnt_lanczos_ground_batched(self.ctx, n, *args, C.byref(p), rs)
+        self._check("tnt_lanczos_ground_batched", code)
+        return [{"E_ritz": r.E_ritz, "E": r.E_refined, "residual": r.residual, "steps": r.steps,
+                 "status": code} for r in rs]
+
+    def sweep_batched(self, mpss, envs, chi_max, kmax=20, precision="fp64", rel_tol=1e-12,
+                      abs_tol=-1.0, err_tol=-1.0, err_type=TNT_ERR_2NORM, beta_tol=1e-12):
+        """One lockstep sweep of several chains; chi_max per chain (list) or common."""
+        n = len(mpss)
+        chis = list(chi_max) if hasattr(chi_max, "__len__") else [chi_max] * n
+        ps = (SweepParams * n)()
+        rec = []
+        for i, m in enumerate(mpss):
+            cap = 2 * (m.L - 1)
+            arr = (np.zeros(cap), np.zeros(cap), np.zeros(cap, np.int32), np.zeros(cap, np.int32))
+            rec.append(arr)
+            ps[i] = SweepParams(LanczosParams(kmax, PRECISIONS[precision], beta_tol, -1.0),
+                                TruncParams(int(chis[i]), int(err_type), float(abs_tol),
+                                            float(rel_tol), float(err_tol), 1),
+                                cap, _ptr(arr[0], F64P), _ptr(arr[1], F64P), _ptr(arr[2], I32P),
+                                _ptr(arr[3], I32P))
+        hm = (P * n)(*[m.h.value for m in mpss])
+        he = (P * n)(*[e.h.value for e in envs])
+        rs = (SweepResult * n)()
+        code = self.lib.tnt_dmrg_sweep_batched(self.ctx, n, hm, he, ps, rs)
+        self._check("tnt_dmrg_sweep_batched", code)
+        out = []
+        for r, (E, eps, chi, steps) in zip(rs, rec):
+            d = {f: getattr(r, f) for f, _ in SweepResult._fields_}
+            d.update({"bond_E": E, "bond_eps": eps, "bond_chi": chi, "bond_steps": steps})
+            out.append(d)
+        return out
 
     def sweep(self, mps, env, chi_max, kmax=20, precision="fp64", rel_tol=1e-12, abs_tol=-1.0,
               err_tol=-1.0, err_type=TNT_ERR_2NORM, beta_tol=1e-12):

@@ -1,0 +1,318 @@
+// Batch operators and the batched Lanczos recurrence (see batch.h).
+#include "batch.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace tnt {
+
+// About this many workgroups per segmented launch, spread over the
+// instances in proportion to their size (at least one each).
+static constexpr int SEG_TARGET_BLOCKS = 1024;
+static constexpr int64_t SEG_MIN_RANGE = 512;  // complex entries per workgroup at least
+
+void SegLayout::build(Ctx& c, const std::vector<int64_t>& off, const std::vector<int64_t>& n) {
+  blk.clear();
+  inst_blk.clear();
+  int64_t N = 0;
+  for (int64_t v : n) N += v;
+  for (size_t i = 0; i < n.size(); ++i) {
+    int64_t nb = N > 0 ? (int64_t)std::llround((double)SEG_TARGET_BLOCKS * n[i] / N) : 1;
+    nb = std::max<int64_t>(1, std::min(nb, (n[i] + SEG_MIN_RANGE - 1) / SEG_MIN_RANGE));
+    const int64_t chunk = (n[i] + nb - 1) / std::max<int64_t>(nb, 1);
+    const int first = (int)blk.size();
+    for (int64_t lo = 0; lo < n[i]; lo += chunk)
+      blk.push_back(SegBlock{(int)i, 0, off[i] + lo, off[i] + std::min(n[i], lo + chunk)});
+    if ((int)blk.size() == first) blk.push_back(SegBlock{(int)i, 0, off[i], off[i]});
+    inst_blk.push_back(int2{first, (int)blk.size()});
+  }
+  nblk = (int)blk.size();
+  const size_t bytes = blk.size() * sizeof(SegBlock) + inst_blk.size() * sizeof(int2);
+  std::vector<char> host(bytes);
+  memcpy(host.data(), blk.data(), blk.size() * sizeof(SegBlock));
+  memcpy(host.data() + blk.size() * sizeof(SegBlock), inst_blk.data(),
+         inst_blk.size() * sizeof(int2));
+  dev = DevBuf(&c.pool, bytes);
+  TNT_HIP(hipMemcpyAsync(dev.ptr, host.data(), bytes, hipMemcpyHostToDevice, c.stream));
+  // the host copy must outlive the transfer
+  TNT_HIP(hipStreamSynchronize(c.stream));
+}
+
+void build_batch(Ctx& c, BatchHeff& b, const std::vector<std::shared_ptr<HeffOp>>& ops,
+                 const std::vector<int64_t>& n, int prec) {
+  if (ops.empty() || ops.size() != n.size()) fail(TNT_E_ARG, "empty or inconsistent batch");
+  b.n = n;
+  b.precision = prec;
+  b.parts.clear();
+  b.L_ext.clear();
+  b.R_ext.clear();
+  b.N = b.L_tot = b.R_tot = 0;
+  std::vector<const HeffPlan*> plans;
+  std::vector<int64_t> off;
+  for (size_t i = 0; i < ops.size(); ++i) {
+    if (ops[i]->precision != prec) fail(TNT_E_STATE, "batch operators disagree in precision");
+    plans.push_back(&ops[i]->plan);
+    b.parts.push_back(BatchPart{b.N, b.L_tot, b.R_tot});
+    off.push_back(b.N);
+    b.L_ext.push_back(ops[i]->L_ext);
+    b.R_ext.push_back(ops[i]->R_ext);
+    b.N += n[i];
+    b.L_tot += ops[i]->L_ext;
+    b.R_tot += ops[i]->R_ext;
+  }
+  b.op = std::make_shared<HeffOp>();
+  b.op->build_plan(c, merge_heff_plans(plans, b.parts), prec);
+  b.op->L_ext = b.L_tot;
+  b.op->R_ext = b.R_tot;
+  b.seg.build(c, off, n);
+}
+
+void bind_batch_envs(Ctx& c, BatchHeff& b, const std::vector<const double*>& Lre,
+                     const std::vector<const double*>& Lim, const std::vector<const double*>& Rre,
+                     const std::vector<const double*>& Rim) {
+  const int m = b.ninst();
+  b.envs.ensure(&c.pool, std::max<int64_t>(1, 2 * (b.L_tot + b.R_tot)) * sizeof(double));
+  double* Lr = b.envs.as<double>();
+  double* Li = Lr + b.L_tot;
+  double* Rr = Li + b.L_tot;
+  double* Ri = Rr + b.R_tot;
+  std::vector<CopyRun> runs;
+  int64_t mx = 0;
+  for (int i = 0; i < m; ++i) {
+    const BatchPart& w = b.parts[i];
+    runs.push_back(CopyRun{Lre[i], Lr + w.L_off, b.L_ext[i]});
+    runs.push_back(CopyRun{Lim[i], Li + w.L_off, b.L_ext[i]});
+    runs.push_back(CopyRun{Rre[i], Rr + w.R_off, b.R_ext[i]});
+    runs.push_back(CopyRun{Rim[i], Ri + w.R_off, b.R_ext[i]});
+    mx = std::max({mx, b.L_ext[i], b.R_ext[i]});
+  }
+  DevBuf t(&c.pool, runs.size() * sizeof(CopyRun));
+  TNT_HIP(hipMemcpyAsync(t.ptr, runs.data(), runs.size() * sizeof(CopyRun),
+                         hipMemcpyHostToDevice, c.stream));
+  launch_copy_runs(t.as<CopyRun>(), (int)runs.size(), mx, c.stream);
+  // the host run list must outlive the transfer
+  TNT_HIP(hipStreamSynchronize(c.stream));
+  b.op->bind_envs(Lr, Li, Rr, Ri);
+}
+
+// ---------------------------------------------------------------------------
+// batched Lanczos
+// ---------------------------------------------------------------------------
+// per-instance scalar block (stride S): re-orthogonalisation coefficients,
+// <v_j, w> pairs (alpha_j = real part), beta_j, next-vector scales, |w|^2,
+// the refinement's <psi, H psi> pair and the Ritz coefficients
+struct Slots {
+  int coef, apair, beta, scale, nrm2, e, y, S;
+  explicit Slots(int kmax) {
+    coef = 0;
+    apair = coef + 2 * (kmax + 1);
+    beta = apair + 2 * kmax;
+    scale = beta + kmax;
+    nrm2 = scale + kmax;
+    e = nrm2 + 1;
+    y = e + 2;
+    S = y + kmax;
+  }
+};
+
+void BatchKrylov::reserve(Ctx& c, int kmax_, int64_t N_, int ninst_, int nblk) {
+  kmax = kmax_;
+  N = N_;
+  ninst = ninst_;
+  S = Slots(kmax).S;
+  basis.ensure(&c.pool, (size_t)kmax * 2 * N * sizeof(double));
+  w.ensure(&c.pool, (size_t)2 * N * sizeof(double));
+  part.ensure(&c.pool, (size_t)nblk * 2 * (kmax + 1) * sizeof(double));
+  scal.ensure(&c.pool, (size_t)ninst * S * sizeof(double));
+  kdev.ensure(&c.pool, (size_t)std::max(1, ninst) * sizeof(int));
+  stage.ensure((size_t)ninst * S + 8);
+}
+
+static void lanczos_step_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, int j,
+                                 const tnt_lanczos_params& p, const hipEvent_t* ev) {
+  const Slots sl(K.kmax);
+  const int64_t N = K.N, ld = 2 * N;
+  const int S = K.S, m = b.ninst(), nb = b.seg.nblk;
+  const SegBlock* blk = b.seg.d_blk();
+  const int2* ib = b.seg.d_inst();
+  double* V = K.basis.as<double>();
+  double* w = K.w.as<double>();
+  double* sc = K.scal.as<double>();
+  double* part = K.part.as<double>();
+  double* vj = V + (size_t)j * ld;
+  if (ev) TNT_HIP(hipEventRecord(ev[0], c.stream));
+  b.op->apply(vj, vj + N, w, w + N, p.precision, ev ? ev + 2 : nullptr);
+  if (ev) TNT_HIP(hipEventRecord(ev[1], c.stream));
+  launch_seg_multidot(vj, ld, 1, w, N, blk, nb, part, c.stream);
+  launch_seg_reduce(part, 2, ib, m, sc + sl.apair + 2 * j, S, c.stream);
+  launch_seg_axpy2(vj, sc + sl.apair + 2 * j, S, j > 0 ? V + (size_t)(j - 1) * ld : nullptr,
+                   j > 0 ? sc + sl.beta + j - 1 : nullptr, S, w, N, blk, nb, c.stream);
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_seg_multidot(V, ld, j + 1, w, N, blk, nb, part, c.stream);
+    launch_seg_reduce(part, 2 * (j + 1), ib, m, sc + sl.coef, S, c.stream);
+    launch_seg_multiaxpy_norm(V, ld, j + 1, sc + sl.coef, S, w, N, blk, nb, part, c.stream);
+  }
+  launch_seg_reduce(part, 1, ib, m, sc + sl.nrm2, S, c.stream);
+  launch_seg_lanczos_beta(sc + sl.nrm2, S, sc + sl.apair, S, p.beta_tol, j, K.kdev.as<int>(),
+                          sc + sl.beta + j, S, sc + sl.scale + j, S, m, c.stream);
+  if (j + 1 < K.kmax)
+    launch_seg_scale_copy(w, V + (size_t)(j + 1) * ld, N, blk, nb, sc + sl.scale + j, S, 0,
+                          c.stream);
+}
+
+void lanczos_run_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, double* x,
+                         const tnt_lanczos_params& p, std::vector<LanczosOut>& out, Timers* tm) {
+  const int m = b.ninst();
+  const int64_t N = b.N, ld = 2 * N;
+  const SegBlock* blk = b.seg.d_blk();
+  const int2* ib = b.seg.d_inst();
+  const int nb = b.seg.nblk;
+  // per-instance step counts: the Krylov space has dimension <= n_i
+  std::vector<int> kmax_i(m);
+  int kmax = 0;
+  for (int i = 0; i < m; ++i) {
+    kmax_i[i] = (int)std::min<int64_t>(p.kmax, b.n[i]);
+    kmax = std::max(kmax, kmax_i[i]);
+  }
+  K.reserve(c, kmax, N, m, nb);
+  const Slots sl(K.kmax);
+  const int S = K.S;
+  double* V = K.basis.as<double>();
+  double* w = K.w.as<double>();
+  double* sc = K.scal.as<double>();
+  double* part = K.part.as<double>();
+  TNT_HIP(hipMemcpyAsync(K.kdev.ptr, kmax_i.data(), m * sizeof(int), hipMemcpyHostToDevice,
+                         c.stream));
+  // v0 = x / |x| per instance
+  launch_seg_norm2(x, N, blk, nb, part, c.stream);
+  launch_seg_reduce(part, 1, ib, m, sc + sl.nrm2, S, c.stream);
+  TNT_HIP(hipMemcpyAsync(K.stage.p, sc, (size_t)m * S * sizeof(double), hipMemcpyDeviceToHost,
+                         c.stream));
+  TNT_HIP(hipStreamSynchronize(c.stream));
+  for (int i = 0; i < m; ++i) {
+    const double x2 = K.stage.p[(size_t)i * S + sl.nrm2];
+    if (!std::isfinite(x2)) fail(TNT_E_NONFINITE, "start vector is not finite");
+    if (x2 <= 0.0) fail(TNT_E_ARG, "start vector is zero");
+  }
+  launch_seg_scale_copy(x, V, N, blk, nb, sc + sl.nrm2, S, 1, c.stream);
+
+  if (tm) {
+    while ((int)c.step_ev.size() < 6 * kmax) {
+      hipEvent_t e;
+      TNT_HIP(hipEventCreate(&e));
+      c.step_ev.push_back(e);
+    }
+  }
+  HeffOp& op = *b.op;
+  if (c.graphs && !tm) {
+    op.prepare(V, V + N, w, w + N, p.precision);
+    std::vector<const void*> key = {V, w, K.part.ptr, K.scal.ptr, K.kdev.ptr, b.seg.dev.ptr,
+                                    (const void*)(intptr_t)kmax,
+                                    (const void*)(intptr_t)p.precision, op.L_re, op.L_im,
+                                    op.R_re, op.R_im};
+    for (auto& bf : c.ws) key.push_back(bf.ptr);
+    if (!op.graph.exec || op.graph.key != key) {
+      if (op.graph.exec) {
+        TNT_HIP(hipStreamSynchronize(c.stream));
+        TNT_HIP(hipGraphExecDestroy(op.graph.exec));
+        op.graph.exec = nullptr;
+      }
+      if (!c.gstream) TNT_HIP(hipStreamCreateWithFlags(&c.gstream, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      const hipStream_t main = c.stream;
+      c.stream = c.gstream;  // recorded, not run
+      hipError_t ce = hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed);
+      if (ce == hipSuccess) {
+        try {
+          for (int j = 0; j < kmax; ++j) lanczos_step_batched(c, b, K, j, p, nullptr);
+        } catch (...) {
+          (void)hipStreamEndCapture(c.stream, &g);
+          if (g) (void)hipGraphDestroy(g);
+          c.stream = main;
+          throw;
+        }
+        ce = hipStreamEndCapture(c.stream, &g);
+      }
+      c.stream = main;
+      if (ce != hipSuccess) fail(TNT_E_HIP, std::string("graph recording: ") + hipGetErrorString(ce));
+      hipError_t ie = hipGraphInstantiate(&op.graph.exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        op.graph.exec = nullptr;
+        fail(TNT_E_HIP, std::string("graph instantiation: ") + hipGetErrorString(ie));
+      }
+      op.graph.key = key;
+    }
+    TNT_HIP(hipGraphLaunch(op.graph.exec, c.stream));
+  } else {
+    for (int j = 0; j < kmax; ++j)
+      lanczos_step_batched(c, b, K, j, p, tm ? &c.step_ev[6 * j] : nullptr);
+  }
+  // every instance's alpha / beta in one round trip
+  TNT_HIP(hipMemcpyAsync(K.stage.p, sc, (size_t)m * S * sizeof(double), hipMemcpyDeviceToHost,
+                         c.stream));
+  TNT_HIP(hipStreamSynchronize(c.stream));
+  if (tm) {
+    for (int j = 0; j < kmax; ++j) {
+      const hipEvent_t* ev = &c.step_ev[6 * j];
+      float ms = 0, m1 = 0, m4 = 0;
+      TNT_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      TNT_HIP(hipEventElapsedTime(&m1, ev[2], ev[3]));
+      TNT_HIP(hipEventElapsedTime(&m4, ev[4], ev[5]));
+      tm->matvec_s += ms * 1e-3;
+      tm->gemm_s += (m1 + m4) * 1e-3;
+      tm->gemm_launches += 2;
+    }
+  }
+  out.assign(m, LanczosOut{});
+  std::vector<double> yall((size_t)m * S, 0.0);
+  int kuse = 1;
+  for (int i = 0; i < m; ++i) {
+    const double* s = K.stage.p + (size_t)i * S;
+    std::vector<double> alpha, beta;
+    const double thr = p.beta_tol * std::max(1.0, std::fabs(s[sl.apair]));
+    for (int j = 0; j < kmax_i[i]; ++j) {
+      const double a = s[sl.apair + 2 * j], bb = s[sl.beta + j];
+      if (!std::isfinite(a) || !std::isfinite(bb)) fail(TNT_E_NONFINITE, "Lanczos produced NaN/Inf");
+      alpha.push_back(a);
+      if (j == kmax_i[i] - 1 || !(bb > thr)) break;
+      beta.push_back(bb);
+    }
+    std::vector<double> y;
+    double ev = 0;
+    tridiag_lowest(alpha, beta, &ev, y);
+    out[i].E_ritz = ev;
+    out[i].steps = (int)alpha.size();
+    out[i].matvecs = kmax_i[i];
+    kuse = std::max(kuse, (int)alpha.size());
+    for (size_t q = 0; q < y.size(); ++q) yall[(size_t)i * S + sl.y + q] = y[q];
+  }
+  // psi_i = V y_i (y_i zero beyond the instance's steps), normalised
+  memcpy(K.stage.p, yall.data(), yall.size() * sizeof(double));
+  TNT_HIP(hipMemcpyAsync(sc, K.stage.p, yall.size() * sizeof(double), hipMemcpyHostToDevice,
+                         c.stream));
+  launch_seg_combine_basis(V, ld, kuse, sc + sl.y, S, x, N, blk, nb, c.stream);
+  launch_seg_norm2(x, N, blk, nb, part, c.stream);
+  launch_seg_reduce(part, 1, ib, m, sc + sl.nrm2, S, c.stream);
+  launch_seg_scale_copy(x, x, N, blk, nb, sc + sl.nrm2, S, 1, c.stream);
+  // FP64 refinement for all instances: E_i = Re <psi_i, H psi_i>, r_i
+  op.apply(x, x + N, w, w + N, TNT_FP64);
+  launch_seg_multidot(x, ld, 1, w, N, blk, nb, part, c.stream);
+  launch_seg_reduce(part, 2, ib, m, sc + sl.e, S, c.stream);
+  launch_seg_axpy2(x, sc + sl.e, S, nullptr, nullptr, S, w, N, blk, nb, c.stream);
+  launch_seg_norm2(w, N, blk, nb, part, c.stream);
+  launch_seg_reduce(part, 1, ib, m, sc + sl.nrm2, S, c.stream);
+  TNT_HIP(hipMemcpyAsync(K.stage.p, sc, (size_t)m * S * sizeof(double), hipMemcpyDeviceToHost,
+                         c.stream));
+  TNT_HIP(hipStreamSynchronize(c.stream));
+  for (int i = 0; i < m; ++i) {
+    const double* s = K.stage.p + (size_t)i * S;
+    out[i].E = s[sl.e];
+    out[i].residual = std::sqrt(std::max(0.0, s[sl.nrm2]));
+    if (!std::isfinite(out[i].E) || !std::isfinite(out[i].residual))
+      fail(TNT_E_NONFINITE, "refined energy is not finite");
+  }
+}
+
+}  // namespace tnt

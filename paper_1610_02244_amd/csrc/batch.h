@@ -1,0 +1,65 @@
+// Batches of independent two-site problems (different chains, bonds, block
+// structures) driven through one merged H_eff operator: one grouped launch
+// per contraction step for all instances, and a Lanczos recurrence whose
+// vector operations are segmented per instance.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "lanczos.h"
+
+namespace tnt {
+
+// Block table of the segmented Krylov kernels over a batch vector.
+struct SegLayout {
+  std::vector<SegBlock> blk;
+  std::vector<int2> inst_blk;  // per instance: [first, last) block
+  DevBuf dev;                  // blk then inst_blk
+  int nblk = 0;
+  const SegBlock* d_blk() const { return dev.as<SegBlock>(); }
+  const int2* d_inst() const {
+    return reinterpret_cast<const int2*>(dev.as<char>() + blk.size() * sizeof(SegBlock));
+  }
+  void build(Ctx& c, const std::vector<int64_t>& off, const std::vector<int64_t>& n);
+};
+
+struct BatchHeff {
+  std::shared_ptr<HeffOp> op;       // merged operator over the batch vector
+  std::vector<BatchPart> parts;     // per instance
+  std::vector<int64_t> n;           // complex entries per instance
+  std::vector<int64_t> L_ext, R_ext;
+  int64_t N = 0, L_tot = 0, R_tot = 0;
+  DevBuf envs;                      // [L re | L im | R re | R im] of all instances
+  SegLayout seg;
+  int precision = TNT_FP64;
+  int ninst() const { return (int)n.size(); }
+};
+
+// Merge the per-instance operators (each built for its own theta layout,
+// n[i] complex entries) into one batch operator; instance i's vector goes to
+// complex offset sum_{j<i} n[j].
+void build_batch(Ctx& c, BatchHeff& b, const std::vector<std::shared_ptr<HeffOp>>& ops,
+                 const std::vector<int64_t>& n, int prec);
+// Gather every instance's FP64 environments into the batch planes and bind
+// them (refreshes the packed copies).
+void bind_batch_envs(Ctx& c, BatchHeff& b, const std::vector<const double*>& Lre,
+                     const std::vector<const double*>& Lim, const std::vector<const double*>& Rre,
+                     const std::vector<const double*>& Rim);
+
+struct BatchKrylov {
+  int kmax = 0, ninst = 0, S = 0;  // S: per-instance scalar stride
+  int64_t N = 0;
+  DevBuf basis, w, part, scal, kdev;
+  HostStage stage;
+  void reserve(Ctx& c, int kmax, int64_t N, int ninst, int nblk);
+};
+
+// Batched lowest eigenpairs: x (re plane of N doubles, then im plane) holds
+// the start vectors on entry and the normalised ground vectors on exit;
+// out[i] per instance (steps, Ritz and refined energies, residual).
+void lanczos_run_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, double* x,
+                         const tnt_lanczos_params& p, std::vector<LanczosOut>& out,
+                         Timers* tm);
+
+}  // namespace tnt

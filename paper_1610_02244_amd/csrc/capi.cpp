@@ -4,12 +4,20 @@
 #include <new>
 #include <unordered_map>
 
+#include "batch.h"
 #include "capi_util.h"
 #include "plan.h"
 
 namespace tnt {
 
 struct PlanCache {
+  // batch operators by the identities of their instance operators (which
+  // they keep alive)
+  struct Batch {
+    std::vector<std::shared_ptr<HeffOp>> ops;
+    std::shared_ptr<BatchHeff> b;
+  };
+  std::unordered_map<uint64_t, Batch> batch;
   // operators by the hash of their parsed block structures
   std::unordered_map<uint64_t, std::shared_ptr<HeffOp>> heff;
   // the same operators by the hash of the raw host descriptors they were
@@ -128,6 +136,39 @@ HeffArgs parse_heff_args(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt
   return a;
 }
 
+std::shared_ptr<BatchHeff> cached_batch(Ctx& c, const std::vector<std::shared_ptr<HeffOp>>& ops,
+                                        const std::vector<int64_t>& n, int prec) {
+  Hasher H;
+  H.add(prec);
+  for (size_t i = 0; i < ops.size(); ++i) {
+    H.add(ops[i].get());
+    H.add(n[i]);
+  }
+  if (!c.plans) c.plans = new PlanCache();
+  auto it = c.plans->batch.find(H.h);
+  if (it != c.plans->batch.end() && it->second.ops == ops) return it->second.b;
+  if (c.plans->batch.size() >= 256) {
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    c.plans->batch.clear();
+  }
+  auto b = std::make_shared<BatchHeff>();
+  build_batch(c, *b, ops, n, prec);
+  c.plans->batch[H.h] = PlanCache::Batch{ops, b};
+  return b;
+}
+
+void copy_runs(Ctx& c, const std::vector<CopyRun>& runs) {
+  if (runs.empty()) return;
+  int64_t mx = 0;
+  for (const CopyRun& r : runs) mx = std::max(mx, r.count);
+  DevBuf t(&c.pool, runs.size() * sizeof(CopyRun));
+  TNT_HIP(hipMemcpyAsync(t.ptr, runs.data(), runs.size() * sizeof(CopyRun),
+                         hipMemcpyHostToDevice, c.stream));
+  launch_copy_runs(t.as<CopyRun>(), (int)runs.size(), mx, c.stream);
+  // the host run list must outlive the transfer
+  TNT_HIP(hipStreamSynchronize(c.stream));
+}
+
 std::shared_ptr<HeffOp> cached_heff(Ctx& c, const HeffArgs& a, int prec) {
   Hasher H;
   H.add(prec);
@@ -205,7 +246,73 @@ tnt_status tnt_ctx_set_autotune(tnt_ctx ctx, int32_t on) {
     TNT_HIP(hipStreamSynchronize(c.stream));
     c.plans->heff.clear();
     c.plans->raw.clear();
+    c.plans->batch.clear();
   }
+  TNT_API_END
+}
+
+tnt_status tnt_heff2_apply_batched(tnt_ctx ctx, int32_t n, const tnt_btensor* const* L,
+                                   const tnt_mpo_site* const* W1, const tnt_mpo_site* const* W2,
+                                   const tnt_btensor* const* R, const tnt_btensor* const* theta,
+                                   tnt_btensor* const* out, int32_t precision) {
+  TNT_API_BEGIN(ctx)
+  check_precision(precision);
+  if (n < 1 || !L || !W1 || !W2 || !R || !theta || !out) fail(TNT_E_ARG, "null or empty batch");
+  // the instances' theta and out layouts as handed over
+  std::vector<ThetaH> tlay(n), olay(n);
+  std::vector<std::shared_ptr<HeffOp>> ops;
+  std::vector<int64_t> nn;
+  for (int i = 0; i < n; ++i) {
+    if (!L[i] || !R[i] || !theta[i] || !out[i]) fail(TNT_E_ARG, "null instance operand");
+    HeffArgs a = parse_heff_args(L[i], W1[i], W2[i], R[i], theta[i], out[i]);
+    if (L[i]->dtype != TNT_DT_F64 || R[i]->dtype != TNT_DT_F64 ||
+        theta[i]->dtype != TNT_DT_F64 || out[i]->dtype != TNT_DT_F64)
+      fail(TNT_E_ARG, "L, R, theta and out must be FP64 planes");
+    tlay[i] = a.th;
+    olay[i] = a.out;
+    // the batch vector holds every instance in its canonical packed layout
+    int64_t off = 0;
+    for (auto& kv : a.th.blocks) {
+      kv.second.off = off;
+      off += (int64_t)kv.second.rows * kv.second.cols;
+    }
+    a.th.elems = a.th.extent = off;
+    a.out = a.th;
+    nn.push_back(off);
+    ops.push_back(cached_heff(c, a, precision));
+  }
+  auto B = cached_batch(c, ops, nn, precision);
+  std::vector<const double *> Lr, Li, Rr, Ri;
+  for (int i = 0; i < n; ++i) {
+    Lr.push_back(static_cast<const double*>(L[i]->re));
+    Li.push_back(static_cast<const double*>(L[i]->im));
+    Rr.push_back(static_cast<const double*>(R[i]->re));
+    Ri.push_back(static_cast<const double*>(R[i]->im));
+  }
+  bind_batch_envs(c, *B, Lr, Li, Rr, Ri);
+  DevBuf xb(&c.pool, std::max<int64_t>(1, 4 * B->N) * sizeof(double));
+  double* x = xb.as<double>();
+  double* y = x + 2 * B->N;
+  std::vector<CopyRun> in, back;
+  for (int i = 0; i < n; ++i) {
+    const int64_t base = B->parts[i].x_off;
+    int64_t off = 0;
+    for (auto& kv : tlay[i].blocks) {
+      const BlockRef& src = kv.second;
+      const BlockRef& dst = olay[i].blocks.at(kv.first);
+      const int64_t cnt = (int64_t)src.rows * src.cols;
+      in.push_back(CopyRun{static_cast<const double*>(theta[i]->re) + src.off, x + base + off, cnt});
+      in.push_back(
+          CopyRun{static_cast<const double*>(theta[i]->im) + src.off, x + B->N + base + off, cnt});
+      back.push_back(CopyRun{y + base + off, static_cast<double*>(out[i]->re) + dst.off, cnt});
+      back.push_back(CopyRun{y + B->N + base + off, static_cast<double*>(out[i]->im) + dst.off, cnt});
+      off += cnt;
+    }
+  }
+  copy_runs(c, in);
+  B->op->apply(x, x + B->N, y, y + B->N, precision);
+  copy_runs(c, back);
+  TNT_HIP(hipGetLastError());
   TNT_API_END
 }
 

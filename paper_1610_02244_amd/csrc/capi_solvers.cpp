@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "batch.h"
 #include "capi_util.h"
 #include "dmrg.h"
 
@@ -97,6 +98,74 @@ tnt_status tnt_lanczos_ground(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_s
   r->residual = o.residual;
   r->steps = o.steps;
   if (p->resid_tol > 0 && o.residual > p->resid_tol) ret = TNT_W_NOCONV;
+  return ret;
+  TNT_API_END
+}
+
+tnt_status tnt_lanczos_ground_batched(tnt_ctx ctx, int32_t n, const tnt_btensor* const* L,
+                                      const tnt_mpo_site* const* W1,
+                                      const tnt_mpo_site* const* W2, const tnt_btensor* const* R,
+                                      tnt_btensor* const* theta, const tnt_lanczos_params* p,
+                                      tnt_lanczos_result* r) {
+  tnt_status ret = TNT_OK;
+  TNT_API_BEGIN(ctx)
+  if (n < 1 || !L || !W1 || !W2 || !R || !theta || !r) fail(TNT_E_ARG, "null or empty batch");
+  check_lanczos(p);
+  std::vector<HeffArgs> args(n);
+  std::vector<ThetaH> lay(n);
+  std::vector<std::shared_ptr<HeffOp>> ops;
+  std::vector<int64_t> nn;
+  for (int i = 0; i < n; ++i) {
+    if (!L[i] || !R[i] || !theta[i]) fail(TNT_E_ARG, "null instance operand");
+    HeffArgs a = parse_heff_args(L[i], W1[i], W2[i], R[i], theta[i], nullptr);
+    if (L[i]->dtype != TNT_DT_F64 || R[i]->dtype != TNT_DT_F64 || theta[i]->dtype != TNT_DT_F64)
+      fail(TNT_E_ARG, "L, R and theta must be FP64 planes");
+    if (a.th.blocks.empty()) fail(TNT_E_SHAPE, "theta has no block");
+    lay[i] = a.th;
+    a.th = packed(a.th);
+    a.out = a.th;
+    nn.push_back(a.th.elems);
+    ops.push_back(cached_heff(c, a, p->precision));
+    args[i] = std::move(a);
+  }
+  auto B = cached_batch(c, ops, nn, p->precision);
+  std::vector<const double *> Lr, Li, Rr, Ri;
+  for (int i = 0; i < n; ++i) {
+    Lr.push_back(static_cast<const double*>(L[i]->re));
+    Li.push_back(static_cast<const double*>(L[i]->im));
+    Rr.push_back(static_cast<const double*>(R[i]->re));
+    Ri.push_back(static_cast<const double*>(R[i]->im));
+  }
+  bind_batch_envs(c, *B, Lr, Li, Rr, Ri);
+  DevBuf xb(&c.pool, std::max<int64_t>(1, 2 * B->N) * sizeof(double));
+  double* x = xb.as<double>();
+  // every block of every instance into the batch vector, and back afterwards
+  std::vector<CopyRun> in, back;
+  for (int i = 0; i < n; ++i) {
+    const int64_t off = B->parts[i].x_off;
+    double* tre = static_cast<double*>(theta[i]->re);
+    double* tim = static_cast<double*>(theta[i]->im);
+    for (auto& kv : args[i].th.blocks) {
+      const BlockRef& src = lay[i].blocks.at(kv.first);
+      const int64_t cnt = (int64_t)src.rows * src.cols;
+      in.push_back(CopyRun{tre + src.off, x + off + kv.second.off, cnt});
+      in.push_back(CopyRun{tim + src.off, x + B->N + off + kv.second.off, cnt});
+      back.push_back(CopyRun{x + off + kv.second.off, tre + src.off, cnt});
+      back.push_back(CopyRun{x + B->N + off + kv.second.off, tim + src.off, cnt});
+    }
+  }
+  copy_runs(c, in);
+  BatchKrylov K;
+  std::vector<LanczosOut> o;
+  lanczos_run_batched(c, *B, K, x, *p, o, nullptr);
+  copy_runs(c, back);
+  for (int i = 0; i < n; ++i) {
+    r[i].E_ritz = o[i].E_ritz;
+    r[i].E_refined = o[i].E;
+    r[i].residual = o[i].residual;
+    r[i].steps = o[i].steps;
+    if (p->resid_tol > 0 && o[i].residual > p->resid_tol) ret = TNT_W_NOCONV;
+  }
   return ret;
   TNT_API_END
 }
@@ -345,17 +414,7 @@ tnt_status tnt_env_create(tnt_ctx ctx, tnt_mps mps, const tnt_mpo_site* mpo, int
 
 void tnt_env_destroy(tnt_env env) { delete reinterpret_cast<EnvObj*>(env); }
 
-tnt_status tnt_dmrg_sweep(tnt_ctx ctx, tnt_mps mps, tnt_env env, const tnt_sweep_params* p,
-                          tnt_sweep_result* r) {
-  TNT_API_BEGIN(ctx)
-  if (!mps || !env || !p || !r) fail(TNT_E_ARG, "null argument");
-  MpsObj* mo = reinterpret_cast<MpsObj*>(mps);
-  EnvObj* eo = reinterpret_cast<EnvObj*>(env);
-  if (eo->mps != mo) fail(TNT_E_STATE, "environment belongs to another MPS");
-  check_lanczos(&p->lanczos);
-  check_trunc(&p->trunc);
-  SweepStats st;
-  dmrg_sweep(c, mo->m, eo->e, *p, st);
+static void fill_result(const SweepStats& st, tnt_sweep_result* r) {
   r->energy = st.energy;
   r->max_residual = st.max_residual;
   r->max_eps = st.max_eps;
@@ -371,6 +430,49 @@ tnt_status tnt_dmrg_sweep(tnt_ctx ctx, tnt_mps mps, tnt_env env, const tnt_sweep
   r->gemm_flops = st.gemm_flops;
   r->seconds_gemm = st.t_gemm;
   r->gemm_launches = st.gemm_launches;
+}
+
+tnt_status tnt_dmrg_sweep_batched(tnt_ctx ctx, int32_t n, const tnt_mps* mps, const tnt_env* env,
+                                  const tnt_sweep_params* p, tnt_sweep_result* r) {
+  TNT_API_BEGIN(ctx)
+  if (n < 1 || !mps || !env || !p || !r) fail(TNT_E_ARG, "null or empty batch");
+  std::vector<MpsH*> ms;
+  std::vector<EnvS*> es;
+  for (int i = 0; i < n; ++i) {
+    if (!mps[i] || !env[i]) fail(TNT_E_ARG, "null MPS or environment handle");
+    MpsObj* mo = reinterpret_cast<MpsObj*>(mps[i]);
+    EnvObj* eo = reinterpret_cast<EnvObj*>(env[i]);
+    if (eo->mps != mo) fail(TNT_E_STATE, "environment belongs to another MPS");
+    if (mo->ctx != &c) fail(TNT_E_STATE, "MPS belongs to another context");
+    for (int k = 0; k < i; ++k)
+      if (ms[k] == &mo->m) fail(TNT_E_ARG, "an MPS appears twice in the batch");
+    check_lanczos(&p[i].lanczos);
+    check_trunc(&p[i].trunc);
+    if (p[i].lanczos.kmax != p[0].lanczos.kmax ||
+        p[i].lanczos.precision != p[0].lanczos.precision ||
+        p[i].lanczos.beta_tol != p[0].lanczos.beta_tol)
+      fail(TNT_E_ARG, "Lanczos parameters differ within the batch");
+    ms.push_back(&mo->m);
+    es.push_back(&eo->e);
+  }
+  std::vector<SweepStats> st;
+  dmrg_sweep_batched(c, ms, es, p, st);
+  for (int i = 0; i < n; ++i) fill_result(st[i], &r[i]);
+  TNT_API_END
+}
+
+tnt_status tnt_dmrg_sweep(tnt_ctx ctx, tnt_mps mps, tnt_env env, const tnt_sweep_params* p,
+                          tnt_sweep_result* r) {
+  TNT_API_BEGIN(ctx)
+  if (!mps || !env || !p || !r) fail(TNT_E_ARG, "null argument");
+  MpsObj* mo = reinterpret_cast<MpsObj*>(mps);
+  EnvObj* eo = reinterpret_cast<EnvObj*>(env);
+  if (eo->mps != mo) fail(TNT_E_STATE, "environment belongs to another MPS");
+  check_lanczos(&p->lanczos);
+  check_trunc(&p->trunc);
+  SweepStats st;
+  dmrg_sweep(c, mo->m, eo->e, *p, st);
+  fill_result(st, r);
   TNT_API_END
 }
 

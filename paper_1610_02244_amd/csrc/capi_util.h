@@ -3,6 +3,7 @@
 
 #include <memory>
 #include <new>
+#include <vector>
 
 #include "plan.h"
 
@@ -46,5 +47,13 @@ void check_precision(int32_t p);
 HeffArgs parse_heff_args(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt_mpo_site* W2,
                          const tnt_btensor* R, const tnt_btensor* theta, const tnt_btensor* out);
 std::shared_ptr<HeffOp> cached_heff(Ctx& c, const HeffArgs& a, int prec);
+
+struct BatchHeff;
+// Batch operator over these (cached) instance operators, built once per
+// distinct sequence of instance operators and kept in the plan cache.
+std::shared_ptr<BatchHeff> cached_batch(Ctx& c, const std::vector<std::shared_ptr<HeffOp>>& ops,
+                                        const std::vector<int64_t>& n, int prec);
+// Copy contiguous runs between device buffers (one launch).
+void copy_runs(Ctx& c, const std::vector<CopyRun>& runs);
 
 }  // namespace tnt

@@ -12,6 +12,7 @@
 #include <climits>
 #include <cmath>
 
+#include "batch.h"
 #include "capi_util.h"
 
 namespace tnt {
@@ -484,6 +485,149 @@ void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats&
     }
   }
   st.t_total = now_s() - t0;
+}
+
+// ---------------------------------------------------------------------------
+// batched sweeps: every chain advances one bond update per step, in lockstep;
+// the Lanczos recurrences of all chains active at a step run as one batch
+// (one grouped launch per contraction step), while theta formation, the
+// truncated SVD and the environment update stay per chain.
+// ---------------------------------------------------------------------------
+void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<EnvS*>& es,
+                        const tnt_sweep_params* ps, std::vector<SweepStats>& st) {
+  const double t0 = now_s();
+  const int nc = (int)ms.size();
+  st.assign(nc, SweepStats{});
+  int T = 0;
+  for (int i = 0; i < nc; ++i) {
+    const int L = ms[i]->L;
+    if (L < 2) fail(TNT_E_STATE, "need at least two sites");
+    const tnt_sweep_params& p = ps[i];
+    if (p.record_cap < 2 * (L - 1) && (p.bond_E || p.bond_eps || p.bond_chi || p.bond_steps))
+      fail(TNT_E_CAPACITY, "record arrays shorter than 2(L-1)");
+    T = std::max(T, 2 * (L - 1));
+  }
+  const tnt_lanczos_params& lp = ps[0].lanczos;
+  std::vector<DevBuf> theta(nc);
+  std::vector<int> rec(nc, 0);
+  BatchKrylov K;
+  DevBuf xall;
+  double t_matvec = 0, t_lanczos = 0, t_gemm = 0, t_svd = 0, t_env = 0;
+  int64_t launches = 0;
+  for (int t = 0; t < T; ++t) {
+    struct Act { int i, j, pass; };
+    std::vector<Act> act;
+    for (int i = 0; i < nc; ++i) {
+      const int steps = ms[i]->L - 1;
+      if (t >= 2 * steps) continue;
+      const int pass = t < steps ? 0 : 1;
+      const int step = pass == 0 ? t : t - steps;
+      act.push_back(Act{i, pass == 0 ? 1 + step : ms[i]->L - 1 - step, pass});
+    }
+    std::vector<ThetaH> ths;
+    std::vector<std::shared_ptr<HeffOp>> ops;
+    std::vector<int64_t> nn;
+    std::vector<const double *> Lr, Li, Rr, Ri;
+    for (const Act& a : act) {
+      MpsH& m = *ms[a.i];
+      EnvS& e = *es[a.i];
+      ThetaH th = form_theta(c, m, a.j, theta[a.i]);
+      HeffArgs h;
+      h.w1 = e.W[a.j - 1];
+      h.w2 = e.W[a.j];
+      h.th = th;
+      h.out = th;
+      h.L = e.Llay[a.j - 1];
+      h.R = e.Rlay[a.j + 2];
+      ops.push_back(cached_heff(c, h, lp.precision));
+      nn.push_back(th.elems);
+      ths.push_back(std::move(th));
+      Lr.push_back(e.Lre(a.j - 1));
+      Li.push_back(e.Lim(a.j - 1));
+      Rr.push_back(e.Rre(a.j + 2));
+      Ri.push_back(e.Rim(a.j + 2));
+    }
+    auto B = cached_batch(c, ops, nn, lp.precision);
+    bind_batch_envs(c, *B, Lr, Li, Rr, Ri);
+    xall.ensure(&c.pool, std::max<int64_t>(1, 2 * B->N) * sizeof(double));
+    double* x = xall.as<double>();
+    {
+      std::vector<CopyRun> runs;
+      for (size_t a = 0; a < act.size(); ++a) {
+        const int64_t n = nn[a], off = B->parts[a].x_off;
+        const double* src = theta[act[a].i].as<double>();
+        runs.push_back(CopyRun{src, x + off, n});
+        runs.push_back(CopyRun{src + n, x + B->N + off, n});
+      }
+      copy_runs(c, runs);
+    }
+    Timers tm;
+    std::vector<LanczosOut> lo;
+    const double tl0 = now_s();
+    lanczos_run_batched(c, *B, K, x, lp, lo, c.graphs ? nullptr : &tm);
+    const double tl1 = now_s();
+    t_matvec += tm.matvec_s;
+    t_lanczos += (tl1 - tl0) - tm.matvec_s;
+    t_gemm += tm.gemm_s;
+    launches += tm.gemm_launches;
+    for (size_t a = 0; a < act.size(); ++a) {
+      const int i = act[a].i, j = act[a].j, pass = act[a].pass;
+      MpsH& m = *ms[i];
+      EnvS& e = *es[i];
+      const tnt_sweep_params& p = ps[i];
+      SweepStats& s = st[i];
+      const HeffOp& op = *ops[a];
+      s.matvecs += lo[a].matvecs;
+      s.matvec_flops += (double)op.plan.flops() * (double)lo[a].matvecs;
+      s.gemm_flops += (double)(op.plan.flops_step1 + op.plan.flops_step4) * (double)lo[a].matvecs;
+      const int absorb = pass == 0 ? TNT_ABSORB_RIGHT : TNT_ABSORB_LEFT;
+      const int64_t off = B->parts[a].x_off;
+      DevBuf na, nb;
+      const double ts0 = now_s();
+      SvdOut r = svd_truncate_dev(c, ths[a], x + off, x + B->N + off, p.trunc, absorb,
+                                  [&](const SvdOut& o) {
+                                    na = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.A.elems) * 8);
+                                    nb = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.B.elems) * 8);
+                                    FactorPlanes fp;
+                                    fp.a_re = na.as<double>();
+                                    fp.a_im = na.as<double>() + o.A.elems;
+                                    fp.b_re = nb.as<double>();
+                                    fp.b_im = nb.as<double>() + o.B.elems;
+                                    return fp;
+                                  });
+      const double ts = now_s();
+      t_svd += ts - ts0;
+      m.bonds[j] = r.bond;
+      m.lay[j - 1] = r.A;
+      m.dat[j - 1] = std::move(na);
+      m.lay[j] = r.B;
+      m.dat[j] = std::move(nb);
+      if (pass == 0) update_left_env(c, e, j);
+      else update_right_env(c, e, j + 1);
+      t_env += now_s() - ts;
+      s.energy = lo[a].E;
+      s.max_residual = std::max(s.max_residual, lo[a].residual);
+      s.max_eps = std::max(s.max_eps, r.eps);
+      s.max_chi = std::max(s.max_chi, r.chi);
+      if (p.bond_E) p.bond_E[rec[i]] = lo[a].E;
+      if (p.bond_eps) p.bond_eps[rec[i]] = r.eps;
+      if (p.bond_chi) p.bond_chi[rec[i]] = r.chi;
+      if (p.bond_steps) p.bond_steps[rec[i]] = lo[a].steps;
+      ++rec[i];
+      s.updates++;
+    }
+  }
+  // batch-level timings (the chains share every launch)
+  const double total = now_s() - t0;
+  for (SweepStats& s : st) {
+    s.t_total = total;
+    s.t_matvec = t_matvec;
+    s.t_lanczos = t_lanczos;
+    s.t_gemm = t_gemm;
+    s.gemm_launches = launches;
+    s.t_svd = t_svd;
+    s.t_env = t_env;
+  }
 }
 
 }  // namespace tnt

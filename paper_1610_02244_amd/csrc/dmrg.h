@@ -51,5 +51,10 @@ struct SweepStats {
 };
 
 void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats& st);
+// One sweep of each of several chains, bond updates in lockstep with one
+// batched Lanczos per step (ps[i]: the chain's parameters; the Lanczos
+// parameters of ps[0] apply to all).  Timings in st are batch totals.
+void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<EnvS*>& es,
+                        const tnt_sweep_params* ps, std::vector<SweepStats>& st);
 
 }  // namespace tnt

@@ -190,6 +190,48 @@ void launch_norm2_partial(const double* x, int64_t n2, double* partial, hipStrea
 // finite check: flag[0] set to 1 if any non-finite among n doubles
 void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Segmented Krylov kernels of the batched recurrence (krylov_seg.hip).  A
+// batch vector has a re plane of N doubles then an im plane; instance i owns
+// complex entries [off_i, off_i + n_i).  Each workgroup owns one SegBlock
+// (a range inside one instance); inst_blk[i] = the instance's block range.
+// Per-instance scalars are read / written at base + inst * stride.
+// ---------------------------------------------------------------------------
+struct SegBlock {
+  int32_t inst;
+  int32_t pad;
+  int64_t lo, hi;  // complex entry range
+};
+void launch_seg_multidot(const double* V, int64_t ld, int k, const double* w, int64_t N,
+                         const SegBlock* blk, int nblk, double* partial, hipStream_t s);
+void launch_seg_reduce(const double* partial, int k2, const int2* inst_blk, int ninst,
+                       double* out, int out_stride, hipStream_t s);
+void launch_seg_axpy2(const double* v1, const double* a, int a_stride, const double* v0,
+                      const double* b, int b_stride, double* w, int64_t N, const SegBlock* blk,
+                      int nblk, hipStream_t s);
+void launch_seg_multiaxpy_norm(const double* V, int64_t ld, int k, const double* c,
+                               int c_stride, double* w, int64_t N, const SegBlock* blk,
+                               int nblk, double* nrm_partial, hipStream_t s);
+void launch_seg_norm2(const double* x, int64_t N, const SegBlock* blk, int nblk, double* part,
+                      hipStream_t s);
+void launch_seg_lanczos_beta(const double* nrm2, int nrm_stride, const double* alpha0,
+                             int a_stride, double tol, int j, const int* kmax, double* beta,
+                             int b_stride, double* scale, int s_stride, int ninst,
+                             hipStream_t s);
+// mode 0: dst = src * scale_i; mode 1: dst = src / sqrt(scale_i) (0 if <= 0)
+void launch_seg_scale_copy(const double* src, double* dst, int64_t N, const SegBlock* blk,
+                           int nblk, const double* scale, int stride, int mode, hipStream_t s);
+void launch_seg_combine_basis(const double* V, int64_t ld, int k, const double* y, int y_stride,
+                              double* out, int64_t N, const SegBlock* blk, int nblk,
+                              hipStream_t s);
+// contiguous runs of doubles between device buffers (gathers / scatters)
+struct CopyRun {
+  const double* src;
+  double* dst;
+  int64_t count;
+};
+void launch_copy_runs(const CopyRun* runs, int nruns, int64_t max_count, hipStream_t s);
+
 // Scatter from an interleaved complex matrix into row-major split-plane
 // blocks: dst(r, c) = f(src[src_off + r * rs + c * cs]) for r < rows,
 // c < cols, where f conjugates when `conj` is set (strides in complex

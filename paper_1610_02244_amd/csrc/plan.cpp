@@ -385,12 +385,108 @@ HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const En
 // ---------------------------------------------------------------------------
 // HeffOp
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// batch plans
+// ---------------------------------------------------------------------------
+static void append_gemm(HostGemm& d, const HostGemm& s, int64_t dc, int64_t da, int64_t db) {
+  const int seg_base = (int)d.segs.size();
+  for (GemmTask t : s.tasks) {
+    t.c_off += dc;
+    t.seg0 += seg_base;
+    d.tasks.push_back(t);
+  }
+  for (GemmSeg g : s.segs) {
+    g.a_off += da;
+    g.b_off += db;
+    d.segs.push_back(g);
+  }
+  d.flops += s.flops;
+}
+
+static void append_comb(HostComb& d, const HostComb& s, int64_t dd, int64_t ds) {
+  const int term_base = (int)d.terms.size();
+  for (CombTask t : s.tasks) {
+    t.dst_off += dd;
+    t.term0 += term_base;
+    d.tasks.push_back(t);
+  }
+  for (CombTerm t : s.terms) {
+    t.src_off += ds;
+    d.terms.push_back(t);
+  }
+  d.flops += s.flops;
+}
+
+static void append_combp(HostCombP& d, const HostCombP& s, int64_t dd, int64_t ds) {
+  const int term_base = (int)d.terms.size();
+  for (CombPTask t : s.tasks) {
+    t.dst_off += dd;
+    t.term0 += term_base;
+    d.tasks.push_back(t);
+  }
+  for (CombTerm t : s.terms) {
+    t.src_off += ds;
+    d.terms.push_back(t);
+  }
+}
+
+static void append_pack(HostPack& d, const HostPack& s, int64_t dsrc) {
+  const int task_base = (int)d.tasks.size();
+  const int64_t dst_base = d.elems;
+  for (PackTask t : s.tasks) {
+    t.src_off += dsrc;
+    t.dst_off += dst_base;
+    d.tasks.push_back(t);
+  }
+  for (int2 t : s.tiles) d.tiles.push_back(int2{t.x + task_base, t.y});
+  d.elems += s.elems;
+}
+
+HeffPlan merge_heff_plans(const std::vector<const HeffPlan*>& plans,
+                          const std::vector<BatchPart>& where) {
+  HeffPlan M;
+  if (plans.empty()) return M;
+  M.packed = plans[0]->packed;
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const HeffPlan& P = *plans[i];
+    const BatchPart& w = where[i];
+    if (P.packed != M.packed) fail(TNT_E_STATE, "batch plans disagree in precision");
+    append_gemm(M.step1, P.step1, M.t1_elems, w.L_off, w.x_off);
+    append_gemm(M.step4, P.step4, w.x_off, M.t3_elems, w.R_off);
+    append_comb(M.mpo, P.mpo, M.t3_elems, M.t1_elems);
+    if (M.packed) {
+      append_gemm(M.step1p, P.step1p, M.t1_elems, M.Lp.elems, M.Xp.elems);
+      append_gemm(M.step4p, P.step4p, w.x_off, M.t3p_elems, M.Rp.elems);
+      append_combp(M.mpop, P.mpop, M.t3p_elems, M.t1_elems);
+      append_pack(M.Lp, P.Lp, w.L_off);
+      append_pack(M.Rp, P.Rp, w.R_off);
+      append_pack(M.Xp, P.Xp, w.x_off);
+      M.t3p_elems += P.t3p_elems;
+    }
+    M.t1_elems += P.t1_elems;
+    M.t3_elems += P.t3_elems;
+    M.flops_step1 += P.flops_step1;
+    M.flops_mpo += P.flops_mpo;
+    M.flops_step4 += P.flops_step4;
+  }
+  M.mpo.finalize();
+  if (M.packed) M.mpop.finalize();
+  return M;
+}
+
 void HeffOp::build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const EnvH& R,
                    const ThetaH& th, const ThetaH& out, int prec) {
+  build_plan(c, build_heff_plan(L, W1, W2, R, th, out, prec != TNT_FP64), prec);
+  L_ext = L.extent;
+  R_ext = R.extent;
+}
+
+void HeffOp::build_plan(Ctx& c, HeffPlan&& p, int prec) {
   ctx = &c;
   precision = prec;
   const bool packed = prec != TNT_FP64;
-  plan = build_heff_plan(L, W1, W2, R, th, out, packed);
+  plan = std::move(p);
+  if (plan.packed != packed) fail(TNT_E_STATE, "plan built for another precision");
   // tile shape: a cached tuning decision for this shape bucket, else the
   // default, plus every candidate for the first application to time when
   // `tunable` (the operator's own precision)
@@ -416,8 +512,6 @@ void HeffOp::build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const 
     tab.upload(c, {&plan.step1, &plan.step4}, {&plan.mpo});
   }
   tuned = !tune;
-  L_ext = L.extent;
-  R_ext = R.extent;
 }
 
 void HeffOp::bind_envs(const void* lre, const void* lim, const void* rre, const void* rim) {

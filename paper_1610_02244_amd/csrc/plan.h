@@ -154,6 +154,18 @@ struct HeffPlan {
 HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const EnvH& R,
                          const ThetaH& th, const ThetaH& out, bool packed);
 
+// Where one instance's operands sit inside a batch: its theta / out blocks
+// at complex offset x_off of the batch vector planes, its L and R planes at
+// element offsets L_off, R_off of the batch environment planes.
+struct BatchPart {
+  int64_t x_off, L_off, R_off;
+};
+// One plan over all instances: task lists concatenated with every operand
+// offset moved to the batch buffers (slab, packed-copy and table offsets
+// stacked instance after instance).  All plans must agree in `packed`.
+HeffPlan merge_heff_plans(const std::vector<const HeffPlan*>& plans,
+                          const std::vector<BatchPart>& where);
+
 // A ready-to-apply H_eff operator on one bond: the plan and its device
 // tables.  Intermediate slabs and packed operand copies live in the
 // context's shared workspaces (Ctx::ws), sized on use: ws[0] T1 slabs,
@@ -170,6 +182,8 @@ struct HeffOp {
   // plan + device tables + workspaces for these block structures
   void build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const EnvH& R,
              const ThetaH& th, const ThetaH& out, int prec);
+  // the same for a ready plan (a merged batch plan)
+  void build_plan(Ctx& c, HeffPlan&& p, int prec);
   // point at the environments' FP64 planes (and refresh the packed copies)
   void bind_envs(const void* lre, const void* lim, const void* rre, const void* rim);
   PackFmt fmt() const { return precision == TNT_BF16X3 ? PK_BF16X3 : PK_F32; }

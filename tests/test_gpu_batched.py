@@ -1,0 +1,208 @@
+"""Batched paths: many independent two-site problems in one set of launches.
+
+- tnt_heff2_apply_batched against per-instance tnt_heff2_apply (bitwise: the
+  merged task lists sum every output block in the same order) and against
+  the oracle (bars of the single-instance tests);
+- tnt_lanczos_ground_batched against per-instance tnt_lanczos_ground (the
+  segmented vector kernels reduce in another order: energies to 1e-12
+  relative, equal step counts), including an instance smaller than kmax;
+- HIP-graph replays of the batched recurrence against the eager run
+  (bitwise, every replay);
+- tnt_dmrg_sweep_batched against per-chain sweeps, one chain being the
+  oracle's stored cfg1 run;
+- the many-chain workload (64 chains, L 16..64, chi 64..384): batched
+  middle-bond matvecs of sampled chains against the oracle.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import heff as oheff
+from oracle import model
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel_err(a, b):
+    num = sum(float(np.sum(np.abs(a[k] - b[k]) ** 2)) for k in b)
+    den = sum(float(np.sum(np.abs(b[k]) ** 2)) for k in b)
+    return (num / den) ** 0.5
+
+
+def instance(left, right, nmax, U, seed, herm=True):
+    d = nmax + 1
+    W, qw = model.bh_mpo(nmax, 1.0, U, 0.0)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pairs = model.MPO_ADJOINT if herm else None
+    Le = synth.random_env(left, qw, rng, pairs)
+    Re = synth.random_env(right, qw, rng, pairs)
+    th = synth.random_theta(left, right, d, rng)
+    return dict(left=left, right=right, nmax=nmax, U=U, W=W, qw=qw, Le=Le, Re=Re, th=th)
+
+
+CASES = [
+    ({0: 1}, {0: 1, 1: 2, 2: 1}, 1, 2.0),
+    ({10: 37, 11: 130, 12: 65, 13: 3}, {12: 9, 13: 70, 14: 129, 15: 64, 16: 1}, 2, 3.0),
+    ({2: 2, 3: 3}, {4: 2, 5: 3, 6: 1}, 2, 5.0),
+    ({13: 7, 14: 26, 15: 57, 16: 40}, {15: 20, 16: 57, 17: 75, 18: 26}, 4, 4.0),
+]
+
+
+def gpu_side(tnt, inst):
+    from paper_1610_02244_amd import binding as B
+    Wg, qg = tnt.bose_hubbard_mpo(inst["nmax"], 1.0, inst["U"], 0.0)
+    mpo = B.Mpo(Wg, qg)
+    return mpo, tnt.env(inst["Le"], qg), tnt.env(inst["Re"], qg)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_heff_batched_matches_single(tnt, precision):
+    insts = [instance(*c, seed=100 + i) for i, c in enumerate(CASES)]
+    sides = [gpu_side(tnt, x) for x in insts]
+    thetas = [tnt.theta(x["th"]) for x in insts]
+    outs_b = [tnt.theta_like(t) for t in thetas]
+    tnt.heff2_apply_batched([s[1] for s in sides], [s[0] for s in sides],
+                            [s[0] for s in sides], [s[2] for s in sides], thetas, outs_b,
+                            precision)
+    bar = {"fp64": 1e-12, "fp32": 2e-6, "bf16x3": 1e-4}[precision]
+    for x, s, t, ob in zip(insts, sides, thetas, outs_b):
+        o1 = tnt.theta_like(t)
+        tnt.heff2_apply(s[1], s[0], s[0], s[2], t, o1, precision)
+        a, b = tnt.download(ob), tnt.download(o1)
+        for k in b:
+            assert np.array_equal(a[k], b[k]), k
+        ref = oheff.heff2_block(x["Le"], x["W"], x["W"], x["Re"], x["th"], x["left"],
+                                x["right"], x["qw"], x["nmax"] + 1)
+        err = rel_err(a, ref)
+        print(f"  [batched heff {precision}] rel err {err:.2e}")
+        assert err <= bar
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lanczos_batched_matches_single(tnt, precision):
+    insts = [instance(*c, seed=200 + i) for i, c in enumerate(CASES)]
+    sides = [gpu_side(tnt, x) for x in insts]
+    keys = [sorted(x["th"]) for x in insts]
+    single = []
+    for x, s, k in zip(insts, sides, keys):
+        td = tnt.theta(x["th"], k)
+        r = tnt.lanczos_ground(s[1], s[0], s[0], s[2], td, kmax=20, precision=precision)
+        single.append((r, tnt.download(td)))
+    tds = [tnt.theta(x["th"], k) for x, k in zip(insts, keys)]
+    got = tnt.lanczos_ground_batched([s[1] for s in sides], [s[0] for s in sides],
+                                     [s[0] for s in sides], [s[2] for s in sides], tds,
+                                     kmax=20, precision=precision)
+    for (r1, psi1), rb, td in zip(single, got, tds):
+        print(f"  [batched lanczos {precision}] E {rb['E']:.15f} single {r1['E']:.15f} "
+              f"steps {rb['steps']} / {r1['steps']}")
+        assert rb["steps"] == r1["steps"]
+        assert abs(rb["E"] - r1["E"]) <= 1e-12 * abs(r1["E"])
+        psi = tnt.download(td)
+        ov = abs(sum(np.vdot(psi1[k], psi[k]) for k in psi1))
+        assert ov == pytest.approx(1.0, abs=1e-10)
+
+
+def test_lanczos_batched_graph_replays(tnt):
+    insts = [instance(*c, seed=300 + i) for i, c in enumerate(CASES)]
+    sides = [gpu_side(tnt, x) for x in insts]
+    keys = [sorted(x["th"]) for x in insts]
+
+    def run():
+        tds = [tnt.theta(x["th"], k) for x, k in zip(insts, keys)]
+        r = tnt.lanczos_ground_batched([s[1] for s in sides], [s[0] for s in sides],
+                                       [s[0] for s in sides], [s[2] for s in sides], tds,
+                                       kmax=20, precision="fp32")
+        return r, [tnt.download(t) for t in tds]
+
+    ref, psi_ref = run()
+    try:
+        tnt.set_graphs(True)
+        for rep in range(3):
+            got, psi = run()
+            for a, b in zip(got, ref):
+                assert a["E"] == b["E"] and a["steps"] == b["steps"]
+            for p, q in zip(psi, psi_ref):
+                for k in q:
+                    assert np.array_equal(p[k], q[k])
+            tnt.sync()
+    finally:
+        tnt.set_graphs(False)
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, f"sweep_{name}.json")) as f:
+        return json.load(f)
+
+
+def make_chain(tnt, L, N, nmax, U, chi, seed):
+    from paper_1610_02244_amd import binding as B
+    W, qw = tnt.bose_hubbard_mpo(nmax, 1.0, U, 0.0)
+    bonds, sites = synth.random_mps(L, N, nmax, chi, seed)
+    mps = tnt.mps(bonds, sites, nmax + 1)
+    mps.right_canonicalize()
+    env = B.Env(tnt, mps, [W] * L, qw, B.MPO_LEFT, B.MPO_RIGHT)
+    return mps, env
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sweep_batched_matches_single(tnt, precision):
+    g = golden("cfg1")
+    chains = [(g["L"], g["N"], g["nmax"], g["U"], g["chi"], g["seed"]),
+              (10, 10, 2, 3.5, 24, 11), (6, 6, 3, 1.5, 12, 12)]
+    single, batch_m, batch_e = [], [], []
+    for (L, N, nmax, U, chi, seed) in chains:
+        m, e = make_chain(tnt, L, N, nmax, U, chi, seed)
+        single.append([tnt.sweep(m, e, chi, kmax=g["lanczos_steps"], precision=precision,
+                                 rel_tol=g["rel_cutoff"]) for _ in range(2)])
+        m2, e2 = make_chain(tnt, L, N, nmax, U, chi, seed)
+        batch_m.append(m2)
+        batch_e.append(e2)
+    chis = [c[4] for c in chains]
+    batched = [tnt.sweep_batched(batch_m, batch_e, chis, kmax=g["lanczos_steps"],
+                                 precision=precision, rel_tol=g["rel_cutoff"]) for _ in range(2)]
+    for ci in range(len(chains)):
+        for sw in range(2):
+            a = np.array(batched[sw][ci]["bond_E"])
+            b = np.array(single[ci][sw]["bond_E"])
+            rel = np.max(np.abs(a - b) / np.abs(b))
+            print(f"  [batched sweep {precision}] chain {ci} sweep {sw + 1}: max|dE/E| {rel:.2e}")
+            assert rel <= 1e-10
+            assert list(batched[sw][ci]["bond_chi"]) == list(single[ci][sw]["bond_chi"])
+    # chain 0 is the oracle's stored cfg1 run
+    e = batched[-1][0]["bond_E"][-1]
+    er = g["sweeps"][-1]["E"][-1]
+    assert abs(e - er) <= 1e-9 * abs(er)
+
+
+def test_many_chain_matvec_sampled_vs_oracle(tnt):
+    """The 64-chain workload at every chain's middle bond in one batched
+    application; four chains (one per chi) checked against the oracle."""
+    from paper_1610_02244_amd import binding as B
+    specs = synth.batched_specs(4)
+    insts, sides, thetas = [], [], []
+    for s in specs:
+        W, qw = model.bh_mpo(s.nmax, s.J, s.U, s.mu)
+        left, right, Le, Re, th = synth.middle_bond_inputs(s, qw)
+        Wg, qg = tnt.bose_hubbard_mpo(s.nmax, s.J, s.U, s.mu)
+        mpo = B.Mpo(Wg, qg)
+        insts.append(dict(left=left, right=right, W=W, qw=qw, Le=Le, Re=Re, th=th, d=s.d))
+        sides.append((mpo, tnt.env(Le, qg), tnt.env(Re, qg)))
+        thetas.append(tnt.theta(th))
+    outs = [tnt.theta_like(t) for t in thetas]
+    tnt.heff2_apply_batched([s[1] for s in sides], [s[0] for s in sides], [s[0] for s in sides],
+                            [s[2] for s in sides], thetas, outs, "fp32")
+    picked = {}
+    for i, s in enumerate(specs):
+        picked.setdefault(s.chi, i)
+    for chi, i in sorted(picked.items()):
+        x = insts[i]
+        ref = oheff.heff2_block(x["Le"], x["W"], x["W"], x["Re"], x["th"], x["left"], x["right"],
+                                x["qw"], x["d"])
+        err = rel_err(tnt.download(outs[i]), ref)
+        print(f"  [64-chain batch] chain {i} (chi {chi}, L {specs[i].L}): rel err {err:.2e}")
+        assert err <= 2e-6
