@@ -31,6 +31,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "2-site H_eff matvec TFLOP/s + sweep time: FP32-MFMA vs FP64, |ΔE/E|<=1e-9"
 PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0}
+# MPO bond index pairs (w, w') exchanged by Hermitian conjugation of the
+# Bose-Hubbard MPO (b and b^dagger channels): random environments drawn with
+# this symmetry give a Hermitian H_eff
+HERM_PAIRS = [0, 2, 1, 3]
 
 
 def log(*a):
@@ -48,12 +52,13 @@ def make_chain(tnt, B, spec):
 
 
 class Roctx:
-    """roctx range around the timed region (a no-op without libroctx64)."""
+    """roctx range around the timed region (the profiler SDK's roctx library,
+    which rocprofv3 --marker-trace records; a no-op without it)."""
 
     def __init__(self):
         import ctypes
         self.lib = None
-        for p in ("/opt/rocm/lib/libroctx64.so", "libroctx64.so"):
+        for p in ("/opt/rocm/lib/librocprofiler-sdk-roctx.so", "librocprofiler-sdk-roctx.so"):
             try:
                 self.lib = ctypes.CDLL(p)
                 self.lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
@@ -120,6 +125,77 @@ def matvec_rates(tnt, B, torch, spec, precs=("fp64", "fp32", "bf16x3"), reps=20)
     del Ld, Rd, td, out
     return {"chi": spec.chi, "bond": f"middle bond of L={spec.L}",
             "flops": int(flops), "parts": [int(x) for x in parts], **rates}
+
+
+def batched_rates(tnt, B, torch, precision="fp32", reps=10):
+    """The 64-chain workload (L 16..64, chi 64..384, seeded) at every chain's
+    middle bond: one batched H_eff application over all chains, the same 64
+    applications one by one, and one batched Lanczos ground-state solve
+    (20 steps + FP64 refinement), eager and replayed from a HIP graph."""
+    import synth
+    specs = synth.batched_specs(4)
+    mpos, Ls, Rs, ths, thetas, outs = [], [], [], [], [], []
+    flops = 0
+    for s in specs:
+        W, qw = tnt.bose_hubbard_mpo(s.nmax, s.J, s.U, s.mu)
+        left, right, Le, Re, th = synth.middle_bond_inputs(s, qw, hermitian_pairs=HERM_PAIRS)
+        mpo = B.Mpo(W, qw)
+        Ld, Rd, td = tnt.env(Le, qw), tnt.env(Re, qw), tnt.theta(th)
+        mpos.append(mpo)
+        Ls.append(Ld)
+        Rs.append(Rd)
+        ths.append(th)
+        thetas.append(td)
+        outs.append(tnt.theta_like(td))
+        flops += tnt.heff2_flops(Ld, mpo, mpo, Rd, td)[0]
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / n
+
+    t_batch = timed(lambda: tnt.heff2_apply_batched(Ls, mpos, mpos, Rs, thetas, outs, precision),
+                    reps)
+
+    def one_by_one():
+        for i in range(len(specs)):
+            tnt.heff2_apply(Ls[i], mpos[i], mpos[i], Rs[i], thetas[i], outs[i], precision)
+
+    t_single = timed(one_by_one, max(1, reps // 2))
+
+    def lanczos():
+        tds = [tnt.theta(th) for th in ths]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = tnt.lanczos_ground_batched(Ls, mpos, mpos, Rs, tds, kmax=20, precision=precision)
+        return time.perf_counter() - t0, r
+
+    lanczos()  # plans, tile tuning
+    t_eager, r_eager = lanczos()
+    tnt.set_graphs(True)
+    try:
+        lanczos()  # records the graph
+        t_graph, r_graph = lanczos()
+    finally:
+        tnt.set_graphs(False)
+    same = all(a["E"] == b["E"] for a, b in zip(r_eager, r_graph))
+    chis = {}
+    for s in specs:
+        chis[s.chi] = chis.get(s.chi, 0) + 1
+    return {"workload": f"{len(specs)} chains, L {min(s.L for s in specs)}..{max(s.L for s in specs)}, "
+                        f"chi counts {dict(sorted(chis.items()))}, middle bonds, seeded",
+            "precision": precision, "flops_per_batched_matvec": int(flops),
+            "batched_matvec_s": t_batch, "batched_matvec_tflops": flops / t_batch / 1e12,
+            "one_by_one_matvecs_s": t_single, "batching_speedup": t_single / t_batch,
+            "batched_lanczos_eager_s": t_eager, "batched_lanczos_graph_s": t_graph,
+            "graph_energies_equal_eager": bool(same),
+            "lanczos_matvec_tflops_graph": 21 * flops / t_graph / 1e12}
 
 
 def cpu_baseline(spec, budget_s=12.0):
@@ -231,7 +307,17 @@ def main():
     ap.add_argument("--no-bf16x3", action="store_true", help="skip the BF16x3-path sweeps")
     ap.add_argument("--no-chi1024", action="store_true",
                     help="skip the single-matvec timing at the chi = 1024 middle bond")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-chain batched matvec / Lanczos timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="only time single H_eff matvecs at the config's middle bond "
+                         "(prints their JSON and exits; for profiling)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the 64-chain batched timing (prints its JSON and exits)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device copy of 256 MiB each way (three times), the "
+                         "reference that scales the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="print timed-region kernel statistics of a rocprofv3 CSV trace and exit")
     args = ap.parse_args()
@@ -244,11 +330,25 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": x.numel() * 4, "copies": 3}), flush=True)
+        return
     import synth
     from paper_1610_02244_amd import binding as B
 
     spec = synth.CONFIGS[args.config]
     tnt = B.load()
+    if args.batched_only:
+        print(json.dumps(batched_rates(tnt, B, torch, args.precision)), flush=True)
+        return
+    if args.matvec_only:
+        print(json.dumps(matvec_rates(tnt, B, torch, spec, precs=(args.precision,))), flush=True)
+        return
     log(f"[bench] {args.config}: L={spec.L} N={spec.N} d={spec.d} chi={spec.chi} U={spec.U} "
         f"precision={args.precision} warmup={args.warmup} steps={args.steps}")
 
@@ -288,6 +388,8 @@ def main():
               "rel_err_vs_oracle": (abs(rb[-1]["energy"] - e_ref) / abs(e_ref)) if e_ref else None}
         del envb, mpsb
 
+    bt = None if args.no_batched else batched_rates(tnt, B, torch, args.precision
+                                                     if args.precision != "fp64" else "fp32")
     mv = matvec_rates(tnt, B, torch, spec)
     mv_big = None
     if not args.no_chi1024 and spec.chi < 1024:
@@ -322,7 +424,7 @@ def main():
                    "max_residual": max(r["max_residual"] for r in res),
                    "max_trunc_eps": max(r["max_eps"] for r in res)},
         "fp64_path": fp64, "bf16x3_path": bf, "single_matvec_middle_bond": mv,
-        "single_matvec_chi1024": mv_big,
+        "single_matvec_chi1024": mv_big, "batched_64_chains": bt,
     }
     print(json.dumps(line), flush=True)
 

@@ -39,6 +39,28 @@ void SegLayout::build(Ctx& c, const std::vector<int64_t>& off, const std::vector
   TNT_HIP(hipStreamSynchronize(c.stream));
 }
 
+RunTable::~RunTable() {
+  if (done) (void)hipEventDestroy(done);
+}
+
+void RunTable::run(Ctx& c, const std::vector<CopyRun>& runs) {
+  if (runs.empty()) return;
+  const bool same = runs.size() == host.size() &&
+                    memcmp(runs.data(), host.data(), runs.size() * sizeof(CopyRun)) == 0;
+  if (!same) {
+    if (done) TNT_HIP(hipEventSynchronize(done));  // the last upload has read `host`
+    host = runs;
+    max_count = 0;
+    for (const CopyRun& r : host) max_count = std::max(max_count, r.count);
+    dev.ensure(&c.pool, host.size() * sizeof(CopyRun));
+    TNT_HIP(hipMemcpyAsync(dev.ptr, host.data(), host.size() * sizeof(CopyRun),
+                           hipMemcpyHostToDevice, c.stream));
+    if (!done) TNT_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    TNT_HIP(hipEventRecord(done, c.stream));
+  }
+  launch_copy_runs(dev.as<CopyRun>(), (int)host.size(), max_count, c.stream);
+}
+
 void build_batch(Ctx& c, BatchHeff& b, const std::vector<std::shared_ptr<HeffOp>>& ops,
                  const std::vector<int64_t>& n, int prec) {
   if (ops.empty() || ops.size() != n.size()) fail(TNT_E_ARG, "empty or inconsistent batch");
@@ -78,21 +100,14 @@ void bind_batch_envs(Ctx& c, BatchHeff& b, const std::vector<const double*>& Lre
   double* Rr = Li + b.L_tot;
   double* Ri = Rr + b.R_tot;
   std::vector<CopyRun> runs;
-  int64_t mx = 0;
   for (int i = 0; i < m; ++i) {
     const BatchPart& w = b.parts[i];
     runs.push_back(CopyRun{Lre[i], Lr + w.L_off, b.L_ext[i]});
     runs.push_back(CopyRun{Lim[i], Li + w.L_off, b.L_ext[i]});
     runs.push_back(CopyRun{Rre[i], Rr + w.R_off, b.R_ext[i]});
     runs.push_back(CopyRun{Rim[i], Ri + w.R_off, b.R_ext[i]});
-    mx = std::max({mx, b.L_ext[i], b.R_ext[i]});
   }
-  DevBuf t(&c.pool, runs.size() * sizeof(CopyRun));
-  TNT_HIP(hipMemcpyAsync(t.ptr, runs.data(), runs.size() * sizeof(CopyRun),
-                         hipMemcpyHostToDevice, c.stream));
-  launch_copy_runs(t.as<CopyRun>(), (int)runs.size(), mx, c.stream);
-  // the host run list must outlive the transfer
-  TNT_HIP(hipStreamSynchronize(c.stream));
+  b.env_runs.run(c, runs);
   b.op->bind_envs(Lr, Li, Rr, Ri);
 }
 

@@ -24,6 +24,19 @@ struct SegLayout {
   void build(Ctx& c, const std::vector<int64_t>& off, const std::vector<int64_t>& n);
 };
 
+// Device copy of a run list, re-uploaded only when the list changes (the
+// host list stays alive with the table, so no wait is needed after an
+// upload; an event guards against rewriting it while a copy is pending).
+struct RunTable {
+  std::vector<CopyRun> host;
+  DevBuf dev;
+  int64_t max_count = 0;
+  hipEvent_t done = nullptr;
+  ~RunTable();
+  // enqueue the copies of `runs` on the context stream
+  void run(Ctx& c, const std::vector<CopyRun>& runs);
+};
+
 struct BatchHeff {
   std::shared_ptr<HeffOp> op;       // merged operator over the batch vector
   std::vector<BatchPart> parts;     // per instance
@@ -31,6 +44,7 @@ struct BatchHeff {
   std::vector<int64_t> L_ext, R_ext;
   int64_t N = 0, L_tot = 0, R_tot = 0;
   DevBuf envs;                      // [L re | L im | R re | R im] of all instances
+  RunTable env_runs;
   SegLayout seg;
   int precision = TNT_FP64;
   int ninst() const { return (int)n.size(); }

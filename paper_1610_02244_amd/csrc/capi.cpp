@@ -4,7 +4,6 @@
 #include <new>
 #include <unordered_map>
 
-#include "batch.h"
 #include "capi_util.h"
 #include "plan.h"
 
@@ -18,6 +17,8 @@ struct PlanCache {
     std::shared_ptr<BatchHeff> b;
   };
   std::unordered_map<uint64_t, Batch> batch;
+  // batched C-ABI calls by the hash of all their raw descriptors
+  std::unordered_map<uint64_t, std::shared_ptr<BatchCall>> raw_batch;
   // operators by the hash of their parsed block structures
   std::unordered_map<uint64_t, std::shared_ptr<HeffOp>> heff;
   // the same operators by the hash of the raw host descriptors they were
@@ -136,6 +137,38 @@ HeffArgs parse_heff_args(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt
   return a;
 }
 
+uint64_t raw_hash_batch(int n, const tnt_btensor* const* L, const tnt_mpo_site* const* W1,
+                        const tnt_mpo_site* const* W2, const tnt_btensor* const* R,
+                        const tnt_btensor* const* theta, const tnt_btensor* const* out,
+                        int prec, uint64_t salt) {
+  uint64_t rh = salt ^ ((uint64_t)(uint32_t)prec << 32) ^ (uint64_t)(uint32_t)n;
+  for (int i = 0; i < n; ++i) {
+    if (!L[i] || !R[i] || !theta[i] || (out && !out[i])) fail(TNT_E_ARG, "null instance operand");
+    raw_btensor(rh, L[i]);
+    raw_btensor(rh, R[i]);
+    raw_btensor(rh, theta[i]);
+    if (out) raw_btensor(rh, out[i]);
+    raw_mpo(rh, W1[i]);
+    raw_mpo(rh, W2[i]);
+  }
+  return rh;
+}
+
+std::shared_ptr<BatchCall> find_batch_call(Ctx& c, uint64_t key) {
+  if (!c.plans) c.plans = new PlanCache();
+  auto it = c.plans->raw_batch.find(key);
+  return it == c.plans->raw_batch.end() ? nullptr : it->second;
+}
+
+void store_batch_call(Ctx& c, uint64_t key, std::shared_ptr<BatchCall> bc) {
+  if (!c.plans) c.plans = new PlanCache();
+  if (c.plans->raw_batch.size() >= 64) {
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    c.plans->raw_batch.clear();
+  }
+  c.plans->raw_batch[key] = std::move(bc);
+}
+
 std::shared_ptr<BatchHeff> cached_batch(Ctx& c, const std::vector<std::shared_ptr<HeffOp>>& ops,
                                         const std::vector<int64_t>& n, int prec) {
   Hasher H;
@@ -150,6 +183,7 @@ std::shared_ptr<BatchHeff> cached_batch(Ctx& c, const std::vector<std::shared_pt
   if (c.plans->batch.size() >= 256) {
     TNT_HIP(hipStreamSynchronize(c.stream));
     c.plans->batch.clear();
+    c.plans->raw_batch.clear();
   }
   auto b = std::make_shared<BatchHeff>();
   build_batch(c, *b, ops, n, prec);
@@ -247,6 +281,7 @@ tnt_status tnt_ctx_set_autotune(tnt_ctx ctx, int32_t on) {
     c.plans->heff.clear();
     c.plans->raw.clear();
     c.plans->batch.clear();
+    c.plans->raw_batch.clear();
   }
   TNT_API_END
 }
@@ -258,30 +293,38 @@ tnt_status tnt_heff2_apply_batched(tnt_ctx ctx, int32_t n, const tnt_btensor* co
   TNT_API_BEGIN(ctx)
   check_precision(precision);
   if (n < 1 || !L || !W1 || !W2 || !R || !theta || !out) fail(TNT_E_ARG, "null or empty batch");
-  // the instances' theta and out layouts as handed over
-  std::vector<ThetaH> tlay(n), olay(n);
-  std::vector<std::shared_ptr<HeffOp>> ops;
-  std::vector<int64_t> nn;
-  for (int i = 0; i < n; ++i) {
-    if (!L[i] || !R[i] || !theta[i] || !out[i]) fail(TNT_E_ARG, "null instance operand");
-    HeffArgs a = parse_heff_args(L[i], W1[i], W2[i], R[i], theta[i], out[i]);
-    if (L[i]->dtype != TNT_DT_F64 || R[i]->dtype != TNT_DT_F64 ||
-        theta[i]->dtype != TNT_DT_F64 || out[i]->dtype != TNT_DT_F64)
-      fail(TNT_E_ARG, "L, R, theta and out must be FP64 planes");
-    tlay[i] = a.th;
-    olay[i] = a.out;
-    // the batch vector holds every instance in its canonical packed layout
-    int64_t off = 0;
-    for (auto& kv : a.th.blocks) {
-      kv.second.off = off;
-      off += (int64_t)kv.second.rows * kv.second.cols;
+  const uint64_t rh = raw_hash_batch(n, L, W1, W2, R, theta, out, precision, 0x13198a2e03707344ULL);
+  std::shared_ptr<BatchCall> bc = find_batch_call(c, rh);
+  if (bc) {
+    // the same descriptors were parsed and validated before
+    for (int i = 0; i < n; ++i)
+      for (const tnt_btensor* t : {L[i], R[i], theta[i], (const tnt_btensor*)out[i]})
+        if (!t->re || !t->im) fail(TNT_E_ARG, "null plane");
+  } else {
+    bc = std::make_shared<BatchCall>();
+    std::vector<int64_t> nn;
+    for (int i = 0; i < n; ++i) {
+      HeffArgs a = parse_heff_args(L[i], W1[i], W2[i], R[i], theta[i], out[i]);
+      if (L[i]->dtype != TNT_DT_F64 || R[i]->dtype != TNT_DT_F64 ||
+          theta[i]->dtype != TNT_DT_F64 || out[i]->dtype != TNT_DT_F64)
+        fail(TNT_E_ARG, "L, R, theta and out must be FP64 planes");
+      bc->tlay.push_back(a.th);
+      bc->olay.push_back(a.out);
+      // the batch vector holds every instance in its canonical packed layout
+      int64_t off = 0;
+      for (auto& kv : a.th.blocks) {
+        kv.second.off = off;
+        off += (int64_t)kv.second.rows * kv.second.cols;
+      }
+      a.th.elems = a.th.extent = off;
+      a.out = a.th;
+      nn.push_back(off);
+      bc->ops.push_back(cached_heff(c, a, precision));
     }
-    a.th.elems = a.th.extent = off;
-    a.out = a.th;
-    nn.push_back(off);
-    ops.push_back(cached_heff(c, a, precision));
+    bc->b = cached_batch(c, bc->ops, nn, precision);
+    store_batch_call(c, rh, bc);
   }
-  auto B = cached_batch(c, ops, nn, precision);
+  BatchHeff& B = *bc->b;
   std::vector<const double *> Lr, Li, Rr, Ri;
   for (int i = 0; i < n; ++i) {
     Lr.push_back(static_cast<const double*>(L[i]->re));
@@ -289,29 +332,29 @@ tnt_status tnt_heff2_apply_batched(tnt_ctx ctx, int32_t n, const tnt_btensor* co
     Rr.push_back(static_cast<const double*>(R[i]->re));
     Ri.push_back(static_cast<const double*>(R[i]->im));
   }
-  bind_batch_envs(c, *B, Lr, Li, Rr, Ri);
-  DevBuf xb(&c.pool, std::max<int64_t>(1, 4 * B->N) * sizeof(double));
-  double* x = xb.as<double>();
-  double* y = x + 2 * B->N;
+  bind_batch_envs(c, B, Lr, Li, Rr, Ri);
+  bc->xy.ensure(&c.pool, std::max<int64_t>(1, 4 * B.N) * sizeof(double));
+  double* x = bc->xy.as<double>();
+  double* y = x + 2 * B.N;
   std::vector<CopyRun> in, back;
   for (int i = 0; i < n; ++i) {
-    const int64_t base = B->parts[i].x_off;
+    const int64_t base = B.parts[i].x_off;
     int64_t off = 0;
-    for (auto& kv : tlay[i].blocks) {
+    for (auto& kv : bc->tlay[i].blocks) {
       const BlockRef& src = kv.second;
-      const BlockRef& dst = olay[i].blocks.at(kv.first);
+      const BlockRef& dst = bc->olay[i].blocks.at(kv.first);
       const int64_t cnt = (int64_t)src.rows * src.cols;
       in.push_back(CopyRun{static_cast<const double*>(theta[i]->re) + src.off, x + base + off, cnt});
       in.push_back(
-          CopyRun{static_cast<const double*>(theta[i]->im) + src.off, x + B->N + base + off, cnt});
+          CopyRun{static_cast<const double*>(theta[i]->im) + src.off, x + B.N + base + off, cnt});
       back.push_back(CopyRun{y + base + off, static_cast<double*>(out[i]->re) + dst.off, cnt});
-      back.push_back(CopyRun{y + B->N + base + off, static_cast<double*>(out[i]->im) + dst.off, cnt});
+      back.push_back(CopyRun{y + B.N + base + off, static_cast<double*>(out[i]->im) + dst.off, cnt});
       off += cnt;
     }
   }
-  copy_runs(c, in);
-  B->op->apply(x, x + B->N, y, y + B->N, precision);
-  copy_runs(c, back);
+  bc->in.run(c, in);
+  B.op->apply(x, x + B.N, y, y + B.N, precision);
+  bc->back.run(c, back);
   TNT_HIP(hipGetLastError());
   TNT_API_END
 }

@@ -111,24 +111,33 @@ tnt_status tnt_lanczos_ground_batched(tnt_ctx ctx, int32_t n, const tnt_btensor*
   TNT_API_BEGIN(ctx)
   if (n < 1 || !L || !W1 || !W2 || !R || !theta || !r) fail(TNT_E_ARG, "null or empty batch");
   check_lanczos(p);
-  std::vector<HeffArgs> args(n);
-  std::vector<ThetaH> lay(n);
-  std::vector<std::shared_ptr<HeffOp>> ops;
-  std::vector<int64_t> nn;
-  for (int i = 0; i < n; ++i) {
-    if (!L[i] || !R[i] || !theta[i]) fail(TNT_E_ARG, "null instance operand");
-    HeffArgs a = parse_heff_args(L[i], W1[i], W2[i], R[i], theta[i], nullptr);
-    if (L[i]->dtype != TNT_DT_F64 || R[i]->dtype != TNT_DT_F64 || theta[i]->dtype != TNT_DT_F64)
-      fail(TNT_E_ARG, "L, R and theta must be FP64 planes");
-    if (a.th.blocks.empty()) fail(TNT_E_SHAPE, "theta has no block");
-    lay[i] = a.th;
-    a.th = packed(a.th);
-    a.out = a.th;
-    nn.push_back(a.th.elems);
-    ops.push_back(cached_heff(c, a, p->precision));
-    args[i] = std::move(a);
+  const uint64_t rh = raw_hash_batch(n, L, W1, W2, R, theta, nullptr, p->precision,
+                                     0xa4093822299f31d0ULL);
+  std::shared_ptr<BatchCall> bc = find_batch_call(c, rh);
+  if (bc) {
+    // the same descriptors were parsed and validated before
+    for (int i = 0; i < n; ++i)
+      for (const tnt_btensor* t : {L[i], R[i], (const tnt_btensor*)theta[i]})
+        if (!t->re || !t->im) fail(TNT_E_ARG, "null plane");
+  } else {
+    bc = std::make_shared<BatchCall>();
+    std::vector<int64_t> nn;
+    for (int i = 0; i < n; ++i) {
+      HeffArgs a = parse_heff_args(L[i], W1[i], W2[i], R[i], theta[i], nullptr);
+      if (L[i]->dtype != TNT_DT_F64 || R[i]->dtype != TNT_DT_F64 || theta[i]->dtype != TNT_DT_F64)
+        fail(TNT_E_ARG, "L, R and theta must be FP64 planes");
+      if (a.th.blocks.empty()) fail(TNT_E_SHAPE, "theta has no block");
+      bc->tlay.push_back(a.th);
+      a.th = packed(a.th);
+      a.out = a.th;
+      nn.push_back(a.th.elems);
+      bc->olay.push_back(a.th);
+      bc->ops.push_back(cached_heff(c, a, p->precision));
+    }
+    bc->b = cached_batch(c, bc->ops, nn, p->precision);
+    store_batch_call(c, rh, bc);
   }
-  auto B = cached_batch(c, ops, nn, p->precision);
+  BatchHeff& B = *bc->b;
   std::vector<const double *> Lr, Li, Rr, Ri;
   for (int i = 0; i < n; ++i) {
     Lr.push_back(static_cast<const double*>(L[i]->re));
@@ -136,29 +145,29 @@ tnt_status tnt_lanczos_ground_batched(tnt_ctx ctx, int32_t n, const tnt_btensor*
     Rr.push_back(static_cast<const double*>(R[i]->re));
     Ri.push_back(static_cast<const double*>(R[i]->im));
   }
-  bind_batch_envs(c, *B, Lr, Li, Rr, Ri);
-  DevBuf xb(&c.pool, std::max<int64_t>(1, 2 * B->N) * sizeof(double));
-  double* x = xb.as<double>();
+  bind_batch_envs(c, B, Lr, Li, Rr, Ri);
+  bc->xy.ensure(&c.pool, std::max<int64_t>(1, 2 * B.N) * sizeof(double));
+  double* x = bc->xy.as<double>();
   // every block of every instance into the batch vector, and back afterwards
   std::vector<CopyRun> in, back;
   for (int i = 0; i < n; ++i) {
-    const int64_t off = B->parts[i].x_off;
+    const int64_t off = B.parts[i].x_off;
     double* tre = static_cast<double*>(theta[i]->re);
     double* tim = static_cast<double*>(theta[i]->im);
-    for (auto& kv : args[i].th.blocks) {
-      const BlockRef& src = lay[i].blocks.at(kv.first);
+    for (auto& kv : bc->olay[i].blocks) {
+      const BlockRef& src = bc->tlay[i].blocks.at(kv.first);
       const int64_t cnt = (int64_t)src.rows * src.cols;
       in.push_back(CopyRun{tre + src.off, x + off + kv.second.off, cnt});
-      in.push_back(CopyRun{tim + src.off, x + B->N + off + kv.second.off, cnt});
+      in.push_back(CopyRun{tim + src.off, x + B.N + off + kv.second.off, cnt});
       back.push_back(CopyRun{x + off + kv.second.off, tre + src.off, cnt});
-      back.push_back(CopyRun{x + B->N + off + kv.second.off, tim + src.off, cnt});
+      back.push_back(CopyRun{x + B.N + off + kv.second.off, tim + src.off, cnt});
     }
   }
-  copy_runs(c, in);
-  BatchKrylov K;
+  bc->in.run(c, in);
   std::vector<LanczosOut> o;
-  lanczos_run_batched(c, *B, K, x, *p, o, nullptr);
-  copy_runs(c, back);
+  lanczos_run_batched(c, B, bc->K, x, *p, o, nullptr);
+  bc->back.run(c, back);
+  TNT_HIP(hipStreamSynchronize(c.stream));
   for (int i = 0; i < n; ++i) {
     r[i].E_ritz = o[i].E_ritz;
     r[i].E_refined = o[i].E;

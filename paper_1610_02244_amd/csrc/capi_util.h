@@ -5,6 +5,7 @@
 #include <new>
 #include <vector>
 
+#include "batch.h"
 #include "plan.h"
 
 namespace tnt {
@@ -48,7 +49,26 @@ HeffArgs parse_heff_args(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt
                          const tnt_btensor* R, const tnt_btensor* theta, const tnt_btensor* out);
 std::shared_ptr<HeffOp> cached_heff(Ctx& c, const HeffArgs& a, int prec);
 
-struct BatchHeff;
+// A batched C-ABI call remembered by the hash of all its raw descriptors:
+// the parsed instance layouts, operators, batch operator, and the call's own
+// batch vectors, Krylov space and gather / scatter tables (so that repeated
+// calls reuse buffers at stable addresses and skip every upload).
+struct BatchCall {
+  std::vector<std::shared_ptr<HeffOp>> ops;
+  std::shared_ptr<BatchHeff> b;
+  std::vector<ThetaH> tlay, olay;
+  DevBuf xy;
+  BatchKrylov K;
+  RunTable in, back;
+};
+// hash of the raw host metadata of n instances (out may be NULL)
+uint64_t raw_hash_batch(int n, const tnt_btensor* const* L, const tnt_mpo_site* const* W1,
+                        const tnt_mpo_site* const* W2, const tnt_btensor* const* R,
+                        const tnt_btensor* const* theta, const tnt_btensor* const* out,
+                        int prec, uint64_t salt);
+std::shared_ptr<BatchCall> find_batch_call(Ctx& c, uint64_t key);
+void store_batch_call(Ctx& c, uint64_t key, std::shared_ptr<BatchCall> bc);
+
 // Batch operator over these (cached) instance operators, built once per
 // distinct sequence of instance operators and kept in the plan cache.
 std::shared_ptr<BatchHeff> cached_batch(Ctx& c, const std::vector<std::shared_ptr<HeffOp>>& ops,

@@ -512,6 +512,7 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
   std::vector<int> rec(nc, 0);
   BatchKrylov K;
   DevBuf xall;
+  RunTable gather;
   double t_matvec = 0, t_lanczos = 0, t_gemm = 0, t_svd = 0, t_env = 0;
   int64_t launches = 0;
   for (int t = 0; t < T; ++t) {
@@ -559,7 +560,7 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
         runs.push_back(CopyRun{src, x + off, n});
         runs.push_back(CopyRun{src + n, x + B->N + off, n});
       }
-      copy_runs(c, runs);
+      gather.run(c, runs);
     }
     Timers tm;
     std::vector<LanczosOut> lo;
