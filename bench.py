@@ -236,7 +236,7 @@ def traffic_for(precision):
             t = json.load(f)
         with open(src, "rb") as f:
             h = hashlib.sha256(f.read()).hexdigest()
-        if t.get("gemm_hip_sha256") != h:
+        if t.get("gemm_packed_hip_sha256") != h:
             return None
         return t.get(precision, {}).get("bytes_per_launch")
     except Exception:
@@ -284,6 +284,46 @@ def summarize_trace(root):
                      "avg_us": v[1] / v[0] / 1e3} for k, v in top[:25]]}
 
 
+def pmc_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir,
+                kernel_prefix="tnt::packed_gemm_kernel<0,"):
+    """HBM bytes per launch of the dominant kernel from `rocprofv3 --pmc
+    FETCH_SIZE` and `--pmc WRITE_SIZE` runs (CSV output directories): the
+    per-dispatch averages over every dispatch whose name starts with
+    kernel_prefix, each counter scaled so that the same counter reads the
+    known size of a plain device copy (bench.py --calibrate-copy runs)."""
+    import csv
+
+    def rows(root, counter):
+        out = []
+        for dp, _, fs in os.walk(root):
+            for f in fs:
+                if f.endswith("counter_collection.csv"):
+                    with open(os.path.join(dp, f)) as fh:
+                        for r in csv.DictReader(fh):
+                            if r["Counter_Name"] == counter:
+                                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return out
+
+    def factor(root, counter):
+        vals = [v for k, v in rows(root, counter) if "copyBuffer" in k]
+        if not vals:
+            raise SystemExit(f"no copy kernel in the calibration run {root}")
+        return (64 * 1024 * 1024 * 4 / 1024) / (sum(vals) / len(vals))
+
+    res = {}
+    for name, root, cal, counter in (("fetch", fetch_dir, cal_fetch_dir, "FETCH_SIZE"),
+                                     ("write", write_dir, cal_write_dir, "WRITE_SIZE")):
+        vals = [v for k, v in rows(root, counter)
+                if k.replace("void ", "").startswith(kernel_prefix)]
+        f = factor(cal, counter)
+        res[name] = {"dispatches": len(vals), "kib_per_dispatch_raw": sum(vals) / len(vals),
+                     "scale": f, "bytes_per_launch": sum(vals) / len(vals) * 1024 * f}
+    res["bytes_per_launch"] = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
+    with open(os.path.join(ROOT, "paper_1610_02244_amd", "csrc", "gemm_packed.hip"), "rb") as fh:
+        res["gemm_packed_hip_sha256"] = hashlib.sha256(fh.read()).hexdigest()
+    return res
+
+
 def golden_energy(config, total_sweeps):
     names = {("cfg1", 2): "cfg1", ("cfg2", 1): "cfg2", ("cfg2", 2): "cfg2_2sweeps"}
     case = names.get((config, total_sweeps))
@@ -318,9 +358,16 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of 256 MiB each way (three times), the "
                          "reference that scales the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--pmc-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR",
+                                                       "CAL_WRITE_DIR"),
+                    help="print the scaled HBM bytes per FP32 packed-GEMM launch from rocprofv3 "
+                         "--pmc CSV runs and exit")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="print timed-region kernel statistics of a rocprofv3 CSV trace and exit")
     args = ap.parse_args()
+    if args.pmc_traffic:
+        print(json.dumps(pmc_traffic(*args.pmc_traffic), indent=1))
+        return
     if args.summarize_trace:
         print(json.dumps(summarize_trace(args.summarize_trace), indent=1))
         return
