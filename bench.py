@@ -226,9 +226,10 @@ def cpu_baseline(spec, budget_s=12.0):
                       f"the same chain shape, {dt:.1f}s"}
 
 
-def traffic_for(precision):
-    """HBM bytes per grouped-GEMM launch from the committed PMC summary, if the
-    kernel source is unchanged since the counters were taken."""
+def traffic_for(config, precision):
+    """HBM bytes per grouped-GEMM launch of this workload from the committed
+    PMC summary, if the kernel source is unchanged since the counters were
+    taken (else None)."""
     path = os.path.join(ROOT, "profiles", "gemm_traffic.json")
     src = os.path.join(ROOT, "paper_1610_02244_amd", "csrc", "gemm_packed.hip")
     try:
@@ -238,7 +239,7 @@ def traffic_for(precision):
             h = hashlib.sha256(f.read()).hexdigest()
         if t.get("gemm_packed_hip_sha256") != h:
             return None
-        return t.get(precision, {}).get("bytes_per_launch")
+        return t.get("workloads", {}).get(config, {}).get(precision, {}).get("bytes_per_launch")
     except Exception:
         return None
 
@@ -443,7 +444,7 @@ def main():
         mv_big = matvec_rates(tnt, B, torch, synth.CONFIGS["cfg3"])
     peak = PEAK[args.precision]
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": traffic_for(args.precision),
+            "frac": achieved / peak, "traffic": traffic_for(args.config, args.precision),
             "kernel": ("grouped_gemm_kernel (FP64)" if args.precision == "fp64" else
                        f"packed_gemm_kernel ({args.precision})") + ", H_eff steps 1 and 4",
             "launches": int(launches),
