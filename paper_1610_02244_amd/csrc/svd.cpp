@@ -152,6 +152,16 @@ std::vector<Sector> sectors_of(const ThetaH& th) {
   return out;
 }
 
+// Batch size class of an n x n sector eigenproblem.
+int padded_size(int n) {
+  static const int sizes[] = {8,   16,  24,  32,  48,   64,   96,   128,  160,  192,  256,
+                              320, 384, 512, 640, 768, 1024, 1280, 1536, 2048, 2560, 3072,
+                              4096};
+  for (int v : sizes)
+    if (n <= v) return v;
+  return (n + 511) / 512 * 512;
+}
+
 int index_of(const std::vector<std::pair<int, int>>& v, int first) {
   for (size_t i = 0; i < v.size(); ++i)
     if (v[i].first == first) return (int)i;
@@ -224,49 +234,89 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
   // the row-major buffer read column-major is G (absorb right) or conj(G) (left)
   launch_interleave(g, g + gsize, z.as<double>(), gsize, right ? 0 : 1, c.stream);
   // --- FP64 Hermitian eigendecompositions, one per sector -------------------
-  // The sectors are independent and each decomposition is a long chain of
-  // small launches, so they run concurrently on the side streams (largest
-  // first, greedy by n^3), forked from and joined back into the main stream.
+  // Each decomposition is a long chain of small, latency-bound launches, so
+  // sectors of similar size go through one strided-batched call: every
+  // sector is padded to its bucket's size (G plus negative eigenvalues below
+  // its spectrum, mixed by a fixed reflector so that no exact split remains;
+  // see the padding kernels).  The buckets run concurrently on the side
+  // streams, forked from and joined back into the main stream; G's
+  // eigenpairs are extracted back into z and W.
   rocblas_handle h = blas(c);
   ensure_side(c);
   double* W = ev.as<double>();
-  double* E = W + esize;
+  struct Bucket {
+    int npad = 0;
+    std::vector<int> secs;
+    std::vector<PadTask> tasks;
+    DevBuf slots, w, e, tab;
+  };
+  std::map<int, Bucket> buckets;
+  std::vector<int> info_pos(secs.size());
   {
-    std::vector<int> order(secs.size());
-    std::iota(order.begin(), order.end(), 0);
+    for (size_t i = 0; i < secs.size(); ++i) {
+      const int np = padded_size(secs[i].n);
+      buckets[np].npad = np;
+      buckets[np].secs.push_back((int)i);
+    }
+    std::vector<Bucket*> order;
+    for (auto& kv : buckets) order.push_back(&kv.second);
+    // heaviest first (cost ~ npad^3, batches ~ one matrix)
     std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return secs[a].n > secs[b].n; });
-    double load[Ctx::kSide] = {};
-    bool used[Ctx::kSide] = {};
+                     [](const Bucket* x, const Bucket* y) { return x->npad > y->npad; });
     TNT_HIP(hipEventRecord(c.side_ev[Ctx::kSide], c.stream));
-    for (int i : order) {
-      const Sector& s = secs[i];
-      int k = 0;
-      for (int q = 1; q < Ctx::kSide; ++q)
-        if (load[q] < load[k]) k = q;
+    bool used[Ctx::kSide] = {};
+    int ipos = 0, k = 0;
+    for (Bucket* bk : order) {
+      const int np = bk->npad, cnt = (int)bk->secs.size();
+      const int64_t slot = (int64_t)np * np;
+      int maxn = 1;
+      for (int q = 0; q < cnt; ++q) {
+        const Sector& sc = secs[bk->secs[q]];
+        bk->tasks.push_back(PadTask{sc.gbase, q * slot, (int64_t)q * np, sc.ebase, sc.n, np});
+        info_pos[bk->secs[q]] = ipos + q;
+        maxn = std::max(maxn, sc.n);
+      }
+      bk->slots = DevBuf(&c.pool, (size_t)2 * slot * cnt * sizeof(double));
+      bk->w = DevBuf(&c.pool, (size_t)np * cnt * sizeof(double));
+      // e: the embedding's work vectors (2 np per slot), then heevd's off-diagonals
+      bk->e = DevBuf(&c.pool, (size_t)2 * np * cnt * sizeof(double));
+      bk->tab = DevBuf(&c.pool, bk->tasks.size() * sizeof(PadTask));
+      hipStream_t ss = c.side[k];
       if (!used[k]) {
-        TNT_HIP(hipStreamWaitEvent(c.side[k], c.side_ev[Ctx::kSide], 0));
+        TNT_HIP(hipStreamWaitEvent(ss, c.side_ev[Ctx::kSide], 0));
         used[k] = true;
       }
-      load[k] += (double)s.n * s.n * s.n + 1e6;
-      auto* A = reinterpret_cast<rocblas_double_complex*>(z.as<double>()) + s.gbase;
-      if (rocsolver_zheevd(static_cast<rocblas_handle>(c.side_blas[k]), rocblas_evect_original,
-                           rocblas_fill_upper, s.n, A, s.n, W + s.ebase, E + s.ebase,
-                           info.as<rocblas_int>() + i) != rocblas_status_success)
-        fail(TNT_E_HIP, "rocsolver_zheevd failed");
+      TNT_HIP(hipMemcpyAsync(bk->tab.ptr, bk->tasks.data(), bk->tasks.size() * sizeof(PadTask),
+                             hipMemcpyHostToDevice, ss));
+      launch_pad_embed(bk->tab.as<PadTask>(), cnt, maxn, np, z.as<double>(), bk->e.as<double>(),
+                       bk->slots.as<double>(), ss);
+      if (rocsolver_zheevd_strided_batched(
+              static_cast<rocblas_handle>(c.side_blas[k]), rocblas_evect_original,
+              rocblas_fill_upper, np, reinterpret_cast<rocblas_double_complex*>(bk->slots.ptr),
+              np, slot, bk->w.as<double>(), np, bk->e.as<double>(), np,
+              info.as<rocblas_int>() + ipos, cnt) != rocblas_status_success)
+        fail(TNT_E_HIP, "rocsolver_zheevd_strided_batched failed");
+      launch_pad_extract(bk->tab.as<PadTask>(), cnt, maxn, bk->slots.as<double>(),
+                         bk->w.as<double>(), z.as<double>(), W, ss);
+      ipos += cnt;
+      k = (k + 1) % Ctx::kSide;
     }
-    for (int k = 0; k < Ctx::kSide; ++k) {
-      if (!used[k]) continue;
-      TNT_HIP(hipEventRecord(c.side_ev[k], c.side[k]));
-      TNT_HIP(hipStreamWaitEvent(c.stream, c.side_ev[k], 0));
+    for (int q = 0; q < Ctx::kSide; ++q) {
+      if (!used[q]) continue;
+      TNT_HIP(hipEventRecord(c.side_ev[q], c.side[q]));
+      TNT_HIP(hipStreamWaitEvent(c.stream, c.side_ev[q], 0));
     }
   }
   std::vector<double> mu(esize);
   std::vector<rocblas_int> hinfo(secs.size());
   TNT_HIP(hipMemcpyAsync(mu.data(), W, esize * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-  TNT_HIP(hipMemcpyAsync(hinfo.data(), info.ptr, secs.size() * sizeof(rocblas_int),
-                         hipMemcpyDeviceToHost, c.stream));
-  TNT_HIP(hipStreamSynchronize(c.stream));
+  {
+    std::vector<rocblas_int> raw(secs.size());
+    TNT_HIP(hipMemcpyAsync(raw.data(), info.ptr, secs.size() * sizeof(rocblas_int),
+                           hipMemcpyDeviceToHost, c.stream));
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    for (size_t i = 0; i < secs.size(); ++i) hinfo[i] = raw[info_pos[i]];
+  }
   // divide and conquer can fail on large clusters of (near-)zero eigenvalues;
   // redo such a sector with the Jacobi eigensolver from the kept Gram planes
   for (size_t i = 0; i < secs.size(); ++i) {

@@ -411,4 +411,168 @@ void launch_interleave(const double* re, const double* im, double* z, int64_t n,
   hipLaunchKernelGGL(interleave_kernel, dim3(grid_for(n)), dim3(256), 0, s, re, im, z, n, conj);
 }
 
+// ---------------------------------------------------------------------------
+// padded Hermitian batches
+//
+// A sector's n x n Gram matrix G goes into an npad x npad slot as
+// M = Q A Q with A = diag(G, D), D = -s diag(1 + j/m) (m = npad - n,
+// s = trace G, or 1 if that is zero) and Q = I - 2 u u^T / (u^T u) for a
+// fixed irregular positive u.  A alone would make the tridiagonal reduction
+// split exactly at the block boundary and at every padding row, and the
+// divide-and-conquer solver returns non-finite vectors for such splits; Q
+// mixes the blocks so M has no exact split while sharing A's spectrum.  D's
+// distinct values lie below G's (positive semidefinite) spectrum, so G's
+// eigenpairs are the last n of the ascending ones, with vectors Q v.
+// ---------------------------------------------------------------------------
+__device__ inline double pad_u(int i) { return 1.0 + 0.5 * sin(0.7 + 2.3 * (double)i); }
+
+// broadcast of block_sum to every thread (256 threads)
+__device__ inline double block_sum_all(double v, double* sh, double* out) {
+  const double r = block_sum(v, sh);
+  if (threadIdx.x == 0) *out = r;
+  __syncthreads();
+  return *out;
+}
+
+// vec[2 (w_src + i)] = (G u)_i for i < n: one wave per row, using column i
+// of G (G Hermitian: row i of G is the conjugate of column i).
+__global__ __launch_bounds__(256) void pad_gvec_kernel(const PadTask* __restrict__ tasks,
+                                                       const double* __restrict__ src,
+                                                       double* __restrict__ vec) {
+  const PadTask t = tasks[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= t.n) return;  // whole wave leaves together
+  const double* col = src + 2 * (t.src_off + (int64_t)i * t.n);
+  double ar = 0, ai = 0;
+  for (int k = lane; k < t.n; k += 64) {
+    const double u = pad_u(k);
+    ar += col[2 * k] * u;
+    ai -= col[2 * k + 1] * u;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    ar += __shfl_down(ar, o, 64);
+    ai += __shfl_down(ai, o, 64);
+  }
+  if (lane == 0) {
+    vec[2 * (t.w_src + i)] = ar;
+    vec[2 * (t.w_src + i) + 1] = ai;
+  }
+}
+
+__global__ __launch_bounds__(256) void pad_embed_kernel(const PadTask* __restrict__ tasks,
+                                                        const double* __restrict__ src,
+                                                        const double* __restrict__ vec,
+                                                        double* __restrict__ dst) {
+  __shared__ double sh[4];
+  __shared__ double bc;
+  const PadTask t = tasks[blockIdx.y];
+  const int n = t.n, np = t.npad, m = np - n;
+  // scalars of the slot (every block computes them: O(npad) from cache)
+  double tr = 0, nu = 0, bg = 0, p0 = 0, p1 = 0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const double u = pad_u(i);
+    nu += u * u;
+    if (i < n) {
+      tr += src[2 * (t.src_off + i + (int64_t)i * n)];
+      bg += u * vec[2 * (t.w_src + i)];
+    } else {
+      p0 += u * u;
+      p1 += u * u * (double)(i - n);
+    }
+  }
+  tr = block_sum_all(tr, sh, &bc);
+  nu = block_sum_all(nu, sh, &bc);
+  bg = block_sum_all(bg, sh, &bc);
+  p0 = block_sum_all(p0, sh, &bc);
+  p1 = block_sum_all(p1, sh, &bc);
+  const double sc = tr > 0 ? tr : 1.0;
+  const double rm = m > 0 ? 1.0 / m : 0.0;
+  // beta = u^T A u; d_i = -sc (1 + (i - n) / m) on the padding rows
+  const double beta = bg - sc * (p0 + p1 * rm);
+  const double f1 = 2.0 / nu, f2 = 4.0 * beta / (nu * nu);
+  const int64_t tot = (int64_t)np * np;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % np), c = (int)(e / np);
+    double ar = 0, ai = 0;
+    if (r < n && c < n) {
+      const int64_t k = t.src_off + r + (int64_t)c * n;
+      ar = src[2 * k];
+      ai = src[2 * k + 1];
+    } else if (r == c) {
+      ar = -sc * (1.0 + (r - n) * rm);
+    }
+    const double ur = pad_u(r), uc = pad_u(c);
+    double wrr, wri, wcr, wci;  // (A u)_r and (A u)_c
+    if (r < n) {
+      wrr = vec[2 * (t.w_src + r)];
+      wri = vec[2 * (t.w_src + r) + 1];
+    } else {
+      wrr = -sc * (1.0 + (r - n) * rm) * ur;
+      wri = 0;
+    }
+    if (c < n) {
+      wcr = vec[2 * (t.w_src + c)];
+      wci = vec[2 * (t.w_src + c) + 1];
+    } else {
+      wcr = -sc * (1.0 + (c - n) * rm) * uc;
+      wci = 0;
+    }
+    // M = A - f1 (u w^H + w u^T) + f2 u u^T
+    dst[2 * (t.dst_off + e)] = ar - f1 * (ur * wcr + wrr * uc) + f2 * ur * uc;
+    dst[2 * (t.dst_off + e) + 1] = ai - f1 * (-ur * wci + wri * uc);
+  }
+}
+
+void launch_pad_embed(const PadTask* t, int ntask, int max_n, int max_npad, const double* src_z,
+                      double* vec, double* dst_z, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(pad_gvec_kernel, dim3((max_n + 3) / 4, ntask), dim3(256), 0, s, t, src_z,
+                     vec);
+  const int gx = grid_for((int64_t)max_npad * max_npad, 256, 512);
+  hipLaunchKernelGGL(pad_embed_kernel, dim3(gx, ntask), dim3(256), 0, s, t, src_z, vec, dst_z);
+}
+
+// One block per kept column c < n: v = slot column npad - n + c, rho = u^T v,
+// z[:, c] = (v - 2 u rho / (u^T u)) restricted to the first n rows.
+__global__ __launch_bounds__(256) void pad_extract_kernel(const PadTask* __restrict__ tasks,
+                                                          const double* __restrict__ slot_z,
+                                                          const double* __restrict__ slot_w,
+                                                          double* __restrict__ z,
+                                                          double* __restrict__ w) {
+  __shared__ double sh[4];
+  __shared__ double bc;
+  const PadTask t = tasks[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= t.n) return;  // uniform over the block
+  const int np = t.npad, sft = np - t.n;
+  const double* v = slot_z + 2 * (t.dst_off + (int64_t)(sft + c) * np);
+  double rr = 0, ri = 0, nu = 0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const double u = pad_u(i);
+    rr += u * v[2 * i];
+    ri += u * v[2 * i + 1];
+    nu += u * u;
+  }
+  rr = block_sum_all(rr, sh, &bc);
+  ri = block_sum_all(ri, sh, &bc);
+  nu = block_sum_all(nu, sh, &bc);
+  const double f = 2.0 / nu;
+  double* out = z + 2 * (t.src_off + (int64_t)c * t.n);
+  for (int r = threadIdx.x; r < t.n; r += blockDim.x) {
+    const double u = pad_u(r);
+    out[2 * r] = v[2 * r] - f * u * rr;
+    out[2 * r + 1] = v[2 * r + 1] - f * u * ri;
+  }
+  if (threadIdx.x == 0) w[t.w_dst + c] = slot_w[t.w_src + sft + c];
+}
+
+void launch_pad_extract(const PadTask* t, int ntask, int max_n, const double* slot_z,
+                        const double* slot_w, double* z, double* w, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(pad_extract_kernel, dim3(max_n, ntask), dim3(256), 0, s, t, slot_z, slot_w,
+                     z, w);
+}
+
 }  // namespace tnt

@@ -167,3 +167,39 @@ def test_svd_truncate_parity(tnt, absorb, rules):
             V = np.concatenate([got["B"][(m, s2)] for s2 in range(d) if (m, s2) in got["B"]],
                                axis=1)
             np.testing.assert_allclose(V @ V.conj().T, np.eye(k), atol=1e-13)
+
+
+@pytest.mark.parametrize("absorb", ["right", "left"])
+def test_svd_truncate_large_sectors_with_zero_rows(tnt, absorb):
+    """Sectors of 100-200 rows (the eigensolver's divide-and-conquer range),
+    with every fifth row and column of theta exactly zero: the Gram matrices
+    then have exact zero rows, which must not break the padded batched
+    eigensolve."""
+    d = 3
+    L = {10: 40, 11: 65, 12: 50, 13: 20}
+    R = {12: 30, 13: 55, 14: 70, 15: 45, 16: 10}
+    rng = np.random.Generator(np.random.PCG64(21))
+    th = synth.random_theta(L, R, d, rng)
+    for k in th:
+        th[k][::5, :] = 0
+        th[k][:, ::5] = 0
+    chi_max = 150
+    print(f"[svd zero rows {absorb}]", flush=True)
+    ref = osvd.svd_truncate(th, L, R, d, chi_max, absorb=absorb)
+    got = tnt.svd_truncate(tnt.theta(th), absorb=absorb, chi_max=chi_max)
+    assert got["chi"] == ref["chi"]
+    assert got["bond"] == ref["bond"]
+    n = max(sum(L.values()), sum(R.values()))
+    lam0 = np.concatenate([ref["lambdas"][m] for m in ref["bond"]]).max()
+    for m in ref["bond"]:
+        r_ = ref["lambdas"][m]
+        assert np.all(np.isfinite(got["lambdas"][m]))
+        tol = 1e-12 * r_ + 32 * n * 2.2e-16 * lam0 ** 2 / r_
+        assert np.all(np.abs(got["lambdas"][m] - r_) <= tol), m
+    for (qa, s1, s2) in blocks.theta_keys(L, R, d):
+        mid = qa + s1
+        if mid not in ref["bond"]:
+            continue
+        g = got["A"][(qa, s1)] @ got["B"][(mid, s2)]
+        r = ref["A"][(qa, s1)] @ ref["B"][(mid, s2)]
+        np.testing.assert_allclose(g, r, atol=1e-10)
