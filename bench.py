@@ -452,7 +452,8 @@ def main():
             "avg_flops_per_launch": gemm_flops / launches if launches else None}
     cpu = None if args.no_cpu_baseline else cpu_baseline(spec)
     per = {k: sum(r[k] for r in res) / len(res) for k in
-           ("seconds_total", "seconds_matvec", "seconds_lanczos", "seconds_svd", "seconds_env")}
+           ("seconds_total", "seconds_matvec", "seconds_lanczos", "seconds_svd", "seconds_env",
+            "seconds_theta", "seconds_setup")}
     line = {
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,

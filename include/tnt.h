@@ -359,6 +359,9 @@ typedef struct {
   double gemm_flops;      /* algorithmic flops of the iteration matvecs' grouped-GEMM launches */
   double seconds_gemm;    /* device time of those launches (HIP events)      */
   int64_t gemm_launches;  /* number of those launches                        */
+  double seconds_theta;   /* wall time of theta formation                   */
+  double seconds_setup;   /* wall time of H_eff plan lookup or build,
+                             environment packing and Krylov reservation     */
 } tnt_sweep_result;
 
 /* One sweep: right pass over bonds 1..L-1 then left pass L-1..1 (each:

@@ -80,7 +80,8 @@ class SweepResult(C.Structure):
                 ("seconds_matvec", C.c_double), ("seconds_lanczos", C.c_double),
                 ("seconds_svd", C.c_double), ("seconds_env", C.c_double),
                 ("gemm_flops", C.c_double), ("seconds_gemm", C.c_double),
-                ("gemm_launches", C.c_int64)]
+                ("gemm_launches", C.c_int64), ("seconds_theta", C.c_double),
+                ("seconds_setup", C.c_double)]
 
 
 # name -> (restype, argtypes); mirrors include/tnt.h

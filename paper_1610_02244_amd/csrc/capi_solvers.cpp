@@ -436,6 +436,8 @@ static void fill_result(const SweepStats& st, tnt_sweep_result* r) {
   r->seconds_lanczos = st.t_lanczos;
   r->seconds_svd = st.t_svd;
   r->seconds_env = st.t_env;
+  r->seconds_theta = st.t_theta;
+  r->seconds_setup = st.t_setup;
   r->gemm_flops = st.gemm_flops;
   r->seconds_gemm = st.t_gemm;
   r->gemm_launches = st.gemm_launches;

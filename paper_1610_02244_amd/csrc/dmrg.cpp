@@ -424,7 +424,10 @@ void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats&
   for (int pass = 0; pass < 2; ++pass) {
     for (int step = 0; step < L - 1; ++step) {
       const int j = pass == 0 ? 1 + step : L - 1 - step;
+      const double tt0 = now_s();
       ThetaH th = form_theta(c, m, j, theta);
+      const double tt1 = now_s();
+      st.t_theta += tt1 - tt0;
       // H_eff on (j, j+1): L_{j-1}, W_j, W_{j+1}, R_{j+2}
       HeffArgs a;
       a.w1 = e.W[j - 1];
@@ -438,6 +441,7 @@ void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats&
       K.reserve(c, p.lanczos.kmax, th.elems);
       Timers tm;
       const double tl0 = now_s();
+      st.t_setup += tl0 - tt1;
       LanczosOut lo =
           lanczos_run(c, *op, K, theta.as<double>(), p.lanczos, c.graphs ? nullptr : &tm);
       const double tl1 = now_s();
@@ -513,7 +517,7 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
   BatchKrylov K;
   DevBuf xall;
   RunTable gather;
-  double t_matvec = 0, t_lanczos = 0, t_gemm = 0, t_svd = 0, t_env = 0;
+  double t_matvec = 0, t_lanczos = 0, t_gemm = 0, t_svd = 0, t_env = 0, t_theta = 0, t_setup = 0;
   int64_t launches = 0;
   for (int t = 0; t < T; ++t) {
     struct Act { int i, j, pass; };
@@ -532,7 +536,10 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
     for (const Act& a : act) {
       MpsH& m = *ms[a.i];
       EnvS& e = *es[a.i];
+      const double tt0 = now_s();
       ThetaH th = form_theta(c, m, a.j, theta[a.i]);
+      const double tt1 = now_s();
+      t_theta += tt1 - tt0;
       HeffArgs h;
       h.w1 = e.W[a.j - 1];
       h.w2 = e.W[a.j];
@@ -541,6 +548,7 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
       h.L = e.Llay[a.j - 1];
       h.R = e.Rlay[a.j + 2];
       ops.push_back(cached_heff(c, h, lp.precision));
+      t_setup += now_s() - tt1;
       nn.push_back(th.elems);
       ths.push_back(std::move(th));
       Lr.push_back(e.Lre(a.j - 1));
@@ -548,6 +556,7 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
       Rr.push_back(e.Rre(a.j + 2));
       Ri.push_back(e.Rim(a.j + 2));
     }
+    const double tb0 = now_s();
     auto B = cached_batch(c, ops, nn, lp.precision);
     bind_batch_envs(c, *B, Lr, Li, Rr, Ri);
     xall.ensure(&c.pool, std::max<int64_t>(1, 2 * B->N) * sizeof(double));
@@ -562,6 +571,7 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
       }
       gather.run(c, runs);
     }
+    t_setup += now_s() - tb0;
     Timers tm;
     std::vector<LanczosOut> lo;
     const double tl0 = now_s();
@@ -628,6 +638,8 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
     s.gemm_launches = launches;
     s.t_svd = t_svd;
     s.t_env = t_env;
+    s.t_theta = t_theta;
+    s.t_setup = t_setup;
   }
 }
 

@@ -55,6 +55,16 @@ std::vector<int2> HostGemm::build_tiles(int cfg) const {
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) bins[x].push_back(int2{i, a | (b << 16)});
   }
+  // within a bin, longest tiles (largest K) first: the dispatcher hands
+  // tiles out in table order, so the short ones fill the tail
+  std::vector<int64_t> tk(nt);
+  for (int i = 0; i < nt; ++i) {
+    int64_t ksum = 0;
+    for (int s = 0; s < tasks[i].nseg; ++s) ksum += segs[tasks[i].seg0 + s].K;
+    tk[i] = ksum;
+  }
+  for (auto& b : bins)
+    std::stable_sort(b.begin(), b.end(), [&](const int2& u, const int2& v) { return tk[u.x] > tk[v.x]; });
   size_t slots = 0;
   for (auto& b : bins) slots = std::max(slots, b.size());
   tiles.assign(slots * 8, int2{-1, 0});
