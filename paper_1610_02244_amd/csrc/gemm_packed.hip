@@ -8,10 +8,19 @@
 // fixed order, no atomics.
 //
 // Loads: a 16-byte group holds G consecutive k of one row and plane (G = 4
-// floats or 8 bf16).  Loader item = (row, group), one 16-byte global load
+// floats or 8 bf16).  Loader item = (row, group), one 16-byte buffer load
 // and one 16-byte LDS store per plane; a chunk is 4 groups (BK = 4 G).  The
-// LDS row of an operand is 4 groups plus one padding group (80 bytes), which
-// keeps the 16 rows read by one lane slot on distinct banks.
+// chunk's base address is uniform and a lane adds only its row and group
+// offset; rows outside the block and groups at or beyond K are given an
+// offset past the buffer's range and come back as zeros, so the loop carries
+// almost no per-lane address arithmetic.  The LDS row of an operand is 4
+// groups plus one padding group (80 bytes), which keeps the 16 rows read by
+// one lane slot on distinct banks.
+//
+// Every fragment of the wave is read from LDS (rows outside the block are
+// zero there); MFMAs on fragments wholly outside the block are skipped, and
+// tiles whose fragments are all live run a copy of the K walk without those
+// tests.
 //
 // FP32 (16x16x4 MFMA): lane slot s reads group s of its row, i.e. k = 4 s ..
 // 4 s + 3; MFMA number kk of the chunk takes element kk of every slot's
@@ -29,6 +38,8 @@
 // schoolbook form on the four planes already in LDS:
 //   P1 += Ar Br,  P2 += Ai Bi,  P3 += Ar Bi + Ai Br;  Cr = P1 - P2, Ci = P3.
 // (Gauss's form would need two more split planes for the sums.)
+#include <type_traits>
+
 #include "mfma.h"
 
 namespace tnt {
@@ -51,23 +62,34 @@ struct PLoader {
   static constexpr int PER = (ITEMS + NT - 1) / NT;
   static constexpr int PL = Fmt<FMT>::PL, G = Fmt<FMT>::G, EB = Fmt<FMT>::EB;
   u32x4 v[PER][PL];
-  // groups at or beyond K and rows at or beyond `rows` load as zero; a group
-  // below K lies inside the row's padded storage (kernels.h)
-  __device__ inline void load(const char* __restrict__ base, int64_t plane_bytes, int64_t off,
-                              int ld, int r0, int rows, int k0, int K, int tid) {
+  int rowc[PER];  // the item's row in the segment's operand block, or -1
+  int jb[PER];    // element offset of the item's group in the chunk
+  __device__ inline void init(int r0, int rows, int tid) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int item = tid + e * NT;
       const int r = item >> 2, j = item & 3;
-      const int kb = k0 + G * j;
-      if (item < ITEMS && r0 + r < rows && kb < K) {
-        const char* p = base + (off + (int64_t)(r0 + r) * ld + kb) * EB;
+      rowc[e] = (item < ITEMS && r0 + r < rows) ? r0 + r : -1;
+      jb[e] = G * j;
+    }
+  }
+  // Buffer loads: the chunk's base address is uniform (scalar registers); a
+  // lane's offset is its row times ld plus its group.  Rows outside the block
+  // and groups at or beyond K get an offset past the buffer's range, which
+  // the hardware returns as zero without touching memory.
+  __device__ inline void load(const char* __restrict__ base, int64_t plane_bytes, int64_t off,
+                              int ld, int k0, int K) {
+    const char* p = base + (off + k0) * EB;
+    const int kv = K - k0;
 #pragma unroll
-        for (int pl = 0; pl < PL; ++pl)
-          v[e][pl] = *reinterpret_cast<const u32x4*>(p + pl * plane_bytes);
-      } else {
+    for (int e = 0; e < PER; ++e) {
+      const bool ok = rowc[e] >= 0 && jb[e] < kv;
+      const uint32_t o = ok ? (uint32_t)(rowc[e] * ld + jb[e]) * EB : 0x80000000u;
 #pragma unroll
-        for (int pl = 0; pl < PL; ++pl) v[e][pl] = u32x4{0u, 0u, 0u, 0u};
+      for (int pl = 0; pl < PL; ++pl) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<char*>(p + pl * plane_bytes), (short)0, 0x7fffffff, 0x00020000);
+        v[e][pl] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0));
       }
     }
   }
@@ -99,7 +121,7 @@ __global__ __launch_bounds__(NT) void packed_gemm_kernel(
   __shared__ u32x4 Bs[STAGES][PL][BN][ROWQ];
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
   const int frow = lane & 15, slot = lane >> 4;
 
@@ -122,9 +144,11 @@ __global__ __launch_bounds__(NT) void packed_gemm_kernel(
 
   PLoader<FMT, BM> la;
   PLoader<FMT, BN> lb;
+  la.init(m0, M, tid);
+  lb.init(n0, N, tid);
   auto load = [&](const GemmSeg& sg, int k0) {
-    la.load(A, a_pb, sg.a_off, sg.lda, m0, M, k0, sg.K, tid);
-    lb.load(B, b_pb, sg.b_off, sg.ldb, n0, N, k0, sg.K, tid);
+    la.load(A, a_pb, sg.a_off, sg.lda, k0, sg.K);
+    lb.load(B, b_pb, sg.b_off, sg.ldb, k0, sg.K);
   };
   auto store = [&](int st) {
     la.store(As[st], tid);
@@ -134,30 +158,33 @@ __global__ __launch_bounds__(NT) void packed_gemm_kernel(
   const int fm_live = min(FM, max(0, (M - m0 - wm + 15) >> 4));
   const int fn_live = min(FN, max(0, (N - n0 - wn + 15) >> 4));
   // k beyond the segment is zero in LDS: every chunk runs whole
-  auto compute = [&](int st, int) {
+  auto compute_t = [&](int st, auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
     if constexpr (FMT == PK_F32) {
       f32x4 ar[FM], ai[FM], as[FM], br[FN], bi[FN], bs[FN];
+      // every fragment is read (dead rows hold zeros in LDS): no register
+      // needs a defined value on a skipped path
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
-        if (i < fm_live) {
-          ar[i] = __builtin_bit_cast(f32x4, As[st][0][wm + 16 * i + frow][slot]);
-          ai[i] = __builtin_bit_cast(f32x4, As[st][1][wm + 16 * i + frow][slot]);
-          as[i] = ar[i] + ai[i];
-        }
+      for (int i = 0; i < FM; ++i) {
+        ar[i] = __builtin_bit_cast(f32x4, As[st][0][wm + 16 * i + frow][slot]);
+        ai[i] = __builtin_bit_cast(f32x4, As[st][1][wm + 16 * i + frow][slot]);
+      }
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
-        if (j < fn_live) {
-          br[j] = __builtin_bit_cast(f32x4, Bs[st][0][wn + 16 * j + frow][slot]);
-          bi[j] = __builtin_bit_cast(f32x4, Bs[st][1][wn + 16 * j + frow][slot]);
-          bs[j] = br[j] + bi[j];
-        }
+      for (int j = 0; j < FN; ++j) {
+        br[j] = __builtin_bit_cast(f32x4, Bs[st][0][wn + 16 * j + frow][slot]);
+        bi[j] = __builtin_bit_cast(f32x4, Bs[st][1][wn + 16 * j + frow][slot]);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i) as[i] = ar[i] + ai[i];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bs[j] = br[j] + bi[j];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
-            if (i < fm_live && j < fn_live) {
+            if (FULL || (i < fm_live && j < fn_live)) {
               acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i][kk], br[j][kk], acc1[i][j], 0, 0, 0);
               acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i][kk], bi[j][kk], acc2[i][j], 0, 0, 0);
               acc3[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[i][kk], bs[j][kk], acc3[i][j], 0, 0, 0);
@@ -180,7 +207,7 @@ __global__ __launch_bounds__(NT) void packed_gemm_kernel(
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          if (i < fm_live && j < fn_live) {
+          if (FULL || (i < fm_live && j < fn_live)) {
             // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo
 #define X3(acc, pa, pb)                                                                  \
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][pa], b[j][pb], acc, 0, 0, 0);     \
@@ -195,7 +222,14 @@ __global__ __launch_bounds__(NT) void packed_gemm_kernel(
     }
   };
 
-  walk_chunks<F::BK, STAGES>(segs, tk.seg0, tk.nseg, load, store, compute);
+  // tiles whose fragments are all live (the common case) run a copy of the
+  // walk without the per-fragment tests
+  auto compute_full = [&](int st, int) { compute_t(st, std::true_type{}); };
+  auto compute_part = [&](int st, int) { compute_t(st, std::false_type{}); };
+  if (fm_live == FM && fn_live == FN)
+    walk_chunks<F::BK, STAGES>(segs, tk.seg0, tk.nseg, load, store, compute_full);
+  else
+    walk_chunks<F::BK, STAGES>(segs, tk.seg0, tk.nseg, load, store, compute_part);
 
 #pragma unroll
   for (int i = 0; i < FM; ++i)
