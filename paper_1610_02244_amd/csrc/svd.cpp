@@ -235,12 +235,12 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
   launch_interleave(g, g + gsize, z.as<double>(), gsize, right ? 0 : 1, c.stream);
   // --- FP64 Hermitian eigendecompositions, one per sector -------------------
   // Each decomposition is a long chain of small, latency-bound launches, so
-  // sectors of similar size go through one strided-batched call: every
+  // the sectors go through a few strided-batched calls (buckets): every
   // sector is padded to its bucket's size (G plus negative eigenvalues below
   // its spectrum, mixed by a fixed reflector so that no exact split remains;
-  // see the padding kernels).  The buckets run concurrently on the side
-  // streams, forked from and joined back into the main stream; G's
-  // eigenpairs are extracted back into z and W.
+  // see the padding kernels).  The buckets run concurrently on side streams,
+  // forked from and joined back into the main stream; G's eigenpairs are
+  // extracted back into z and W.
   rocblas_handle h = blas(c);
   ensure_side(c);
   double* W = ev.as<double>();
@@ -250,23 +250,33 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
     std::vector<PadTask> tasks;
     DevBuf slots, w, e, tab;
   };
-  std::map<int, Bucket> buckets;
+  std::vector<Bucket> buckets;
   std::vector<int> info_pos(secs.size());
   {
-    for (size_t i = 0; i < secs.size(); ++i) {
-      const int np = padded_size(secs[i].n);
-      buckets[np].npad = np;
-      buckets[np].secs.push_back((int)i);
+    // A batched eigensolve costs about as much as one of its matrices (the
+    // launch chain is ~n steps long whatever the batch), and the GPU serves
+    // only a few streams concurrently, so the sectors form at most
+    // kMaxBuckets buckets: in descending size, a bucket takes every sector
+    // of at least half its largest one (the last takes the rest), all padded
+    // to the size class of that largest sector.
+    constexpr int kMaxBuckets = 3;
+    std::vector<int> by_n(secs.size());
+    std::iota(by_n.begin(), by_n.end(), 0);
+    std::stable_sort(by_n.begin(), by_n.end(),
+                     [&](int a, int b) { return secs[a].n > secs[b].n; });
+    for (size_t i = 0; i < by_n.size();) {
+      Bucket bk;
+      const int top = secs[by_n[i]].n;
+      bk.npad = padded_size(top);
+      const bool last = (int)buckets.size() == kMaxBuckets - 1;
+      while (i < by_n.size() && (last || 2 * secs[by_n[i]].n >= top)) bk.secs.push_back(by_n[i++]);
+      buckets.push_back(std::move(bk));
     }
-    std::vector<Bucket*> order;
-    for (auto& kv : buckets) order.push_back(&kv.second);
-    // heaviest first (cost ~ npad^3, batches ~ one matrix)
-    std::stable_sort(order.begin(), order.end(),
-                     [](const Bucket* x, const Bucket* y) { return x->npad > y->npad; });
     TNT_HIP(hipEventRecord(c.side_ev[Ctx::kSide], c.stream));
     bool used[Ctx::kSide] = {};
     int ipos = 0, k = 0;
-    for (Bucket* bk : order) {
+    for (Bucket& bref : buckets) {
+      Bucket* bk = &bref;
       const int np = bk->npad, cnt = (int)bk->secs.size();
       const int64_t slot = (int64_t)np * np;
       int maxn = 1;
