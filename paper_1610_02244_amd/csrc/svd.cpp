@@ -257,8 +257,8 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
     // launch chain is ~n steps long whatever the batch), and the GPU serves
     // only a few streams concurrently, so the sectors form at most
     // kMaxBuckets buckets: in descending size, a bucket takes every sector
-    // of at least half its largest one (the last takes the rest), all padded
-    // to the size class of that largest sector.
+    // of at least a quarter of its largest one (the last takes the rest), all
+    // padded to the size class of that largest sector.
     constexpr int kMaxBuckets = 3;
     std::vector<int> by_n(secs.size());
     std::iota(by_n.begin(), by_n.end(), 0);
@@ -269,7 +269,7 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
       const int top = secs[by_n[i]].n;
       bk.npad = padded_size(top);
       const bool last = (int)buckets.size() == kMaxBuckets - 1;
-      while (i < by_n.size() && (last || 2 * secs[by_n[i]].n >= top)) bk.secs.push_back(by_n[i++]);
+      while (i < by_n.size() && (last || 4 * secs[by_n[i]].n >= top)) bk.secs.push_back(by_n[i++]);
       buckets.push_back(std::move(bk));
     }
     TNT_HIP(hipEventRecord(c.side_ev[Ctx::kSide], c.stream));
