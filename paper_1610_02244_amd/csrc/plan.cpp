@@ -294,12 +294,21 @@ HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const En
   const int D = W1.D, d = th.d;
   const Bond& left = th.left;
   const Bond& right = th.right;
-  // combined two-site MPO coefficient sum_v W1[w,v,s1',s1] W2[v,u,s2',s2]
-  auto coef = [&](int w, int u, int s1p, int s2p, int s1, int s2) {
-    double c = 0.0;
-    for (int v = 0; v < D; ++v) c += W1.at(w, v, s1p, s1) * W2.at(v, u, s2p, s2);
-    return c;
-  };
+  // combined two-site MPO coefficients sum_v W1[w,v,s1',s1] W2[v,u,s2',s2],
+  // kept as the list of nonzero (w, s1, s2) terms per (u, s1', s2'), in
+  // ascending (w, s1, s2) order
+  struct MTerm { int w, s1, s2; double c; };
+  std::vector<std::vector<MTerm>> mterms((size_t)D * d * d);
+  for (int u = 0; u < D; ++u)
+    for (int s1p = 0; s1p < d; ++s1p)
+      for (int s2p = 0; s2p < d; ++s2p)
+        for (int w = 0; w < D; ++w)
+          for (int s1 = 0; s1 < d; ++s1)
+            for (int s2 = 0; s2 < d; ++s2) {
+              double c = 0.0;
+              for (int v = 0; v < D; ++v) c += W1.at(w, v, s1p, s1) * W2.at(v, u, s2p, s2);
+              if (c != 0.0) mterms[((size_t)u * d + s1p) * d + s2p].push_back(MTerm{w, s1, s2, c});
+            }
   struct Term { int w, qa, s1, s2; double c; };
   struct Slab { int u; std::array<int, 3> okey; int qb; std::vector<Term> terms; };
   std::vector<Slab> live;
@@ -311,15 +320,10 @@ HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const En
       const int qb = qbp - W2.qw[u];
       if (!R.blocks.count({u, qb}) || !right.count(qb)) continue;
       Slab sl{u, ob.first, qb, {}};
-      for (int w = 0; w < D; ++w) {
-        const int qa = qap - W1.qw[w];
-        if (!L.blocks.count({w, qa})) continue;
-        for (int s1 = 0; s1 < d; ++s1)
-          for (int s2 = 0; s2 < d; ++s2) {
-            if (!th.blocks.count({qa, s1, s2})) continue;
-            const double c = coef(w, u, s1p, s2p, s1, s2);
-            if (c != 0.0) sl.terms.push_back(Term{w, qa, s1, s2, c});
-          }
+      for (const MTerm& m : mterms[((size_t)u * d + s1p) * d + s2p]) {
+        const int qa = qap - W1.qw[m.w];
+        if (!L.blocks.count({m.w, qa}) || !th.blocks.count({qa, m.s1, m.s2})) continue;
+        sl.terms.push_back(Term{m.w, qa, m.s1, m.s2, m.c});
       }
       if (sl.terms.empty()) continue;
       for (auto& t : sl.terms) t1_off[{t.w, t.qa, t.s1, t.s2}] = -1;
