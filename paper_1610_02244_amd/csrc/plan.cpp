@@ -1,6 +1,8 @@
 // Task-list construction for the grouped kernels and the two-site H_eff plan.
 #include "plan.h"
 
+#include <climits>
+
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -279,21 +281,67 @@ HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const En
                          const ThetaH& th, const ThetaH& out, bool packed) {
   HeffPlan P;
   P.packed = packed;
-  // packed operand copies: every L and R block as stored, theta blocks
-  // transposed (K = dim(q_a) becomes the contiguous index)
-  std::map<std::pair<int, int>, int64_t> lp_off, rp_off;
-  std::map<std::array<int, 3>, int64_t> xp_off;
-  if (packed) {
-    for (auto& b : L.blocks)
-      lp_off[b.first] = P.Lp.add(b.second.off, b.second.rows, b.second.cols, b.second.cols, false);
-    for (auto& b : R.blocks)
-      rp_off[b.first] = P.Rp.add(b.second.off, b.second.rows, b.second.cols, b.second.cols, false);
-    for (auto& b : th.blocks)
-      xp_off[b.first] = P.Xp.add(b.second.off, b.second.cols, b.second.rows, b.second.cols, true);
-  }
   const int D = W1.D, d = th.d;
   const Bond& left = th.left;
   const Bond& right = th.right;
+  // dense charge indices (the block maps are only walked, never searched)
+  auto span = [](const Bond& a, const Bond& b, int& lo, int& hi) {
+    lo = INT_MAX;
+    hi = INT_MIN;
+    for (const Bond* x : {&a, &b})
+      if (!x->empty()) {
+        lo = std::min(lo, x->begin()->first);
+        hi = std::max(hi, x->rbegin()->first);
+      }
+    if (lo > hi) lo = hi = 0;
+  };
+  int llo, lhi, rlo, rhi;
+  span(left, L.bond, llo, lhi);
+  span(right, R.bond, rlo, rhi);
+  const int nl = lhi - llo + 1, nr = rhi - rlo + 1;
+  auto li = [&](int q) { return q < llo || q > lhi ? -1 : q - llo; };
+  auto ri = [&](int q) { return q < rlo || q > rhi ? -1 : q - rlo; };
+  std::vector<int> ldim(nl, 0), rdim(nr, 0);
+  for (auto& kv : left) ldim[kv.first - llo] = kv.second;
+  for (auto& kv : right) rdim[kv.first - rlo] = kv.second;
+  std::vector<const BlockRef*> Lb((size_t)D * nl, nullptr), Rb((size_t)D * nr, nullptr),
+      Tb((size_t)nl * d * d, nullptr);
+  for (auto& b : L.blocks) {
+    const int q = li(b.first.second);
+    if (q >= 0) Lb[(size_t)b.first.first * nl + q] = &b.second;
+  }
+  for (auto& b : R.blocks) {
+    const int q = ri(b.first.second);
+    if (q >= 0) Rb[(size_t)b.first.first * nr + q] = &b.second;
+  }
+  auto tix = [&](int q, int s1, int s2) { return ((size_t)q * d + s1) * d + s2; };
+  for (auto& b : th.blocks) {
+    const int q = li(b.first[0]);
+    if (q >= 0) Tb[tix(q, b.first[1], b.first[2])] = &b.second;
+  }
+  // packed operand copies: every L and R block as stored, theta blocks
+  // transposed (K = dim(q_a) becomes the contiguous index)
+  std::vector<int64_t> lp_off, rp_off, xp_off;
+  if (packed) {
+    lp_off.assign((size_t)D * nl, -1);
+    rp_off.assign((size_t)D * nr, -1);
+    xp_off.assign((size_t)nl * d * d, -1);
+    for (auto& b : L.blocks) {
+      const int64_t o = P.Lp.add(b.second.off, b.second.rows, b.second.cols, b.second.cols, false);
+      const int q = li(b.first.second);
+      if (q >= 0) lp_off[(size_t)b.first.first * nl + q] = o;
+    }
+    for (auto& b : R.blocks) {
+      const int64_t o = P.Rp.add(b.second.off, b.second.rows, b.second.cols, b.second.cols, false);
+      const int q = ri(b.first.second);
+      if (q >= 0) rp_off[(size_t)b.first.first * nr + q] = o;
+    }
+    for (auto& b : th.blocks) {
+      const int64_t o = P.Xp.add(b.second.off, b.second.cols, b.second.rows, b.second.cols, true);
+      const int q = li(b.first[0]);
+      if (q >= 0) xp_off[tix(q, b.first[1], b.first[2])] = o;
+    }
+  }
   // combined two-site MPO coefficients sum_v W1[w,v,s1',s1] W2[v,u,s2',s2],
   // kept as the list of nonzero (w, s1, s2) terms per (u, s1', s2'), in
   // ascending (w, s1, s2) order
@@ -309,60 +357,72 @@ HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const En
               for (int v = 0; v < D; ++v) c += W1.at(w, v, s1p, s1) * W2.at(v, u, s2p, s2);
               if (c != 0.0) mterms[((size_t)u * d + s1p) * d + s2p].push_back(MTerm{w, s1, s2, c});
             }
-  struct Term { int w, qa, s1, s2; double c; };
-  struct Slab { int u; std::array<int, 3> okey; int qb; std::vector<Term> terms; };
+  // T1 slab (w, q_a, s1, s2) -> index in the dense table; the slabs are laid
+  // out in ascending (w, q_a, s1, s2) order
+  auto t1x = [&](int w, int q, int s1, int s2) { return (size_t)w * nl * d * d + tix(q, s1, s2); };
+  struct Term { size_t t1; double c; };
+  struct Slab { int u, qi, s1p, s2p, qbi; std::vector<Term> terms; };
   std::vector<Slab> live;
-  std::map<std::array<int, 4>, int64_t> t1_off;  // (w, qa, s1, s2) -> slab offset (assigned later)
+  constexpr int64_t kUnused = -2, kUsed = -1;
+  std::vector<int64_t> t1_off((size_t)D * nl * d * d, kUnused);
   for (auto& ob : th.blocks) {
     const int qap = ob.first[0], s1p = ob.first[1], s2p = ob.first[2];
     const int qbp = qap + s1p + s2p;
+    const int qpi = li(qap);
     for (int u = 0; u < D; ++u) {
-      const int qb = qbp - W2.qw[u];
-      if (!R.blocks.count({u, qb}) || !right.count(qb)) continue;
-      Slab sl{u, ob.first, qb, {}};
+      const int qbi = ri(qbp - W2.qw[u]);
+      if (qbi < 0 || !Rb[(size_t)u * nr + qbi] || rdim[qbi] == 0) continue;
+      Slab sl{u, qpi, s1p, s2p, qbi, {}};
       for (const MTerm& m : mterms[((size_t)u * d + s1p) * d + s2p]) {
-        const int qa = qap - W1.qw[m.w];
-        if (!L.blocks.count({m.w, qa}) || !th.blocks.count({qa, m.s1, m.s2})) continue;
-        sl.terms.push_back(Term{m.w, qa, m.s1, m.s2, m.c});
+        const int qi = li(qap - W1.qw[m.w]);
+        if (qi < 0 || !Lb[(size_t)m.w * nl + qi] || !Tb[tix(qi, m.s1, m.s2)]) continue;
+        sl.terms.push_back(Term{t1x(m.w, qi, m.s1, m.s2), m.c});
       }
       if (sl.terms.empty()) continue;
-      for (auto& t : sl.terms) t1_off[{t.w, t.qa, t.s1, t.s2}] = -1;
+      for (auto& t : sl.terms) t1_off[t.t1] = kUsed;
       live.push_back(std::move(sl));
     }
   }
-  // step 1 tasks: one per live T1 slab (ascending key order)
+  // step 1 tasks: one per live T1 slab
   int64_t off = 0;
-  for (auto& kv : t1_off) {
-    const int w = kv.first[0], qa = kv.first[1], s1 = kv.first[2], s2 = kv.first[3];
-    const int qap = qa + W1.qw[w], qb = qa + s1 + s2;
-    const int M = left.at(qap), N = right.at(qb), K = left.at(qa);
-    kv.second = off;
-    const BlockRef& lb = L.blocks.at({w, qa});
-    const BlockRef& tb = th.blocks.at({qa, s1, s2});
-    P.step1.add_task(off, M, N, N);
-    P.step1.add_seg(lb.off, lb.cols, tb.off, tb.cols, K);
-    if (packed) {
-      P.step1p.add_task(off, M, N, N);
-      P.step1p.add_seg(lp_off.at({w, qa}), (int)pad8(K), xp_off.at({qa, s1, s2}), (int)pad8(K), K);
-    }
-    P.flops_step1 += 8LL * M * N * K;
-    off += (int64_t)M * N;
-  }
+  for (int w = 0; w < D; ++w)
+    for (int qi = 0; qi < nl; ++qi)
+      for (int s1 = 0; s1 < d; ++s1)
+        for (int s2 = 0; s2 < d; ++s2) {
+          const size_t x = t1x(w, qi, s1, s2);
+          if (t1_off[x] == kUnused) continue;
+          const int qa = qi + llo;
+          const int M = ldim[li(qa + W1.qw[w])], N = rdim[ri(qa + s1 + s2)], K = ldim[qi];
+          t1_off[x] = off;
+          const BlockRef& lb = *Lb[(size_t)w * nl + qi];
+          const BlockRef& tb = *Tb[tix(qi, s1, s2)];
+          P.step1.add_task(off, M, N, N);
+          P.step1.add_seg(lb.off, lb.cols, tb.off, tb.cols, K);
+          if (packed) {
+            P.step1p.add_task(off, M, N, N);
+            P.step1p.add_seg(lp_off[(size_t)w * nl + qi], (int)pad8(K), xp_off[tix(qi, s1, s2)],
+                             (int)pad8(K), K);
+          }
+          P.flops_step1 += 8LL * M * N * K;
+          off += (int64_t)M * N;
+        }
   P.t1_elems = off;
   // MPO combination: one T3 slab per live (u, output block)
   off = 0;
-  std::map<std::array<int, 4>, int64_t> t3_off;  // (u, qa', s1', s2') -> offset
-  std::map<std::array<int, 4>, int64_t> t3p_off;  // the same slabs, packed
+  auto t3x = [&](int u, int q, int s1, int s2) { return (size_t)u * nl * d * d + tix(q, s1, s2); };
+  std::vector<int64_t> t3_off((size_t)D * nl * d * d, -1), t3p_off;
+  if (packed) t3p_off.assign(t3_off.size(), -1);
   int64_t offp = 0;
   for (auto& sl : live) {
-    const int M = left.at(sl.okey[0]), N = right.at(sl.qb);
-    t3_off[{sl.u, sl.okey[0], sl.okey[1], sl.okey[2]}] = off;
+    const int M = ldim[sl.qi], N = rdim[sl.qbi];
+    const size_t x = t3x(sl.u, sl.qi, sl.s1p, sl.s2p);
+    t3_off[x] = off;
     P.mpo.add_task(off, M * N);
-    for (auto& t : sl.terms) P.mpo.add_term(t1_off.at({t.w, t.qa, t.s1, t.s2}), t.c);
+    for (auto& t : sl.terms) P.mpo.add_term(t1_off[t.t1], t.c);
     if (packed) {
-      t3p_off[{sl.u, sl.okey[0], sl.okey[1], sl.okey[2]}] = offp;
+      t3p_off[x] = offp;
       P.mpop.add_task(offp, M, N, (int)pad8(N));
-      for (auto& t : sl.terms) P.mpop.add_term(t1_off.at({t.w, t.qa, t.s1, t.s2}), t.c);
+      for (auto& t : sl.terms) P.mpop.add_term(t1_off[t.t1], t.c);
       offp += (int64_t)M * pad8(N);
     }
     P.flops_mpo += 4LL * (int64_t)sl.terms.size() * M * N;
@@ -374,20 +434,21 @@ HeffPlan build_heff_plan(const EnvH& L, const MpoH& W1, const MpoH& W2, const En
   for (auto& ob : out.blocks) {
     const int qap = ob.first[0], s1p = ob.first[1], s2p = ob.first[2];
     const int qbp = qap + s1p + s2p;
+    const int qpi = li(qap);
     const int M = ob.second.rows, N = ob.second.cols;
     P.step4.add_task(ob.second.off, M, N, N);
     if (packed) P.step4p.add_task(ob.second.off, M, N, N);
     P.out_keys.push_back(ob.first);
+    if (qpi < 0) continue;
     for (int u = 0; u < D; ++u) {
-      auto it = t3_off.find({u, qap, s1p, s2p});
-      if (it == t3_off.end()) continue;
-      const int qb = qbp - W2.qw[u];
-      const BlockRef& rb = R.blocks.at({u, qb});
-      const int K = right.at(qb);
-      P.step4.add_seg(it->second, K, rb.off, rb.cols, K);
+      const size_t x = t3x(u, qpi, s1p, s2p);
+      if (t3_off[x] < 0) continue;
+      const int qbi = ri(qbp - W2.qw[u]);
+      const BlockRef& rb = *Rb[(size_t)u * nr + qbi];
+      const int K = rdim[qbi];
+      P.step4.add_seg(t3_off[x], K, rb.off, rb.cols, K);
       if (packed)
-        P.step4p.add_seg(t3p_off.at({u, qap, s1p, s2p}), (int)pad8(K), rp_off.at({u, qb}),
-                         (int)pad8(K), K);
+        P.step4p.add_seg(t3p_off[x], (int)pad8(K), rp_off[(size_t)u * nr + qbi], (int)pad8(K), K);
       P.flops_step4 += 8LL * M * N * K;
     }
   }
