@@ -325,6 +325,43 @@ def pmc_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir,
     return res
 
 
+def mfma_util(root, simds=1024, xcds=8):
+    """MFMA utilisation per kernel from a `rocprofv3 --pmc GRBM_GUI_ACTIVE
+    SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_MFMA ...` run (CSV output directory):
+    busy MFMA cycles summed over the SIMDs / (SIMDs x the dispatch's GPU
+    cycles); GRBM_GUI_ACTIVE counts every XCD, so one dispatch lasts
+    GRBM_GUI_ACTIVE / xcds cycles."""
+    import csv
+    disp = {}
+    for dp, _, fs in os.walk(root):
+        for f in fs:
+            if f.endswith("counter_collection.csv"):
+                with open(os.path.join(dp, f)) as fh:
+                    for r in csv.DictReader(fh):
+                        key = (r.get("Dispatch_Id"), r["Kernel_Name"])
+                        disp.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    agg = {}
+    for (_, name), c in disp.items():
+        if "GRBM_GUI_ACTIVE" not in c or "SQ_VALU_MFMA_BUSY_CYCLES" not in c:
+            continue
+        if c["SQ_VALU_MFMA_BUSY_CYCLES"] <= 0:
+            continue
+        short = name.replace("void ", "").split("(")[0]
+        a = agg.setdefault(short, {"dispatches": 0, "gpu_cycles": 0.0, "mfma_busy": 0.0,
+                                   "mfma_insts": 0.0})
+        a["dispatches"] += 1
+        a["gpu_cycles"] += c["GRBM_GUI_ACTIVE"] / xcds
+        a["mfma_busy"] += c["SQ_VALU_MFMA_BUSY_CYCLES"]
+        a["mfma_insts"] += c.get("SQ_INSTS_MFMA", 0.0)
+    out = {}
+    for k, a in sorted(agg.items(), key=lambda kv: -kv[1]["mfma_busy"]):
+        out[k] = {"dispatches": a["dispatches"],
+                  "avg_gpu_cycles": a["gpu_cycles"] / a["dispatches"],
+                  "mfma_busy_frac": a["mfma_busy"] / (simds * a["gpu_cycles"]),
+                  "avg_mfma_insts": a["mfma_insts"] / a["dispatches"]}
+    return out
+
+
 def golden_energy(config, total_sweeps):
     names = {("cfg1", 2): "cfg1", ("cfg2", 1): "cfg2", ("cfg2", 2): "cfg2_2sweeps"}
     case = names.get((config, total_sweeps))
@@ -363,11 +400,17 @@ def main():
                                                        "CAL_WRITE_DIR"),
                     help="print the scaled HBM bytes per FP32 packed-GEMM launch from rocprofv3 "
                          "--pmc CSV runs and exit")
+    ap.add_argument("--mfma-util", metavar="DIR",
+                    help="MFMA utilisation per kernel from a rocprofv3 --pmc run "
+                         "(GRBM_GUI_ACTIVE, SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_MFMA)")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="print timed-region kernel statistics of a rocprofv3 CSV trace and exit")
     args = ap.parse_args()
     if args.pmc_traffic:
         print(json.dumps(pmc_traffic(*args.pmc_traffic), indent=1))
+        return
+    if args.mfma_util:
+        print(json.dumps(mfma_util(args.mfma_util), indent=1))
         return
     if args.summarize_trace:
         print(json.dumps(summarize_trace(args.summarize_trace), indent=1))

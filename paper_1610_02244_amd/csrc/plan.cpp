@@ -723,23 +723,26 @@ void HeffOp::autotune(const double* xre, const double* xim, double* yre, double*
     const int gi = (fp64 ? 0 : 2) + (step == 1 ? 0 : 1);
     DevTables::G& g = tab.g[gi];
     if (g.nvar <= 1) continue;
-    int best = g.sel;
-    float best_ms = 1e30f;
-    for (int v = 0; v < g.nvar; ++v) {
-      if (!gemm_cfg_valid(g.cfg[v], path)) continue;
-      launch_step(step, v, fp64, xre, xim, yre, yim);  // warm-up
-      TNT_HIP(hipEventRecord(c.ev[6], c.stream));
-      launch_step(step, v, fp64, xre, xim, yre, yim);
-      launch_step(step, v, fp64, xre, xim, yre, yim);
-      TNT_HIP(hipEventRecord(c.ev[7], c.stream));
-      TNT_HIP(hipEventSynchronize(c.ev[7]));
-      float ms = 0;
-      TNT_HIP(hipEventElapsedTime(&ms, c.ev[6], c.ev[7]));
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = v;
+    // one warm-up launch per candidate, then three interleaved rounds of one
+    // timed launch each; a candidate's time is its fastest round, so a
+    // single disturbed launch cannot decide
+    std::vector<float> t(g.nvar, 1e30f);
+    for (int v = 0; v < g.nvar; ++v)
+      if (gemm_cfg_valid(g.cfg[v], path)) launch_step(step, v, fp64, xre, xim, yre, yim);
+    for (int round = 0; round < 3; ++round)
+      for (int v = 0; v < g.nvar; ++v) {
+        if (!gemm_cfg_valid(g.cfg[v], path)) continue;
+        TNT_HIP(hipEventRecord(c.ev[6], c.stream));
+        launch_step(step, v, fp64, xre, xim, yre, yim);
+        TNT_HIP(hipEventRecord(c.ev[7], c.stream));
+        TNT_HIP(hipEventSynchronize(c.ev[7]));
+        float ms = 0;
+        TNT_HIP(hipEventElapsedTime(&ms, c.ev[6], c.ev[7]));
+        t[v] = std::min(t[v], ms);
       }
-    }
+    int best = g.sel;
+    for (int v = 0; v < g.nvar; ++v)
+      if (t[v] < t[best] || !gemm_cfg_valid(g.cfg[best], path)) best = v;
     g.sel = best;
     const HostGemm& h = fp64 ? (step == 1 ? plan.step1 : plan.step4)
                              : (step == 1 ? plan.step1p : plan.step4p);
