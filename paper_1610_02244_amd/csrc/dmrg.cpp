@@ -581,6 +581,20 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
     t_lanczos += (tl1 - tl0) - tm.matvec_s;
     t_gemm += tm.gemm_s;
     launches += tm.gemm_launches;
+    // the sector eigendecompositions of every chain of the step share one
+    // set of batched calls
+    const double te0 = now_s();
+    std::vector<std::shared_ptr<SvdJob>> jobs;
+    std::vector<SvdJob*> jp;
+    for (size_t a = 0; a < act.size(); ++a) {
+      if (ps[act[a].i].trunc.chi_max < 1) fail(TNT_E_ARG, "chi_max must be >= 1");
+      const int64_t off = B->parts[a].x_off;
+      jobs.push_back(svd_begin(c, ths[a], x + off, x + B->N + off,
+                               act[a].pass == 0 ? TNT_ABSORB_RIGHT : TNT_ABSORB_LEFT));
+      jp.push_back(jobs.back().get());
+    }
+    svd_eig(c, jp);
+    t_svd += now_s() - te0;
     for (size_t a = 0; a < act.size(); ++a) {
       const int i = act[a].i, j = act[a].j, pass = act[a].pass;
       MpsH& m = *ms[i];
@@ -591,21 +605,18 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
       s.matvecs += lo[a].matvecs;
       s.matvec_flops += (double)op.plan.flops() * (double)lo[a].matvecs;
       s.gemm_flops += (double)(op.plan.flops_step1 + op.plan.flops_step4) * (double)lo[a].matvecs;
-      const int absorb = pass == 0 ? TNT_ABSORB_RIGHT : TNT_ABSORB_LEFT;
-      const int64_t off = B->parts[a].x_off;
       DevBuf na, nb;
       const double ts0 = now_s();
-      SvdOut r = svd_truncate_dev(c, ths[a], x + off, x + B->N + off, p.trunc, absorb,
-                                  [&](const SvdOut& o) {
-                                    na = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.A.elems) * 8);
-                                    nb = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.B.elems) * 8);
-                                    FactorPlanes fp;
-                                    fp.a_re = na.as<double>();
-                                    fp.a_im = na.as<double>() + o.A.elems;
-                                    fp.b_re = nb.as<double>();
-                                    fp.b_im = nb.as<double>() + o.B.elems;
-                                    return fp;
-                                  });
+      SvdOut r = svd_finish(c, *jobs[a], p.trunc, [&](const SvdOut& o) {
+        na = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.A.elems) * 8);
+        nb = DevBuf(&c.pool, std::max<int64_t>(1, 2 * o.B.elems) * 8);
+        FactorPlanes fp;
+        fp.a_re = na.as<double>();
+        fp.a_im = na.as<double>() + o.A.elems;
+        fp.b_re = nb.as<double>();
+        fp.b_im = nb.as<double>() + o.B.elems;
+        return fp;
+      });
       const double ts = now_s();
       t_svd += ts - ts0;
       m.bonds[j] = r.bond;

@@ -266,18 +266,21 @@ void launch_scatter_z(const ScatterTask* t, int ntask, int maxrows, int maxcols,
 // reduction), using vec (2 npad doubles per slot at 2 w_src) as work space;
 // extract takes G's eigenpairs back from the slot's ascending eigenpairs (the
 // last n values, their vectors mapped through Q, first n rows) into an n x n
-// eigenvector matrix at src and n eigenvalues at w_dst.
+// eigenvector matrix at z + src_off and n eigenvalues at w + w_dst.  Every task
+// names its own z and w, so one batch can serve several thetas.
 struct PadTask {
-  int64_t src_off;   // complex offset of the n x n matrix
+  double* z;         // the matrix's job buffer: interleaved Gram in, eigenvectors out
+  double* w;         // the job's eigenvalue buffer
+  int64_t src_off;   // complex offset of the n x n matrix in z
   int64_t dst_off;   // complex offset of the npad x npad slot
   int64_t w_src;     // offset of the slot's npad eigenvalues (and work vector)
-  int64_t w_dst;     // offset of the sector's n eigenvalues
+  int64_t w_dst;     // offset of the sector's n eigenvalues in w
   int32_t n, npad;
 };
-void launch_pad_embed(const PadTask* t, int ntask, int max_n, int max_npad, const double* src_z,
-                      double* vec, double* dst_z, hipStream_t s);
+void launch_pad_embed(const PadTask* t, int ntask, int max_n, int max_npad, double* vec,
+                      double* dst_z, hipStream_t s);
 void launch_pad_extract(const PadTask* t, int ntask, int max_n, const double* slot_z,
-                        const double* slot_w, double* z, double* w, hipStream_t s);
+                        const double* slot_w, hipStream_t s);
 
 // z[2k] = re[k], z[2k+1] = (conj ? -im[k] : im[k]) for k < n
 void launch_interleave(const double* re, const double* im, double* z, int64_t n, int conj,

@@ -169,15 +169,36 @@ int index_of(const std::vector<std::pair<int, int>>& v, int first) {
 }
 }  // namespace
 
-SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double* im,
-                        const tnt_trunc_params& p, int absorb, const FactorAlloc& alloc) {
-  if (p.chi_max < 1) fail(TNT_E_ARG, "chi_max must be >= 1");
+// State of one theta between the SVD phases.
+struct SvdJob {
+  ThetaH th;
+  const double* re = nullptr;
+  const double* im = nullptr;
+  bool right = true;
+  std::vector<Sector> secs;
+  int64_t gsize = 0;  // complex elements of the Gram matrices
+  int esize = 0;      // eigenvalues
+  DevTables tg;
+  DevBuf gram, z, ev, info;
+  std::vector<rocblas_int> hinfo;  // per sector, from the batched eigensolve
+};
+
+
+std::shared_ptr<SvdJob> svd_begin(Ctx& c, const ThetaH& th, const double* re, const double* im,
+                                  int absorb) {
   if (absorb != TNT_ABSORB_RIGHT && absorb != TNT_ABSORB_LEFT) fail(TNT_E_ARG, "bad absorb");
-  const bool right = absorb == TNT_ABSORB_RIGHT;
-  std::vector<Sector> secs = sectors_of(th);
+  auto job = std::make_shared<SvdJob>();
+  SvdJob& J = *job;
+  J.th = th;
+  J.re = re;
+  J.im = im;
+  J.right = absorb == TNT_ABSORB_RIGHT;
+  const bool right = J.right;
+  std::vector<Sector>& secs = J.secs;
+  secs = sectors_of(th);
   if (secs.empty()) fail(TNT_E_SHAPE, "theta has no sector to decompose");
-  int64_t gsize = 0;
-  int esize = 0;
+  int64_t& gsize = J.gsize;
+  int& esize = J.esize;
   for (auto& s : secs) {
     s.n = right ? s.R : s.C;
     s.gbase = gsize;
@@ -222,111 +243,130 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
     }
   }
   gg.finalize(default_tile_cfg(gg, PATH_F64));
-  DevTables tg;
-  tg.upload(c, {&gg}, {});
-  DevBuf gram(&c.pool, std::max<int64_t>(1, 2 * gsize) * sizeof(double));
-  DevBuf z(&c.pool, std::max<int64_t>(1, 2 * gsize) * sizeof(double));
-  DevBuf ev(&c.pool, (size_t)std::max(1, 2 * esize) * sizeof(double));
-  DevBuf info(&c.pool, std::max<size_t>(secs.size(), 1) * sizeof(rocblas_int));
-  double* g = gram.as<double>();
-  run_gemm(c, tg.g[0], right ? FORM_cNT : FORM_CN, PATH_F64, re, im, ET_F64, re, im, ET_F64, g,
+  J.tg.upload(c, {&gg}, {});
+  J.gram = DevBuf(&c.pool, std::max<int64_t>(1, 2 * gsize) * sizeof(double));
+  J.z = DevBuf(&c.pool, std::max<int64_t>(1, 2 * gsize) * sizeof(double));
+  J.ev = DevBuf(&c.pool, (size_t)std::max(1, 2 * esize) * sizeof(double));
+  J.info = DevBuf(&c.pool, std::max<size_t>(secs.size(), 1) * sizeof(rocblas_int));
+  J.hinfo.assign(secs.size(), 0);
+  double* g = J.gram.as<double>();
+  run_gemm(c, J.tg.g[0], right ? FORM_cNT : FORM_CN, PATH_F64, re, im, ET_F64, re, im, ET_F64, g,
            g + gsize, ET_F64);
   // the row-major buffer read column-major is G (absorb right) or conj(G) (left)
-  launch_interleave(g, g + gsize, z.as<double>(), gsize, right ? 0 : 1, c.stream);
-  // --- FP64 Hermitian eigendecompositions, one per sector -------------------
+  launch_interleave(g, g + gsize, J.z.as<double>(), gsize, right ? 0 : 1, c.stream);
+  return job;
+}
+
+void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
   // Each decomposition is a long chain of small, latency-bound launches, so
-  // the sectors go through a few strided-batched calls (buckets): every
-  // sector is padded to its bucket's size (G plus negative eigenvalues below
-  // its spectrum, mixed by a fixed reflector so that no exact split remains;
-  // see the padding kernels).  The buckets run concurrently on side streams,
-  // forked from and joined back into the main stream; G's eigenpairs are
-  // extracted back into z and W.
-  rocblas_handle h = blas(c);
+  // the sectors of all jobs go through a few strided-batched calls
+  // (buckets): every sector is padded to its bucket's size (G plus negative
+  // eigenvalues below its spectrum, mixed by a fixed reflector so that no
+  // exact split remains; see the padding kernels).  The buckets run
+  // concurrently on side streams, forked from and joined back into the main
+  // stream; G's eigenpairs are extracted back into each job's z and W.
   ensure_side(c);
-  double* W = ev.as<double>();
+  struct Ref { SvdJob* job; int sec; };
   struct Bucket {
     int npad = 0;
-    std::vector<int> secs;
+    std::vector<Ref> secs;
     std::vector<PadTask> tasks;
-    DevBuf slots, w, e, tab;
+    DevBuf slots, w, e, tab, info;
   };
+  std::vector<Ref> all;
+  for (SvdJob* j : jobs)
+    for (size_t i = 0; i < j->secs.size(); ++i) all.push_back(Ref{j, (int)i});
+  auto n_of = [](const Ref& r) { return r.job->secs[r.sec].n; };
+  std::stable_sort(all.begin(), all.end(),
+                   [&](const Ref& a, const Ref& b) { return n_of(a) > n_of(b); });
+  // A batched eigensolve costs about as much as one of its matrices (the
+  // launch chain is ~n steps long whatever the batch), and the GPU serves
+  // only a few streams concurrently, so the sectors form at most
+  // kMaxBuckets buckets: in descending size, a bucket takes every sector of
+  // at least a quarter of its largest one (the last takes the rest), all
+  // padded to the size class of that largest sector.
+  constexpr int kMaxBuckets = 3;
   std::vector<Bucket> buckets;
-  std::vector<int> info_pos(secs.size());
-  {
-    // A batched eigensolve costs about as much as one of its matrices (the
-    // launch chain is ~n steps long whatever the batch), and the GPU serves
-    // only a few streams concurrently, so the sectors form at most
-    // kMaxBuckets buckets: in descending size, a bucket takes every sector
-    // of at least a quarter of its largest one (the last takes the rest), all
-    // padded to the size class of that largest sector.
-    constexpr int kMaxBuckets = 3;
-    std::vector<int> by_n(secs.size());
-    std::iota(by_n.begin(), by_n.end(), 0);
-    std::stable_sort(by_n.begin(), by_n.end(),
-                     [&](int a, int b) { return secs[a].n > secs[b].n; });
-    for (size_t i = 0; i < by_n.size();) {
-      Bucket bk;
-      const int top = secs[by_n[i]].n;
-      bk.npad = padded_size(top);
-      const bool last = (int)buckets.size() == kMaxBuckets - 1;
-      while (i < by_n.size() && (last || 4 * secs[by_n[i]].n >= top)) bk.secs.push_back(by_n[i++]);
-      buckets.push_back(std::move(bk));
-    }
-    TNT_HIP(hipEventRecord(c.side_ev[Ctx::kSide], c.stream));
-    bool used[Ctx::kSide] = {};
-    int ipos = 0, k = 0;
-    for (Bucket& bref : buckets) {
-      Bucket* bk = &bref;
-      const int np = bk->npad, cnt = (int)bk->secs.size();
-      const int64_t slot = (int64_t)np * np;
-      int maxn = 1;
-      for (int q = 0; q < cnt; ++q) {
-        const Sector& sc = secs[bk->secs[q]];
-        bk->tasks.push_back(PadTask{sc.gbase, q * slot, (int64_t)q * np, sc.ebase, sc.n, np});
-        info_pos[bk->secs[q]] = ipos + q;
-        maxn = std::max(maxn, sc.n);
-      }
-      bk->slots = DevBuf(&c.pool, (size_t)2 * slot * cnt * sizeof(double));
-      bk->w = DevBuf(&c.pool, (size_t)np * cnt * sizeof(double));
-      // e: the embedding's work vectors (2 np per slot), then heevd's off-diagonals
-      bk->e = DevBuf(&c.pool, (size_t)2 * np * cnt * sizeof(double));
-      bk->tab = DevBuf(&c.pool, bk->tasks.size() * sizeof(PadTask));
-      hipStream_t ss = c.side[k];
-      if (!used[k]) {
-        TNT_HIP(hipStreamWaitEvent(ss, c.side_ev[Ctx::kSide], 0));
-        used[k] = true;
-      }
-      TNT_HIP(hipMemcpyAsync(bk->tab.ptr, bk->tasks.data(), bk->tasks.size() * sizeof(PadTask),
-                             hipMemcpyHostToDevice, ss));
-      launch_pad_embed(bk->tab.as<PadTask>(), cnt, maxn, np, z.as<double>(), bk->e.as<double>(),
-                       bk->slots.as<double>(), ss);
-      if (rocsolver_zheevd_strided_batched(
-              static_cast<rocblas_handle>(c.side_blas[k]), rocblas_evect_original,
-              rocblas_fill_upper, np, reinterpret_cast<rocblas_double_complex*>(bk->slots.ptr),
-              np, slot, bk->w.as<double>(), np, bk->e.as<double>(), np,
-              info.as<rocblas_int>() + ipos, cnt) != rocblas_status_success)
-        fail(TNT_E_HIP, "rocsolver_zheevd_strided_batched failed");
-      launch_pad_extract(bk->tab.as<PadTask>(), cnt, maxn, bk->slots.as<double>(),
-                         bk->w.as<double>(), z.as<double>(), W, ss);
-      ipos += cnt;
-      k = (k + 1) % Ctx::kSide;
-    }
-    for (int q = 0; q < Ctx::kSide; ++q) {
-      if (!used[q]) continue;
-      TNT_HIP(hipEventRecord(c.side_ev[q], c.side[q]));
-      TNT_HIP(hipStreamWaitEvent(c.stream, c.side_ev[q], 0));
-    }
+  for (size_t i = 0; i < all.size();) {
+    Bucket bk;
+    const int top = n_of(all[i]);
+    bk.npad = padded_size(top);
+    const bool last = (int)buckets.size() == kMaxBuckets - 1;
+    while (i < all.size() && (last || 4 * n_of(all[i]) >= top)) bk.secs.push_back(all[i++]);
+    buckets.push_back(std::move(bk));
   }
+  TNT_HIP(hipEventRecord(c.side_ev[Ctx::kSide], c.stream));
+  bool used[Ctx::kSide] = {};
+  int k = 0;
+  for (Bucket& bk : buckets) {
+    const int np = bk.npad, cnt = (int)bk.secs.size();
+    const int64_t slot = (int64_t)np * np;
+    int maxn = 1;
+    for (int q = 0; q < cnt; ++q) {
+      SvdJob& J = *bk.secs[q].job;
+      const Sector& sc = J.secs[bk.secs[q].sec];
+      bk.tasks.push_back(PadTask{J.z.as<double>(), J.ev.as<double>(), sc.gbase, q * slot,
+                                 (int64_t)q * np, sc.ebase, sc.n, np});
+      maxn = std::max(maxn, sc.n);
+    }
+    bk.slots = DevBuf(&c.pool, (size_t)2 * slot * cnt * sizeof(double));
+    bk.w = DevBuf(&c.pool, (size_t)np * cnt * sizeof(double));
+    // e: the embedding's work vectors (2 np per slot), then heevd's off-diagonals
+    bk.e = DevBuf(&c.pool, (size_t)2 * np * cnt * sizeof(double));
+    bk.tab = DevBuf(&c.pool, bk.tasks.size() * sizeof(PadTask));
+    bk.info = DevBuf(&c.pool, (size_t)cnt * sizeof(rocblas_int));
+    hipStream_t ss = c.side[k];
+    if (!used[k]) {
+      TNT_HIP(hipStreamWaitEvent(ss, c.side_ev[Ctx::kSide], 0));
+      used[k] = true;
+    }
+    TNT_HIP(hipMemcpyAsync(bk.tab.ptr, bk.tasks.data(), bk.tasks.size() * sizeof(PadTask),
+                           hipMemcpyHostToDevice, ss));
+    launch_pad_embed(bk.tab.as<PadTask>(), cnt, maxn, np, bk.e.as<double>(),
+                     bk.slots.as<double>(), ss);
+    if (rocsolver_zheevd_strided_batched(
+            static_cast<rocblas_handle>(c.side_blas[k]), rocblas_evect_original,
+            rocblas_fill_upper, np, reinterpret_cast<rocblas_double_complex*>(bk.slots.ptr), np,
+            slot, bk.w.as<double>(), np, bk.e.as<double>(), np, bk.info.as<rocblas_int>(),
+            cnt) != rocblas_status_success)
+      fail(TNT_E_HIP, "rocsolver_zheevd_strided_batched failed");
+    launch_pad_extract(bk.tab.as<PadTask>(), cnt, maxn, bk.slots.as<double>(), bk.w.as<double>(),
+                       ss);
+    k = (k + 1) % Ctx::kSide;
+  }
+  for (int q = 0; q < Ctx::kSide; ++q) {
+    if (!used[q]) continue;
+    TNT_HIP(hipEventRecord(c.side_ev[q], c.side[q]));
+    TNT_HIP(hipStreamWaitEvent(c.stream, c.side_ev[q], 0));
+  }
+  // the buckets (device slots and host task lists) live until here
+  TNT_HIP(hipStreamSynchronize(c.stream));
+  for (Bucket& bk : buckets) {
+    std::vector<rocblas_int> raw(bk.secs.size());
+    TNT_HIP(hipMemcpy(raw.data(), bk.info.ptr, raw.size() * sizeof(rocblas_int),
+                      hipMemcpyDeviceToHost));
+    for (size_t q = 0; q < raw.size(); ++q) bk.secs[q].job->hinfo[bk.secs[q].sec] = raw[q];
+  }
+}
+
+SvdOut svd_finish(Ctx& c, SvdJob& J, const tnt_trunc_params& p, const FactorAlloc& alloc) {
+  if (p.chi_max < 1) fail(TNT_E_ARG, "chi_max must be >= 1");
+  const ThetaH& th = J.th;
+  const double* re = J.re;
+  const double* im = J.im;
+  const bool right = J.right;
+  std::vector<Sector>& secs = J.secs;
+  const int64_t gsize = J.gsize;
+  const int esize = J.esize;
+  DevBuf& z = J.z;
+  DevBuf& info = J.info;
+  double* g = J.gram.as<double>();
+  double* W = J.ev.as<double>();
+  rocblas_handle h = blas(c);
   std::vector<double> mu(esize);
-  std::vector<rocblas_int> hinfo(secs.size());
+  std::vector<rocblas_int>& hinfo = J.hinfo;
   TNT_HIP(hipMemcpyAsync(mu.data(), W, esize * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-  {
-    std::vector<rocblas_int> raw(secs.size());
-    TNT_HIP(hipMemcpyAsync(raw.data(), info.ptr, secs.size() * sizeof(rocblas_int),
-                           hipMemcpyDeviceToHost, c.stream));
-    TNT_HIP(hipStreamSynchronize(c.stream));
-    for (size_t i = 0; i < secs.size(); ++i) hinfo[i] = raw[info_pos[i]];
-  }
+  TNT_HIP(hipStreamSynchronize(c.stream));
   // divide and conquer can fail on large clusters of (near-)zero eigenvalues;
   // redo such a sector with the Jacobi eigensolver from the kept Gram planes
   for (size_t i = 0; i < secs.size(); ++i) {
@@ -534,6 +574,14 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
   // the host task vectors above must outlive the asynchronous copies
   TNT_HIP(hipStreamSynchronize(c.stream));
   return out;
+}
+
+SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double* im,
+                        const tnt_trunc_params& p, int absorb, const FactorAlloc& alloc) {
+  if (p.chi_max < 1) fail(TNT_E_ARG, "chi_max must be >= 1");
+  auto job = svd_begin(c, th, re, im, absorb);
+  svd_eig(c, {job.get()});
+  return svd_finish(c, *job, p, alloc);
 }
 
 }  // namespace tnt

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <functional>
+#include <memory>
 #include <vector>
 
 #include "layout.h"
@@ -43,5 +44,16 @@ double trunc_error(const double* lam, int n, int kind);
 // columns the (s2, q_b) pairs present among theta's blocks with q_a + s1 = m.
 SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double* im,
                         const tnt_trunc_params& p, int absorb, const FactorAlloc& alloc);
+
+// The same in three phases, so that the eigendecompositions of several
+// thetas share batched calls: svd_begin launches the sector Gram matrices of
+// one theta (its planes must stay valid until svd_finish), svd_eig
+// decomposes every sector of every job and returns when done, svd_finish
+// selects the kept values and writes the factors.
+struct SvdJob;
+std::shared_ptr<SvdJob> svd_begin(Ctx& c, const ThetaH& th, const double* re, const double* im,
+                                  int absorb);
+void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs);
+SvdOut svd_finish(Ctx& c, SvdJob& job, const tnt_trunc_params& p, const FactorAlloc& alloc);
 
 }  // namespace tnt

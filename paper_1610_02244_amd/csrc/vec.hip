@@ -437,13 +437,12 @@ __device__ inline double block_sum_all(double v, double* sh, double* out) {
 // vec[2 (w_src + i)] = (G u)_i for i < n: one wave per row, using column i
 // of G (G Hermitian: row i of G is the conjugate of column i).
 __global__ __launch_bounds__(256) void pad_gvec_kernel(const PadTask* __restrict__ tasks,
-                                                       const double* __restrict__ src,
                                                        double* __restrict__ vec) {
   const PadTask t = tasks[blockIdx.y];
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= t.n) return;  // whole wave leaves together
-  const double* col = src + 2 * (t.src_off + (int64_t)i * t.n);
+  const double* col = t.z + 2 * (t.src_off + (int64_t)i * t.n);
   double ar = 0, ai = 0;
   for (int k = lane; k < t.n; k += 64) {
     const double u = pad_u(k);
@@ -461,12 +460,12 @@ __global__ __launch_bounds__(256) void pad_gvec_kernel(const PadTask* __restrict
 }
 
 __global__ __launch_bounds__(256) void pad_embed_kernel(const PadTask* __restrict__ tasks,
-                                                        const double* __restrict__ src,
                                                         const double* __restrict__ vec,
                                                         double* __restrict__ dst) {
   __shared__ double sh[4];
   __shared__ double bc;
   const PadTask t = tasks[blockIdx.y];
+  const double* __restrict__ src = t.z;
   const int n = t.n, np = t.npad, m = np - n;
   // scalars of the slot (every block computes them: O(npad) from cache)
   double tr = 0, nu = 0, bg = 0, p0 = 0, p1 = 0;
@@ -525,22 +524,19 @@ __global__ __launch_bounds__(256) void pad_embed_kernel(const PadTask* __restric
   }
 }
 
-void launch_pad_embed(const PadTask* t, int ntask, int max_n, int max_npad, const double* src_z,
-                      double* vec, double* dst_z, hipStream_t s) {
+void launch_pad_embed(const PadTask* t, int ntask, int max_n, int max_npad, double* vec,
+                      double* dst_z, hipStream_t s) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(pad_gvec_kernel, dim3((max_n + 3) / 4, ntask), dim3(256), 0, s, t, src_z,
-                     vec);
+  hipLaunchKernelGGL(pad_gvec_kernel, dim3((max_n + 3) / 4, ntask), dim3(256), 0, s, t, vec);
   const int gx = grid_for((int64_t)max_npad * max_npad, 256, 512);
-  hipLaunchKernelGGL(pad_embed_kernel, dim3(gx, ntask), dim3(256), 0, s, t, src_z, vec, dst_z);
+  hipLaunchKernelGGL(pad_embed_kernel, dim3(gx, ntask), dim3(256), 0, s, t, vec, dst_z);
 }
 
 // One block per kept column c < n: v = slot column npad - n + c, rho = u^T v,
 // z[:, c] = (v - 2 u rho / (u^T u)) restricted to the first n rows.
 __global__ __launch_bounds__(256) void pad_extract_kernel(const PadTask* __restrict__ tasks,
                                                           const double* __restrict__ slot_z,
-                                                          const double* __restrict__ slot_w,
-                                                          double* __restrict__ z,
-                                                          double* __restrict__ w) {
+                                                          const double* __restrict__ slot_w) {
   __shared__ double sh[4];
   __shared__ double bc;
   const PadTask t = tasks[blockIdx.y];
@@ -559,20 +555,19 @@ __global__ __launch_bounds__(256) void pad_extract_kernel(const PadTask* __restr
   ri = block_sum_all(ri, sh, &bc);
   nu = block_sum_all(nu, sh, &bc);
   const double f = 2.0 / nu;
-  double* out = z + 2 * (t.src_off + (int64_t)c * t.n);
+  double* out = t.z + 2 * (t.src_off + (int64_t)c * t.n);
   for (int r = threadIdx.x; r < t.n; r += blockDim.x) {
     const double u = pad_u(r);
     out[2 * r] = v[2 * r] - f * u * rr;
     out[2 * r + 1] = v[2 * r + 1] - f * u * ri;
   }
-  if (threadIdx.x == 0) w[t.w_dst + c] = slot_w[t.w_src + sft + c];
+  if (threadIdx.x == 0) t.w[t.w_dst + c] = slot_w[t.w_src + sft + c];
 }
 
 void launch_pad_extract(const PadTask* t, int ntask, int max_n, const double* slot_z,
-                        const double* slot_w, double* z, double* w, hipStream_t s) {
+                        const double* slot_w, hipStream_t s) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(pad_extract_kernel, dim3(max_n, ntask), dim3(256), 0, s, t, slot_z, slot_w,
-                     z, w);
+  hipLaunchKernelGGL(pad_extract_kernel, dim3(max_n, ntask), dim3(256), 0, s, t, slot_z, slot_w);
 }
 
 }  // namespace tnt

@@ -156,6 +156,24 @@ def test_heff_full_size_sampled(tnt):
         assert err <= bar
 
 
+def test_heff_chi2048_sampled(tnt):
+    """chi = 2048 middle bond (L = 128; blocks up to 601 x 601): the largest
+    single-GPU configuration, in the tile shapes the autotuner picks there;
+    two output sectors compared with the oracle."""
+    left, right, nmax = bonds_of("cfg5")
+    print(f"[heff chi 2048] left={left}", flush=True)
+    W, qw, Le, Re, th = make_case(left, right, nmax, seed=51)
+    qs = sorted(left)
+    pick = {qs[0], qs[len(qs) // 2]}
+    ref = oheff.heff2_block(Le, W[0], W[0], Re, th, left, right, qw, nmax + 1, out_sectors=pick)
+    for prec, bar in (("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 1e-4)):
+        got = run_gpu(tnt, W, qw, Le, Re, th, prec)
+        sel = {k: ref[k] for k in ref if k[0] in pick}
+        err = rel_err(got, sel)
+        print(f"  {prec}: sampled rel err = {err:.3e} over {len(sel)} blocks", flush=True)
+        assert err <= bar
+
+
 def test_heff_rejects_charge_violation(tnt):
     """A descriptor edited in place after a successful call is parsed again
     (the library caches operators by descriptor content, not by address)."""
