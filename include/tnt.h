@@ -184,7 +184,9 @@ int64_t tnt_heff2_flops(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt_
 /* ------------------------------------------------------------------------
  * Lowest eigenpair of H_eff (Sec. 4.2, network minimisation; the initial
  * guess is the current theta).  Plain Lanczos in FP64: alpha/beta
- * recurrence, two passes of full re-orthogonalisation, stop at kmax steps
+ * recurrence with classical Gram-Schmidt against all previous Krylov
+ * vectors, applied twice (the first pass also removes the three-term
+ * part alpha_j v_j + beta_{j-1} v_{j-1}), stop at kmax steps
  * or when beta_j <= beta_tol * max(1, |alpha_0|); lowest Ritz pair of the
  * tridiagonal matrix; then one FP64 matvec for the Rayleigh quotient
  * E_refined and the residual |H psi - E psi|.  The matvecs inside the

@@ -114,14 +114,13 @@ void bind_batch_envs(Ctx& c, BatchHeff& b, const std::vector<const double*>& Lre
 // ---------------------------------------------------------------------------
 // batched Lanczos
 // ---------------------------------------------------------------------------
-// per-instance scalar block (stride S): re-orthogonalisation coefficients,
-// <v_j, w> pairs (alpha_j = real part), beta_j, next-vector scales, |w|^2,
-// the refinement's <psi, H psi> pair and the Ritz coefficients
+// per-instance scalar block (stride S): the recurrence's <v_j, H v_j> pairs
+// (alpha_j = real part), beta_j, next-vector scales, |w|^2, the
+// refinement's <psi, H psi> pair and the Ritz coefficients
 struct Slots {
-  int coef, apair, beta, scale, nrm2, e, y, S;
+  int apair, beta, scale, nrm2, e, y, S;
   explicit Slots(int kmax) {
-    coef = 0;
-    apair = coef + 2 * (kmax + 1);
+    apair = 0;
     beta = apair + 2 * kmax;
     scale = beta + kmax;
     nrm2 = scale + kmax;
@@ -139,55 +138,60 @@ void BatchKrylov::reserve(Ctx& c, int kmax_, int64_t N_, int ninst_, int nblk) {
   basis.ensure(&c.pool, (size_t)kmax * 2 * N * sizeof(double));
   w.ensure(&c.pool, (size_t)2 * N * sizeof(double));
   part.ensure(&c.pool, (size_t)nblk * 2 * (kmax + 1) * sizeof(double));
+  part2.ensure(&c.pool, (size_t)nblk * 2 * (kmax + 1) * sizeof(double));
   scal.ensure(&c.pool, (size_t)ninst * S * sizeof(double));
   kdev.ensure(&c.pool, (size_t)std::max(1, ninst) * sizeof(int));
   stage.ensure((size_t)ninst * S + 8);
 }
 
-static void lanczos_step_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, int j,
-                                 const tnt_lanczos_params& p, const hipEvent_t* ev) {
+// Step j of the recurrence for every instance, on the device:
+//   w = H v_j;  c = V^H w over v_0 .. v_j (alpha_j = Re c_j);
+//   w -= V c;  c' = V^H w;  w -= V c'  (classical Gram-Schmidt, twice);
+//   beta_j = |w|;  v_{j+1} = w / beta_j (zero after a breakdown).
+// Subtracting the full projection also removes alpha_j v_j and
+// beta_{j-1} v_{j-1}, the three-term part of the recurrence.
+static void lanczos_step_batched(Ctx& c, HeffOp& op, const SegLayout& seg, BatchKrylov& K,
+                                 int j, const tnt_lanczos_params& p, const hipEvent_t* ev) {
   const Slots sl(K.kmax);
   const int64_t N = K.N, ld = 2 * N;
-  const int S = K.S, m = b.ninst(), nb = b.seg.nblk;
-  const SegBlock* blk = b.seg.d_blk();
-  const int2* ib = b.seg.d_inst();
+  const int S = K.S, nb = seg.nblk, k = j + 1;
+  const SegBlock* blk = seg.d_blk();
+  const int2* ib = seg.d_inst();
   double* V = K.basis.as<double>();
   double* w = K.w.as<double>();
   double* sc = K.scal.as<double>();
-  double* part = K.part.as<double>();
+  double* pa = K.part.as<double>();
+  double* pb = K.part2.as<double>();
   double* vj = V + (size_t)j * ld;
   if (ev) TNT_HIP(hipEventRecord(ev[0], c.stream));
-  b.op->apply(vj, vj + N, w, w + N, p.precision, ev ? ev + 2 : nullptr);
+  op.apply(vj, vj + N, w, w + N, p.precision, ev ? ev + 2 : nullptr);
   if (ev) TNT_HIP(hipEventRecord(ev[1], c.stream));
-  launch_seg_multidot(vj, ld, 1, w, N, blk, nb, part, c.stream);
-  launch_seg_reduce(part, 2, ib, m, sc + sl.apair + 2 * j, S, c.stream);
-  launch_seg_axpy2(vj, sc + sl.apair + 2 * j, S, j > 0 ? V + (size_t)(j - 1) * ld : nullptr,
-                   j > 0 ? sc + sl.beta + j - 1 : nullptr, S, w, N, blk, nb, c.stream);
-  for (int pass = 0; pass < 2; ++pass) {
-    launch_seg_multidot(V, ld, j + 1, w, N, blk, nb, part, c.stream);
-    launch_seg_reduce(part, 2 * (j + 1), ib, m, sc + sl.coef, S, c.stream);
-    launch_seg_multiaxpy_norm(V, ld, j + 1, sc + sl.coef, S, w, N, blk, nb, part, c.stream);
-  }
-  launch_seg_reduce(part, 1, ib, m, sc + sl.nrm2, S, c.stream);
-  launch_seg_lanczos_beta(sc + sl.nrm2, S, sc + sl.apair, S, p.beta_tol, j, K.kdev.as<int>(),
-                          sc + sl.beta + j, S, sc + sl.scale + j, S, m, c.stream);
-  if (j + 1 < K.kmax)
-    launch_seg_scale_copy(w, V + (size_t)(j + 1) * ld, N, blk, nb, sc + sl.scale + j, S, 0,
-                          c.stream);
+  launch_seg_cgs_dot(V, ld, k, w, N, blk, nb, pa, c.stream);
+  launch_seg_cgs_update_dot(V, ld, k, pa, w, N, blk, ib, nb, pb, sc + sl.apair + 2 * j, S,
+                            c.stream);
+  launch_seg_cgs_update_norm(V, ld, k, pb, w, N, blk, ib, nb, pa, c.stream);
+  launch_seg_cgs_next(pa, w, j + 1 < K.kmax ? V + (size_t)(j + 1) * ld : nullptr, N, blk, ib, nb,
+                      sc, S, sl.nrm2, sl.apair, sl.beta + j, sl.scale + j, p.beta_tol, j,
+                      K.kdev.as<int>(), c.stream);
 }
 
-void lanczos_run_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, double* x,
-                         const tnt_lanczos_params& p, std::vector<LanczosOut>& out, Timers* tm) {
-  const int m = b.ninst();
-  const int64_t N = b.N, ld = 2 * N;
-  const SegBlock* blk = b.seg.d_blk();
-  const int2* ib = b.seg.d_inst();
-  const int nb = b.seg.nblk;
+void lanczos_core(Ctx& c, HeffOp& op, const SegLayout& seg, const std::vector<int64_t>& n,
+                  BatchKrylov& K, double* x, const tnt_lanczos_params& p,
+                  std::vector<LanczosOut>& out, Timers* tm) {
+  const int m = (int)n.size();
+  int64_t N = 0;
+  for (int64_t v : n) N += v;
+  const int64_t ld = 2 * N;
+  const SegBlock* blk = seg.d_blk();
+  const int2* ib = seg.d_inst();
+  const int nb = seg.nblk;
+  // the fused re-orthogonalisation kernels hold at most 32 coefficients
+  if (p.kmax < 1 || p.kmax > 32) fail(TNT_E_ARG, "kmax must be in [1, 32]");
   // per-instance step counts: the Krylov space has dimension <= n_i
   std::vector<int> kmax_i(m);
   int kmax = 0;
   for (int i = 0; i < m; ++i) {
-    kmax_i[i] = (int)std::min<int64_t>(p.kmax, b.n[i]);
+    kmax_i[i] = (int)std::min<int64_t>(p.kmax, n[i]);
     kmax = std::max(kmax, kmax_i[i]);
   }
   K.reserve(c, kmax, N, m, nb);
@@ -197,7 +201,9 @@ void lanczos_run_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, double* x,
   double* w = K.w.as<double>();
   double* sc = K.scal.as<double>();
   double* part = K.part.as<double>();
-  TNT_HIP(hipMemcpyAsync(K.kdev.ptr, kmax_i.data(), m * sizeof(int), hipMemcpyHostToDevice,
+  // through the pinned stage, so the copy does not wait for the stream
+  memcpy(K.stage.p, kmax_i.data(), m * sizeof(int));
+  TNT_HIP(hipMemcpyAsync(K.kdev.ptr, K.stage.p, m * sizeof(int), hipMemcpyHostToDevice,
                          c.stream));
   // v0 = x / |x| per instance
   launch_seg_norm2(x, N, blk, nb, part, c.stream);
@@ -211,7 +217,6 @@ void lanczos_run_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, double* x,
     if (x2 <= 0.0) fail(TNT_E_ARG, "start vector is zero");
   }
   launch_seg_scale_copy(x, V, N, blk, nb, sc + sl.nrm2, S, 1, c.stream);
-
   if (tm) {
     while ((int)c.step_ev.size() < 6 * kmax) {
       hipEvent_t e;
@@ -219,10 +224,10 @@ void lanczos_run_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, double* x,
       c.step_ev.push_back(e);
     }
   }
-  HeffOp& op = *b.op;
   if (c.graphs && !tm) {
     op.prepare(V, V + N, w, w + N, p.precision);
-    std::vector<const void*> key = {V, w, K.part.ptr, K.scal.ptr, K.kdev.ptr, b.seg.dev.ptr,
+    std::vector<const void*> key = {V, w, K.part.ptr, K.part2.ptr, K.scal.ptr, K.kdev.ptr,
+                                    seg.dev.ptr,
                                     (const void*)(intptr_t)kmax,
                                     (const void*)(intptr_t)p.precision, op.L_re, op.L_im,
                                     op.R_re, op.R_im};
@@ -240,7 +245,7 @@ void lanczos_run_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, double* x,
       hipError_t ce = hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed);
       if (ce == hipSuccess) {
         try {
-          for (int j = 0; j < kmax; ++j) lanczos_step_batched(c, b, K, j, p, nullptr);
+          for (int j = 0; j < kmax; ++j) lanczos_step_batched(c, op, seg, K, j, p, nullptr);
         } catch (...) {
           (void)hipStreamEndCapture(c.stream, &g);
           if (g) (void)hipGraphDestroy(g);
@@ -262,7 +267,7 @@ void lanczos_run_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, double* x,
     TNT_HIP(hipGraphLaunch(op.graph.exec, c.stream));
   } else {
     for (int j = 0; j < kmax; ++j)
-      lanczos_step_batched(c, b, K, j, p, tm ? &c.step_ev[6 * j] : nullptr);
+      lanczos_step_batched(c, op, seg, K, j, p, tm ? &c.step_ev[6 * j] : nullptr);
   }
   // every instance's alpha / beta in one round trip
   TNT_HIP(hipMemcpyAsync(K.stage.p, sc, (size_t)m * S * sizeof(double), hipMemcpyDeviceToHost,
@@ -313,7 +318,7 @@ void lanczos_run_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, double* x,
   launch_seg_scale_copy(x, x, N, blk, nb, sc + sl.nrm2, S, 1, c.stream);
   // FP64 refinement for all instances: E_i = Re <psi_i, H psi_i>, r_i
   op.apply(x, x + N, w, w + N, TNT_FP64);
-  launch_seg_multidot(x, ld, 1, w, N, blk, nb, part, c.stream);
+  launch_seg_cgs_dot(x, ld, 1, w, N, blk, nb, part, c.stream);
   launch_seg_reduce(part, 2, ib, m, sc + sl.e, S, c.stream);
   launch_seg_axpy2(x, sc + sl.e, S, nullptr, nullptr, S, w, N, blk, nb, c.stream);
   launch_seg_norm2(w, N, blk, nb, part, c.stream);
@@ -328,6 +333,11 @@ void lanczos_run_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, double* x,
     if (!std::isfinite(out[i].E) || !std::isfinite(out[i].residual))
       fail(TNT_E_NONFINITE, "refined energy is not finite");
   }
+}
+
+void lanczos_run_batched(Ctx& c, BatchHeff& b, BatchKrylov& K, double* x,
+                         const tnt_lanczos_params& p, std::vector<LanczosOut>& out, Timers* tm) {
+  lanczos_core(c, *b.op, b.seg, b.n, K, x, p, out, tm);
 }
 
 }  // namespace tnt

@@ -11,19 +11,6 @@
 
 namespace tnt {
 
-// Block table of the segmented Krylov kernels over a batch vector.
-struct SegLayout {
-  std::vector<SegBlock> blk;
-  std::vector<int2> inst_blk;  // per instance: [first, last) block
-  DevBuf dev;                  // blk then inst_blk
-  int nblk = 0;
-  const SegBlock* d_blk() const { return dev.as<SegBlock>(); }
-  const int2* d_inst() const {
-    return reinterpret_cast<const int2*>(dev.as<char>() + blk.size() * sizeof(SegBlock));
-  }
-  void build(Ctx& c, const std::vector<int64_t>& off, const std::vector<int64_t>& n);
-};
-
 // Device copy of a run list, re-uploaded only when the list changes (the
 // host list stays alive with the table, so no wait is needed after an
 // upload; an event guards against rewriting it while a copy is pending).
@@ -60,14 +47,6 @@ void build_batch(Ctx& c, BatchHeff& b, const std::vector<std::shared_ptr<HeffOp>
 void bind_batch_envs(Ctx& c, BatchHeff& b, const std::vector<const double*>& Lre,
                      const std::vector<const double*>& Lim, const std::vector<const double*>& Rre,
                      const std::vector<const double*>& Rim);
-
-struct BatchKrylov {
-  int kmax = 0, ninst = 0, S = 0;  // S: per-instance scalar stride
-  int64_t N = 0;
-  DevBuf basis, w, part, scal, kdev;
-  HostStage stage;
-  void reserve(Ctx& c, int kmax, int64_t N, int ninst, int nblk);
-};
 
 // Batched lowest eigenpairs: x (re plane of N doubles, then im plane) holds
 // the start vectors on entry and the normalised ground vectors on exit;

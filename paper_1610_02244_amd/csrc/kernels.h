@@ -157,34 +157,9 @@ void launch_scale_host(double* x, int64_t n, double scale, hipStream_t s);
 // deterministic (fixed per-block order, then one block reduces the partials).
 constexpr int RED_BLOCKS = 512;
 constexpr int RED_THREADS = 256;
-// partial[b*2k + 2i + {0,1}] = block b's share of <V_i, w> (re, im), i < k.
-void launch_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n,
-                     double* partial, hipStream_t s);
-// out[2i + {0,1}] = sum over blocks of partial (i < k), optionally also
-// writing the scalar into the given device slot.
+// out[j] = sum over blocks b < nblk of partial[b * k2 + j], j < k2
 void launch_reduce_partials(const double* partial, int k2, int nblk, double* out,
                             hipStream_t s);
-// w -= sum_i c_i V_i with complex coefficients c (device, 2k doubles, k <= 32), and
-// nrm_partial[b] = block b's share of |w|^2 after the update.
-void launch_multiaxpy_norm(const double* V, int64_t ld, int k, const double* c, double* w,
-                           int64_t n, double* nrm_partial, hipStream_t s);
-// w -= a * v1 + b * v0 (real scalars on the device: a = *a_dev, b = *b_dev;
-// v0 may be NULL).
-void launch_axpy2(const double* v1, const double* a_dev, const double* v0,
-                       const double* b_dev, double* w, int64_t n, hipStream_t s);
-// dst = src / sqrt(*nrm2_dev)
-void launch_normalize_copy(const double* src, double* dst, int64_t n, const double* nrm2_dev,
-                           hipStream_t s);
-// dst = src * (*scale_dev)
-void launch_scale_copy(const double* src, double* dst, int64_t n, const double* scale_dev,
-                       hipStream_t s);
-// beta = sqrt(*nrm2); scale = 1 / beta, or 0 at breakdown (beta <= tol *
-// max(1, |*alpha0|), or not finite); one thread
-void launch_lanczos_beta(const double* nrm2_dev, const double* alpha0_dev, double tol,
-                         double* beta_dev, double* scale_dev, hipStream_t s);
-// out = sum_i y_i V_i (real y on the host copy uploaded to y_dev)
-void launch_combine_basis(const double* V, int64_t ld, int k, const double* y_dev,
-                          double* out, int64_t n, hipStream_t s);
 // partial sums of |x|^2 over 2n doubles
 void launch_norm2_partial(const double* x, int64_t n2, double* partial, hipStream_t s);
 // finite check: flag[0] set to 1 if any non-finite among n doubles
@@ -202,28 +177,44 @@ struct SegBlock {
   int32_t pad;
   int64_t lo, hi;  // complex entry range
 };
-void launch_seg_multidot(const double* V, int64_t ld, int k, const double* w, int64_t N,
-                         const SegBlock* blk, int nblk, double* partial, hipStream_t s);
 void launch_seg_reduce(const double* partial, int k2, const int2* inst_blk, int ninst,
                        double* out, int out_stride, hipStream_t s);
 void launch_seg_axpy2(const double* v1, const double* a, int a_stride, const double* v0,
                       const double* b, int b_stride, double* w, int64_t N, const SegBlock* blk,
                       int nblk, hipStream_t s);
-void launch_seg_multiaxpy_norm(const double* V, int64_t ld, int k, const double* c,
-                               int c_stride, double* w, int64_t N, const SegBlock* blk,
-                               int nblk, double* nrm_partial, hipStream_t s);
 void launch_seg_norm2(const double* x, int64_t N, const SegBlock* blk, int nblk, double* part,
                       hipStream_t s);
-void launch_seg_lanczos_beta(const double* nrm2, int nrm_stride, const double* alpha0,
-                             int a_stride, double tol, int j, const int* kmax, double* beta,
-                             int b_stride, double* scale, int s_stride, int ninst,
-                             hipStream_t s);
 // mode 0: dst = src * scale_i; mode 1: dst = src / sqrt(scale_i) (0 if <= 0)
 void launch_seg_scale_copy(const double* src, double* dst, int64_t N, const SegBlock* blk,
                            int nblk, const double* scale, int stride, int mode, hipStream_t s);
 void launch_seg_combine_basis(const double* V, int64_t ld, int k, const double* y, int y_stride,
                               double* out, int64_t N, const SegBlock* blk, int nblk,
                               hipStream_t s);
+// Fused recurrence steps over k = 1 .. 32 basis vectors V_0 .. V_{k-1}.
+// Each kernel leaves per-workgroup partial sums part[b * W + o] (W = 2k
+// values for projections, 1 for norms; nblk * W doubles) and the next
+// kernel adds up its instance's partials itself, in a fixed order.
+// Partials of c = V^H w, (re, im) pairs:
+void launch_seg_cgs_dot(const double* V, int64_t ld, int k, const double* w, int64_t N,
+                        const SegBlock* blk, int nblk, double* part, hipStream_t s);
+// c = instance sum of part_in; w -= V c; partials of V^H w into part_out;
+// the pair of V_{k-1} in c goes to pair_dst + inst * S when pair_dst is set.
+void launch_seg_cgs_update_dot(const double* V, int64_t ld, int k, const double* part_in,
+                               double* w, int64_t N, const SegBlock* blk, const int2* inst_blk,
+                               int nblk, double* part_out, double* pair_dst, int S,
+                               hipStream_t s);
+// c = instance sum of part_in; w -= V c; partials of |w|^2 into part_out.
+void launch_seg_cgs_update_norm(const double* V, int64_t ld, int k, const double* part_in,
+                                double* w, int64_t N, const SegBlock* blk, const int2* inst_blk,
+                                int nblk, double* part_out, hipStream_t s);
+// nrm2 = instance sum of part_in (one value per workgroup); in instance i's
+// scalar block sc + i * S: nrm2, beta_j = sqrt(nrm2), scale_j = 1 / beta_j
+// unless j >= kmax[i] - 1 or beta_j <= tol * max(1, |alpha_0|) or is not
+// finite (then 0); dst = w * scale_j when dst is set.
+void launch_seg_cgs_next(const double* part_in, const double* w, double* dst, int64_t N,
+                         const SegBlock* blk, const int2* inst_blk, int nblk, double* sc, int S,
+                         int nrm2_slot, int alpha0_slot, int beta_slot, int scale_slot, double tol,
+                         int j, const int* kmax, hipStream_t s);
 // contiguous runs of doubles between device buffers (gathers / scatters)
 struct CopyRun {
   const double* src;

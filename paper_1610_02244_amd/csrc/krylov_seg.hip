@@ -25,47 +25,6 @@ __device__ inline double seg_block_sum(double v, double* sh) {
 
 constexpr int SEG_MAXK = 32;
 
-// partial[b * 2k + 2i + {0,1}] = block b's share of <V_i, w> (re, im)
-__global__ __launch_bounds__(RED_THREADS) void seg_multidot_kernel(
-    const double* __restrict__ V, int64_t ld, int k, const double* __restrict__ w, int64_t N,
-    const SegBlock* __restrict__ blk, double* __restrict__ partial) {
-  __shared__ double sh[4];
-  const SegBlock sb = blk[blockIdx.x];
-  for (int i0 = 0; i0 < k; i0 += 8) {
-    double accr[8], acci[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) { accr[u] = 0; acci[u] = 0; }
-    for (int64_t x = sb.lo + threadIdx.x; x < sb.hi; x += RED_THREADS) {
-      const double wr = w[x], wi = w[N + x];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (i0 + u < k) {
-          const double vr = V[(i0 + u) * ld + x], vi = V[(i0 + u) * ld + N + x];
-          accr[u] += vr * wr + vi * wi;
-          acci[u] += vr * wi - vi * wr;
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (i0 + u < k) {
-        const double r = seg_block_sum(accr[u], sh);
-        const double m = seg_block_sum(acci[u], sh);
-        if (threadIdx.x == 0) {
-          partial[blockIdx.x * 2 * k + 2 * (i0 + u)] = r;
-          partial[blockIdx.x * 2 * k + 2 * (i0 + u) + 1] = m;
-        }
-      }
-    }
-  }
-}
-
-void launch_seg_multidot(const double* V, int64_t ld, int k, const double* w, int64_t N,
-                         const SegBlock* blk, int nblk, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(seg_multidot_kernel, dim3(nblk), dim3(RED_THREADS), 0, s, V, ld, k, w, N,
-                     blk, partial);
-}
-
 // out[inst * out_stride + j] = sum over the instance's blocks of
 // partial[b * k2 + j], in block order
 __global__ void seg_reduce_kernel(const double* __restrict__ partial, int k2,
@@ -112,41 +71,6 @@ void launch_seg_axpy2(const double* v1, const double* a, int a_stride, const dou
                      b, b_stride, w, N, blk);
 }
 
-// w -= sum_i c_{inst,i} V_i (complex c at c + inst * c_stride), then |w|^2
-// partials per block
-__global__ __launch_bounds__(RED_THREADS) void seg_multiaxpy_norm_kernel(
-    const double* __restrict__ V, int64_t ld, int k, const double* __restrict__ c, int c_stride,
-    double* __restrict__ w, int64_t N, const SegBlock* __restrict__ blk,
-    double* __restrict__ nrm_partial) {
-  __shared__ double sh[4];
-  __shared__ double cs[2 * SEG_MAXK];
-  const SegBlock sb = blk[blockIdx.x];
-  if (threadIdx.x < 2 * k) cs[threadIdx.x] = c[sb.inst * c_stride + threadIdx.x];
-  __syncthreads();
-  double acc = 0;
-  for (int64_t x = sb.lo + threadIdx.x; x < sb.hi; x += RED_THREADS) {
-    double wr = w[x], wi = w[N + x];
-    for (int i = 0; i < k; ++i) {
-      const double vr = V[i * ld + x], vi = V[i * ld + N + x];
-      const double cr = cs[2 * i], ci = cs[2 * i + 1];
-      wr -= cr * vr - ci * vi;
-      wi -= cr * vi + ci * vr;
-    }
-    w[x] = wr;
-    w[N + x] = wi;
-    acc += wr * wr + wi * wi;
-  }
-  const double r = seg_block_sum(acc, sh);
-  if (threadIdx.x == 0) nrm_partial[blockIdx.x] = r;
-}
-
-void launch_seg_multiaxpy_norm(const double* V, int64_t ld, int k, const double* c,
-                               int c_stride, double* w, int64_t N, const SegBlock* blk,
-                               int nblk, double* nrm_partial, hipStream_t s) {
-  hipLaunchKernelGGL(seg_multiaxpy_norm_kernel, dim3(nblk), dim3(RED_THREADS), 0, s, V, ld, k, c,
-                     c_stride, w, N, blk, nrm_partial);
-}
-
 // |x|^2 partials per block
 __global__ __launch_bounds__(RED_THREADS) void seg_norm2_kernel(const double* __restrict__ x,
                                                                 int64_t N,
@@ -164,31 +88,6 @@ __global__ __launch_bounds__(RED_THREADS) void seg_norm2_kernel(const double* __
 void launch_seg_norm2(const double* x, int64_t N, const SegBlock* blk, int nblk, double* part,
                       hipStream_t s) {
   hipLaunchKernelGGL(seg_norm2_kernel, dim3(nblk), dim3(RED_THREADS), 0, s, x, N, blk, part);
-}
-
-// Per instance (one thread each): beta = sqrt(|w|^2); scale = 1 / beta when
-// step j is not the instance's last (j < kmax_i - 1) and beta is above the
-// breakdown tolerance tol * max(1, |alpha_0|) and finite, else 0.
-__global__ void seg_lanczos_beta_kernel(const double* __restrict__ nrm2, int nrm_stride,
-                                        const double* __restrict__ alpha0, int a_stride,
-                                        double tol, int j, const int* __restrict__ kmax,
-                                        double* __restrict__ beta, int b_stride,
-                                        double* __restrict__ scale, int s_stride, int ninst) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ninst) return;
-  const double b = sqrt(nrm2[i * nrm_stride]);
-  beta[i * b_stride] = b;
-  const double thr = tol * fmax(1.0, fabs(alpha0[i * a_stride]));
-  scale[i * s_stride] = (j < kmax[i] - 1 && b > thr && b < INFINITY) ? 1.0 / b : 0.0;
-}
-
-void launch_seg_lanczos_beta(const double* nrm2, int nrm_stride, const double* alpha0,
-                             int a_stride, double tol, int j, const int* kmax, double* beta,
-                             int b_stride, double* scale, int s_stride, int ninst,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(seg_lanczos_beta_kernel, dim3((ninst + 63) / 64), dim3(64), 0, s, nrm2,
-                     nrm_stride, alpha0, a_stride, tol, j, kmax, beta, b_stride, scale, s_stride,
-                     ninst);
 }
 
 // dst = src * f_i with f_i = scale[i * stride] (mode 0) or
@@ -235,6 +134,289 @@ void launch_seg_combine_basis(const double* V, int64_t ld, int k, const double* 
                               hipStream_t s) {
   hipLaunchKernelGGL(seg_combine_basis_kernel, dim3(nblk), dim3(RED_THREADS), 0, s, V, ld, k, y,
                      y_stride, out, N, blk);
+}
+
+// ---------------------------------------------------------------------------
+// Fused steps of the re-orthogonalised recurrence.  Each kernel leaves
+// per-workgroup partial sums part[b * W + o] (W values per workgroup) and
+// the next kernel starts by adding up its instance's partials, every
+// workgroup on its own in the same fixed order: all workgroups obtain
+// bitwise the same coefficients without a separate reduction launch and
+// without any communication inside a launch.  The basis size K is a
+// template parameter, so the loads of all K vectors for one entry are
+// issued together.
+// ---------------------------------------------------------------------------
+
+// sum over the instance's workgroups [b0, b1) of part[b * W + o], o < W,
+// into out[o] (LDS); every thread of the workgroup must call it
+template <int W>
+__device__ inline void instance_sums(const double* __restrict__ part, int b0, int b1,
+                                     double* red, double* out) {
+  constexpr int NSUB = RED_THREADS / W;  // workgroup subsets, each over every NSUB-th partial
+  const int t = threadIdx.x;
+  if constexpr (W == 1) {
+    double v = 0;
+    for (int b = b0 + t; b < b1; b += RED_THREADS) v += part[b];
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s, 64);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return;
+  }
+  if (t < NSUB * W) {
+    const int o = t % W, sub = t / W;
+    double v = 0;
+    for (int b = b0 + sub; b < b1; b += NSUB) v += part[(size_t)b * W + o];
+    red[sub * W + o] = v;
+  }
+  __syncthreads();
+  if (t < W) {
+    double v = 0;
+    for (int sub = 0; sub < NSUB; ++sub) v += red[sub * W + t];
+    out[t] = v;
+  }
+  __syncthreads();
+}
+
+// smallest power of two >= n
+constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
+
+// P values per lane in (P a power of two <= 64); lane L < P out with the
+// wave total of value L.  Recursive halving, stage by stage over all
+// values so the shuffles of one stage are independent: each stage sends
+// half of the remaining values to the partner lane (P - 1 shuffles for
+// P = 64, plus one full exchange per lane bit above P).
+template <int P>
+__device__ inline double wave_reduce_scatter(double* v) {
+  static_assert(P >= 1 && P <= 64 && (P & (P - 1)) == 0, "P must be a power of two <= 64");
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 32; o >= P; o >>= 1) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[i] += __shfl_xor(v[i], o, 64);
+  }
+#pragma unroll
+  for (int o = P / 2; o >= 1; o >>= 1) {
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < o; ++i) {
+      const double lo = v[i], hi = v[i + o];
+      v[i] = (up ? hi : lo) + __shfl_xor(up ? lo : hi, o, 64);
+    }
+  }
+  return v[0];
+}
+
+// workgroup totals of the first W of P per-thread values (P =
+// pow2_at_least(W), the rest zero) into part[blockIdx.x * W + o]; red
+// holds 4 * P doubles
+template <int W, int P>
+__device__ inline void block_partials(double* v, double* red, double* part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double r = wave_reduce_scatter<P>(v);
+  if (lane < P) red[wv * P + lane] = r;
+  __syncthreads();
+  if (threadIdx.x < W) {
+    const int o = threadIdx.x;
+    part[(size_t)blockIdx.x * W + o] = (red[o] + red[P + o]) + (red[2 * P + o] + red[3 * P + o]);
+  }
+}
+
+// partials of c = V^H w over V_0 .. V_{K-1}, as (re, im) pairs
+template <int K>
+__global__ __launch_bounds__(RED_THREADS) void seg_cgs_dot_kernel(
+    const double* __restrict__ V, int64_t ld, const double* __restrict__ w, int64_t N,
+    const SegBlock* __restrict__ blk, double* __restrict__ part) {
+  constexpr int P = pow2_at_least(2 * K);
+  __shared__ double red[4 * P];
+  const SegBlock sb = blk[blockIdx.x];
+  double acc[P];
+#pragma unroll
+  for (int o = 0; o < P; ++o) acc[o] = 0;
+  for (int64_t x = sb.lo + threadIdx.x; x < sb.hi; x += RED_THREADS) {
+    const double wr = w[x], wi = w[N + x];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const double vr = V[i * ld + x], vi = V[i * ld + N + x];
+      acc[2 * i] += vr * wr + vi * wi;
+      acc[2 * i + 1] += vr * wi - vi * wr;
+    }
+  }
+  block_partials<2 * K, P>(acc, red, part);
+}
+
+// c = the instance's sum of part_in (2K values); w -= V c; partials of
+// V^H w into part_out.  The instance's first workgroup writes the pair of
+// V_{K-1} to pair_dst + inst * S (the recurrence's alpha_j).
+template <int K>
+__global__ __launch_bounds__(RED_THREADS) void seg_cgs_update_dot_kernel(
+    const double* __restrict__ V, int64_t ld, const double* __restrict__ part_in,
+    double* __restrict__ w, int64_t N, const SegBlock* __restrict__ blk,
+    const int2* __restrict__ inst_blk, double* __restrict__ part_out,
+    double* __restrict__ pair_dst, int S) {
+  constexpr int P = pow2_at_least(2 * K);
+  __shared__ double red[RED_THREADS > 4 * P ? RED_THREADS : 4 * P];
+  __shared__ double cs[2 * K];
+  const SegBlock sb = blk[blockIdx.x];
+  const int2 r = inst_blk[sb.inst];
+  instance_sums<2 * K>(part_in, r.x, r.y, red, cs);
+  if (pair_dst && blockIdx.x == r.x && threadIdx.x < 2)
+    pair_dst[(size_t)sb.inst * S + threadIdx.x] = cs[2 * (K - 1) + threadIdx.x];
+  double acc[P];
+#pragma unroll
+  for (int o = 0; o < P; ++o) acc[o] = 0;
+  for (int64_t x = sb.lo + threadIdx.x; x < sb.hi; x += RED_THREADS) {
+    double wr = w[x], wi = w[N + x];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const double vr = V[i * ld + x], vi = V[i * ld + N + x];
+      const double cr = cs[2 * i], ci = cs[2 * i + 1];
+      wr -= cr * vr - ci * vi;
+      wi -= cr * vi + ci * vr;
+    }
+    w[x] = wr;
+    w[N + x] = wi;
+    // read the basis again (from cache) rather than holding 2K values in
+    // registers across the update: half the registers, twice the occupancy
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const double vr = V[i * ld + x], vi = V[i * ld + N + x];
+      acc[2 * i] += vr * wr + vi * wi;
+      acc[2 * i + 1] += vr * wi - vi * wr;
+    }
+  }
+  __syncthreads();  // red is reused
+  block_partials<2 * K, P>(acc, red, part_out);
+}
+
+// c = the instance's sum of part_in; w -= V c; partials of |w|^2 into
+// part_out (one value per workgroup)
+template <int K>
+__global__ __launch_bounds__(RED_THREADS) void seg_cgs_update_norm_kernel(
+    const double* __restrict__ V, int64_t ld, const double* __restrict__ part_in,
+    double* __restrict__ w, int64_t N, const SegBlock* __restrict__ blk,
+    const int2* __restrict__ inst_blk, double* __restrict__ part_out) {
+  __shared__ double red[RED_THREADS];
+  __shared__ double cs[2 * K];
+  const SegBlock sb = blk[blockIdx.x];
+  const int2 r = inst_blk[sb.inst];
+  instance_sums<2 * K>(part_in, r.x, r.y, red, cs);
+  double acc[1] = {0};
+  for (int64_t x = sb.lo + threadIdx.x; x < sb.hi; x += RED_THREADS) {
+    double wr = w[x], wi = w[N + x];
+    double vr[K], vi[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      vr[i] = V[i * ld + x];
+      vi[i] = V[i * ld + N + x];
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const double cr = cs[2 * i], ci = cs[2 * i + 1];
+      wr -= cr * vr[i] - ci * vi[i];
+      wi -= cr * vi[i] + ci * vr[i];
+    }
+    w[x] = wr;
+    w[N + x] = wi;
+    acc[0] += wr * wr + wi * wi;
+  }
+  __syncthreads();
+  block_partials<1, 1>(acc, red, part_out);
+}
+
+// nrm2 = the instance's sum of part_in; beta_j = sqrt(nrm2); scale_j =
+// 1 / beta_j unless j >= kmax_i - 1, beta_j <= tol * max(1, |alpha_0|) or
+// beta_j is not finite (then 0); dst = w * scale_j when dst is set.  The
+// instance's first workgroup stores nrm2, beta_j and scale_j in its scalar
+// block sc + inst * S.
+__global__ __launch_bounds__(RED_THREADS) void seg_cgs_next_kernel(
+    const double* __restrict__ part_in, const double* __restrict__ w, double* __restrict__ dst,
+    int64_t N, const SegBlock* __restrict__ blk, const int2* __restrict__ inst_blk,
+    double* __restrict__ sc, int S, int nrm2_slot, int alpha0_slot, int beta_slot,
+    int scale_slot, double tol, int j, const int* __restrict__ kmax) {
+  __shared__ double red[RED_THREADS];
+  __shared__ double tot[1];
+  const SegBlock sb = blk[blockIdx.x];
+  const int2 r = inst_blk[sb.inst];
+  instance_sums<1>(part_in, r.x, r.y, red, tot);
+  double* si = sc + (size_t)sb.inst * S;
+  const double n2 = tot[0];
+  const double b = sqrt(n2);
+  const double thr = tol * fmax(1.0, fabs(si[alpha0_slot]));
+  const double f = (j < kmax[sb.inst] - 1 && b > thr && b < INFINITY) ? 1.0 / b : 0.0;
+  if (blockIdx.x == r.x && threadIdx.x == 0) {
+    si[nrm2_slot] = n2;
+    si[beta_slot] = b;
+    si[scale_slot] = f;
+  }
+  if (!dst) return;
+  for (int64_t x = sb.lo + threadIdx.x; x < sb.hi; x += RED_THREADS) {
+    dst[x] = w[x] * f;
+    dst[N + x] = w[N + x] * f;
+  }
+}
+
+// K = 1 .. 32 dispatch
+#define TNT_K_CASES(M) \
+  M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16) \
+  M(17) M(18) M(19) M(20) M(21) M(22) M(23) M(24) M(25) M(26) M(27) M(28) M(29) M(30) M(31) M(32)
+
+void launch_seg_cgs_dot(const double* V, int64_t ld, int k, const double* w, int64_t N,
+                        const SegBlock* blk, int nblk, double* part, hipStream_t s) {
+  switch (k) {
+#define TNT_CASE(KK)                                                                          \
+  case KK:                                                                                    \
+    hipLaunchKernelGGL(seg_cgs_dot_kernel<KK>, dim3(nblk), dim3(RED_THREADS), 0, s, V, ld, w, \
+                       N, blk, part);                                                         \
+    break;
+    TNT_K_CASES(TNT_CASE)
+#undef TNT_CASE
+    default: break;
+  }
+}
+
+void launch_seg_cgs_update_dot(const double* V, int64_t ld, int k, const double* part_in,
+                               double* w, int64_t N, const SegBlock* blk, const int2* inst_blk,
+                               int nblk, double* part_out, double* pair_dst, int S,
+                               hipStream_t s) {
+  switch (k) {
+#define TNT_CASE(KK)                                                                             \
+  case KK:                                                                                       \
+    hipLaunchKernelGGL(seg_cgs_update_dot_kernel<KK>, dim3(nblk), dim3(RED_THREADS), 0, s, V, ld, \
+                       part_in, w, N, blk, inst_blk, part_out, pair_dst, S);                     \
+    break;
+    TNT_K_CASES(TNT_CASE)
+#undef TNT_CASE
+    default: break;
+  }
+}
+
+void launch_seg_cgs_update_norm(const double* V, int64_t ld, int k, const double* part_in,
+                                double* w, int64_t N, const SegBlock* blk, const int2* inst_blk,
+                                int nblk, double* part_out, hipStream_t s) {
+  switch (k) {
+#define TNT_CASE(KK)                                                                           \
+  case KK:                                                                                     \
+    hipLaunchKernelGGL(seg_cgs_update_norm_kernel<KK>, dim3(nblk), dim3(RED_THREADS), 0, s, V, \
+                       ld, part_in, w, N, blk, inst_blk, part_out);                            \
+    break;
+    TNT_K_CASES(TNT_CASE)
+#undef TNT_CASE
+    default: break;
+  }
+}
+#undef TNT_K_CASES
+
+void launch_seg_cgs_next(const double* part_in, const double* w, double* dst, int64_t N,
+                         const SegBlock* blk, const int2* inst_blk, int nblk, double* sc, int S,
+                         int nrm2_slot, int alpha0_slot, int beta_slot, int scale_slot, double tol,
+                         int j, const int* kmax, hipStream_t s) {
+  hipLaunchKernelGGL(seg_cgs_next_kernel, dim3(nblk), dim3(RED_THREADS), 0, s, part_in, w, dst, N,
+                     blk, inst_blk, sc, S, nrm2_slot, alpha0_slot, beta_slot, scale_slot, tol, j,
+                     kmax);
 }
 
 // Gather / scatter of contiguous runs between separate buffers and a batch

@@ -134,52 +134,6 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;  // valid in thread 0
 }
 
-constexpr int MAXK = 32;  // largest basis handled by one multi-axpy
-
-// partial[b * 2k + 2i + {0,1}] = sum over block b's range of conj(V_i) w.
-// Vectors are taken 8 at a time so the accumulators stay in registers.
-__global__ __launch_bounds__(RED_THREADS) void multidot_kernel(const double* __restrict__ V,
-                                                               int64_t ld, int k,
-                                                               const double* __restrict__ w,
-                                                               int64_t n,
-                                                               double* __restrict__ partial) {
-  __shared__ double sh[4];
-  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
-  for (int i0 = 0; i0 < k; i0 += 8) {
-    double accr[8], acci[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) { accr[u] = 0; acci[u] = 0; }
-    for (int64_t x = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; x < n; x += stride) {
-      const double wr = w[x], wi = w[n + x];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (i0 + u < k) {
-          const double vr = V[(i0 + u) * ld + x], vi = V[(i0 + u) * ld + n + x];
-          accr[u] += vr * wr + vi * wi;
-          acci[u] += vr * wi - vi * wr;
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (i0 + u < k) {
-        const double r = block_sum(accr[u], sh);
-        const double m = block_sum(acci[u], sh);
-        if (threadIdx.x == 0) {
-          partial[blockIdx.x * 2 * k + 2 * (i0 + u)] = r;
-          partial[blockIdx.x * 2 * k + 2 * (i0 + u) + 1] = m;
-        }
-      }
-    }
-  }
-}
-
-void launch_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n,
-                     double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(multidot_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, w,
-                     n, partial);
-}
-
 // out[j] = sum_b partial[b * k2 + j], j < k2, summed in block order
 __global__ void reduce_partials_kernel(const double* __restrict__ partial, int k2, int nblk,
                                        double* __restrict__ out) {
@@ -195,125 +149,6 @@ __global__ void reduce_partials_kernel(const double* __restrict__ partial, int k
 void launch_reduce_partials(const double* partial, int k2, int nblk, double* out,
                             hipStream_t s) {
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(k2), dim3(256), 0, s, partial, k2, nblk, out);
-}
-
-// w -= sum_i c_i V_i ; then |w|^2 partials
-__global__ __launch_bounds__(RED_THREADS) void multiaxpy_norm_kernel(
-    const double* __restrict__ V, int64_t ld, int k, const double* __restrict__ c,
-    double* __restrict__ w, int64_t n, double* __restrict__ nrm_partial) {
-  __shared__ double sh[4];
-  __shared__ double cs[2 * MAXK];
-  if (threadIdx.x < 2 * k) cs[threadIdx.x] = c[threadIdx.x];
-  __syncthreads();
-  double acc = 0;
-  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
-  for (int64_t x = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; x < n; x += stride) {
-    double wr = w[x], wi = w[n + x];
-    for (int i = 0; i < k; ++i) {
-      const double vr = V[i * ld + x], vi = V[i * ld + n + x];
-      const double cr = cs[2 * i], ci = cs[2 * i + 1];
-      wr -= cr * vr - ci * vi;
-      wi -= cr * vi + ci * vr;
-    }
-    w[x] = wr;
-    w[n + x] = wi;
-    acc += wr * wr + wi * wi;
-  }
-  const double r = block_sum(acc, sh);
-  if (threadIdx.x == 0 && nrm_partial) nrm_partial[blockIdx.x] = r;
-}
-
-void launch_multiaxpy_norm(const double* V, int64_t ld, int k, const double* c, double* w,
-                           int64_t n, double* nrm_partial, hipStream_t s) {
-  hipLaunchKernelGGL(multiaxpy_norm_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k,
-                     c, w, n, nrm_partial);
-}
-
-// w -= a v1 + b v0 (a, b real, read from device)
-__global__ __launch_bounds__(RED_THREADS) void axpy2_kernel(const double* __restrict__ v1,
-                                                            const double* __restrict__ a_dev,
-                                                            const double* __restrict__ v0,
-                                                            const double* __restrict__ b_dev,
-                                                            double* __restrict__ w, int64_t n2) {
-  const double a = *a_dev;
-  const double b = v0 ? *b_dev : 0.0;
-  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
-  for (int64_t x = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; x < n2; x += stride) {
-    double v = w[x] - a * v1[x];
-    if (v0) v -= b * v0[x];
-    w[x] = v;
-  }
-}
-
-void launch_axpy2(const double* v1, const double* a_dev, const double* v0,
-                       const double* b_dev, double* w, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(axpy2_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, v1, a_dev, v0,
-                     b_dev, w, 2 * n);
-}
-
-__global__ void normalize_copy_kernel(const double* __restrict__ src, double* __restrict__ dst,
-                                      int64_t n2, const double* __restrict__ nrm2) {
-  const double f = 1.0 / sqrt(*nrm2);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2;
-       i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i] * f;
-}
-
-void launch_normalize_copy(const double* src, double* dst, int64_t n, const double* nrm2_dev,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(normalize_copy_kernel, dim3(grid_for(2 * n)), dim3(256), 0, s, src, dst,
-                     2 * n, nrm2_dev);
-}
-
-// dst = src * (*scale)
-__global__ void scale_copy_kernel(const double* __restrict__ src, double* __restrict__ dst,
-                                  int64_t n2, const double* __restrict__ scale) {
-  const double f = *scale;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2;
-       i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i] * f;
-}
-
-void launch_scale_copy(const double* src, double* dst, int64_t n, const double* scale_dev,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(scale_copy_kernel, dim3(grid_for(2 * n)), dim3(256), 0, s, src, dst, 2 * n,
-                     scale_dev);
-}
-
-// beta = sqrt(|w|^2); the next basis vector is w / beta unless beta falls to
-// the breakdown tolerance tol * max(1, |alpha_0|) (or is not finite): then
-// its scale is 0 and every later Krylov vector stays zero.
-__global__ void lanczos_beta_kernel(const double* __restrict__ nrm2,
-                                    const double* __restrict__ alpha0, double tol,
-                                    double* __restrict__ beta, double* __restrict__ scale) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double b = sqrt(*nrm2);
-  *beta = b;
-  const double thr = tol * fmax(1.0, fabs(*alpha0));
-  *scale = (b > thr && b < INFINITY) ? 1.0 / b : 0.0;
-}
-
-void launch_lanczos_beta(const double* nrm2_dev, const double* alpha0_dev, double tol,
-                         double* beta_dev, double* scale_dev, hipStream_t s) {
-  hipLaunchKernelGGL(lanczos_beta_kernel, dim3(1), dim3(64), 0, s, nrm2_dev, alpha0_dev, tol,
-                     beta_dev, scale_dev);
-}
-
-__global__ void combine_basis_kernel(const double* __restrict__ V, int64_t ld, int k,
-                                     const double* __restrict__ y, double* __restrict__ out,
-                                     int64_t n2) {
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n2;
-       x += (int64_t)gridDim.x * blockDim.x) {
-    double acc = 0;
-    for (int i = 0; i < k; ++i) acc += y[i] * V[i * ld + x];
-    out[x] = acc;
-  }
-}
-
-void launch_combine_basis(const double* V, int64_t ld, int k, const double* y_dev, double* out,
-                          int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(combine_basis_kernel, dim3(grid_for(2 * n)), dim3(256), 0, s, V, ld, k,
-                     y_dev, out, 2 * n);
 }
 
 __global__ __launch_bounds__(RED_THREADS) void norm2_partial_kernel(const double* __restrict__ x,
