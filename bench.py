@@ -127,6 +127,53 @@ def matvec_rates(tnt, B, torch, spec, precs=("fp64", "fp32", "bf16x3"), reps=20)
             "flops": int(flops), "parts": [int(x) for x in parts], **rates}
 
 
+def batched_sweep(tnt, B, torch, precision="fp32"):
+    """The 64-chain workload, whole sweeps: one lockstep sweep of every chain
+    through the batched path (tnt_dmrg_sweep_batched: one merged H_eff
+    operator and one Lanczos recurrence per step, the sector eigensolves of
+    all chains of a step in shared batched calls) against the same sweep run
+    chain by chain; both start from the same seeded states and follow one
+    warm-up sweep."""
+    import synth
+    specs = synth.batched_specs(4)
+    kw = dict(kmax=specs[0].lanczos_steps, precision=precision, rel_tol=specs[0].rel_cutoff)
+    chis = [s.chi for s in specs]
+
+    def build():
+        return [make_chain(tnt, B, s) for s in specs]
+
+    chains = build()
+    ms, es = [c[0] for c in chains], [c[1] for c in chains]
+    tnt.sweep_batched(ms, es, chis, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = tnt.sweep_batched(ms, es, chis, **kw)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    del chains, ms, es
+    chains = build()
+    for (m, e), s in zip(chains, specs):
+        tnt.sweep(m, e, s.chi, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = [tnt.sweep(m, e, s.chi, **kw) for (m, e), s in zip(chains, specs)]
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    del chains
+    flops = sum(r["matvec_flops"] for r in rb)
+    per = {k: sum(r[k] for r in rb) / len(rb) for k in
+           ("seconds_svd", "seconds_lanczos", "seconds_matvec", "seconds_setup")}
+    return {"workload": f"{len(specs)} chains (batched_specs seed 4), one sweep each, "
+                        "second sweep from seeded random states",
+            "precision": precision, "bond_updates": int(sum(r["updates"] for r in rb)),
+            "batched_sweep_s": t_batch, "chain_by_chain_sweeps_s": t_single,
+            "batching_speedup": t_single / t_batch,
+            "batched_matvec_tflops": flops / t_batch / 1e12,
+            "batched_breakdown_s": per,
+            "max_rel_dE_batched_vs_single": max(abs(a["energy"] - b["energy"]) / abs(b["energy"])
+                                                for a, b in zip(rb, rs))}
+
+
 def batched_rates(tnt, B, torch, precision="fp32", reps=10):
     """The 64-chain workload (L 16..64, chi 64..384, seeded) at every chain's
     middle bond: one batched H_eff application over all chains, the same 64
@@ -391,6 +438,9 @@ def main():
     ap.add_argument("--matvec-only", action="store_true",
                     help="only time single H_eff matvecs at the config's middle bond "
                          "(prints their JSON and exits; for profiling)")
+    ap.add_argument("--batched-sweep", action="store_true",
+                    help="only run one lockstep sweep of the 64 chains, batched and chain by "
+                         "chain (prints its JSON and exits; takes about two minutes)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 64-chain batched timing (prints its JSON and exits)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -434,6 +484,9 @@ def main():
 
     spec = synth.CONFIGS[args.config]
     tnt = B.load()
+    if args.batched_sweep:
+        print(json.dumps(batched_sweep(tnt, B, torch, args.precision)), flush=True)
+        return
     if args.batched_only:
         print(json.dumps(batched_rates(tnt, B, torch, args.precision)), flush=True)
         return

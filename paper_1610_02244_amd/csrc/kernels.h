@@ -268,6 +268,14 @@ struct PadTask {
   int64_t w_dst;     // offset of the sector's n eigenvalues in w
   int32_t n, npad;
 };
+// Small sectors (n <= EIG_SMALL_MAX): eigenpairs of the Hermitian matrix at
+// z + src_off (interleaved, column-major, upper triangle used), ascending
+// values into w + w_dst and their vectors over the matrix, by cyclic Jacobi
+// in LDS, one workgroup per task (max_n: the largest n of the tasks, <=
+// EIG_SMALL_MAX); info[i] = 0 when task i converged, else 1.  Only z, w,
+// src_off, w_dst and n of a task are read.
+constexpr int EIG_SMALL_MAX = 32;
+void launch_eig_small(const PadTask* t, int ntask, int max_n, int* info, hipStream_t s);
 void launch_pad_embed(const PadTask* t, int ntask, int max_n, int max_npad, double* vec,
                       double* dst_z, hipStream_t s);
 void launch_pad_extract(const PadTask* t, int ntask, int max_n, const double* slot_z,

@@ -258,8 +258,10 @@ std::shared_ptr<SvdJob> svd_begin(Ctx& c, const ThetaH& th, const double* re, co
 }
 
 void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
-  // Each decomposition is a long chain of small, latency-bound launches, so
-  // the sectors of all jobs go through a few strided-batched calls
+  // Small sectors are solved by cyclic Jacobi in LDS (see below).  For the
+  // larger ones each decomposition is a long
+  // chain of small, latency-bound launches, so the sectors of all jobs go
+  // through a few strided-batched calls
   // (buckets): every sector is padded to its bucket's size (G plus negative
   // eigenvalues below its spectrum, mixed by a fixed reflector so that no
   // exact split remains; see the padding kernels).  The buckets run
@@ -273,10 +275,18 @@ void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
     std::vector<PadTask> tasks;
     DevBuf slots, w, e, tab, info;
   };
-  std::vector<Ref> all;
-  for (SvdJob* j : jobs)
-    for (size_t i = 0; i < j->secs.size(); ++i) all.push_back(Ref{j, (int)i});
+  std::vector<Ref> all, small[2];
   auto n_of = [](const Ref& r) { return r.job->secs[r.sec].n; };
+  // Small sectors (order <= EIG_SMALL_MAX) go to the Jacobi kernel beside
+  // the library calls, in two launches (orders <= 16 and <= 32, so that the
+  // smallest take less LDS).
+  for (SvdJob* j : jobs)
+    for (size_t i = 0; i < j->secs.size(); ++i) {
+      const Ref r{j, (int)i};
+      const int n = n_of(r);
+      if (n <= EIG_SMALL_MAX) small[n <= 16 ? 0 : 1].push_back(r);
+      else all.push_back(r);
+    }
   std::stable_sort(all.begin(), all.end(),
                    [&](const Ref& a, const Ref& b) { return n_of(a) > n_of(b); });
   // A batched eigensolve costs about as much as one of its matrices (the
@@ -297,6 +307,35 @@ void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
   }
   TNT_HIP(hipEventRecord(c.side_ev[Ctx::kSide], c.stream));
   bool used[Ctx::kSide] = {};
+  // the Jacobi launches go first, on the last side stream, so that they run
+  // while the library's launch chains are being enqueued
+  struct SmallSet {
+    std::vector<PadTask> tasks;
+    DevBuf tab, info;
+    int maxn = 1;
+  } sm[2];
+  const int js = Ctx::kSide - 1;
+  for (int g = 0; g < 2; ++g) {
+    if (small[g].empty()) continue;
+    SmallSet& S = sm[g];
+    for (const Ref& r : small[g]) {
+      SvdJob& J = *r.job;
+      const Sector& sc = J.secs[r.sec];
+      S.tasks.push_back(PadTask{J.z.as<double>(), J.ev.as<double>(), sc.gbase, 0, 0, sc.ebase,
+                                sc.n, sc.n});
+      S.maxn = std::max(S.maxn, sc.n);
+    }
+    S.tab = DevBuf(&c.pool, S.tasks.size() * sizeof(PadTask));
+    S.info = DevBuf(&c.pool, S.tasks.size() * sizeof(int));
+    if (!used[js]) {
+      TNT_HIP(hipStreamWaitEvent(c.side[js], c.side_ev[Ctx::kSide], 0));
+      used[js] = true;
+    }
+    TNT_HIP(hipMemcpyAsync(S.tab.ptr, S.tasks.data(), S.tasks.size() * sizeof(PadTask),
+                           hipMemcpyHostToDevice, c.side[js]));
+    launch_eig_small(S.tab.as<PadTask>(), (int)S.tasks.size(), S.maxn, S.info.as<int>(),
+                     c.side[js]);
+  }
   int k = 0;
   for (Bucket& bk : buckets) {
     const int np = bk.npad, cnt = (int)bk.secs.size();
@@ -332,7 +371,7 @@ void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
       fail(TNT_E_HIP, "rocsolver_zheevd_strided_batched failed");
     launch_pad_extract(bk.tab.as<PadTask>(), cnt, maxn, bk.slots.as<double>(), bk.w.as<double>(),
                        ss);
-    k = (k + 1) % Ctx::kSide;
+    k = (k + 1) % (Ctx::kSide - 1);
   }
   for (int q = 0; q < Ctx::kSide; ++q) {
     if (!used[q]) continue;
@@ -346,6 +385,13 @@ void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
     TNT_HIP(hipMemcpy(raw.data(), bk.info.ptr, raw.size() * sizeof(rocblas_int),
                       hipMemcpyDeviceToHost));
     for (size_t q = 0; q < raw.size(); ++q) bk.secs[q].job->hinfo[bk.secs[q].sec] = raw[q];
+  }
+  for (int g = 0; g < 2; ++g) {
+    if (small[g].empty()) continue;
+    std::vector<int> raw(small[g].size());
+    TNT_HIP(hipMemcpy(raw.data(), sm[g].info.ptr, raw.size() * sizeof(int),
+                      hipMemcpyDeviceToHost));
+    for (size_t q = 0; q < raw.size(); ++q) small[g][q].job->hinfo[small[g][q].sec] = raw[q];
   }
 }
 

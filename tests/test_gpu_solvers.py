@@ -169,6 +169,50 @@ def test_svd_truncate_parity(tnt, absorb, rules):
             np.testing.assert_allclose(V @ V.conj().T, np.eye(k), atol=1e-13)
 
 
+SMALL_L = {0: 1, 1: 2, 2: 5, 3: 7, 4: 4}
+SMALL_R = {1: 3, 2: 6, 3: 5, 4: 8, 5: 2, 6: 1}
+
+
+@pytest.mark.parametrize("absorb", ["right", "left"])
+def test_svd_truncate_small_sectors_graded(tnt, absorb):
+    """Only small sectors (Gram orders 1..~20, odd and even: the Jacobi
+    eigensolver's range), with theta's blocks scaled by a geometric factor
+    per block so the Gram eigenvalues span ~10 orders of magnitude; every
+    value is kept.  Checked against the oracle like the general case."""
+    d = 3
+    rng = np.random.Generator(np.random.PCG64(21))
+    th = synth.random_theta(SMALL_L, SMALL_R, d, rng)
+    for i, k in enumerate(sorted(th)):
+        th[k] = th[k] * 10.0 ** (-0.12 * i)
+    ref = osvd.svd_truncate(th, SMALL_L, SMALL_R, d, 1000, absorb=absorb)
+    got = tnt.svd_truncate(tnt.theta(th), absorb=absorb, chi_max=1000)
+    assert got["chi"] == ref["chi"]
+    assert got["bond"] == ref["bond"]
+    all_ref = np.concatenate([ref["lambdas"][m] for m in ref["bond"]])
+    lam0 = all_ref.max()
+    n = max(sum(SMALL_L.values()), sum(SMALL_R.values()))
+    for m in ref["bond"]:
+        r_ = ref["lambdas"][m]
+        tol = 1e-12 * r_ + 32 * n * 2.2e-16 * lam0 ** 2 / r_
+        assert np.all(np.abs(got["lambdas"][m] - r_) <= tol), m
+    for (qa, s1, s2) in blocks.theta_keys(SMALL_L, SMALL_R, d):
+        mid = qa + s1
+        if mid not in ref["bond"]:
+            continue
+        g = got["A"][(qa, s1)] @ got["B"][(mid, s2)]
+        r = ref["A"][(qa, s1)] @ ref["B"][(mid, s2)]
+        np.testing.assert_allclose(g, r, atol=1e-10 * lam0)
+    for m, k in got["bond"].items():
+        if absorb == "right":
+            U = np.concatenate([got["A"][(m - s1, s1)] for s1 in range(d)
+                                if (m - s1, s1) in got["A"]], axis=0)
+            np.testing.assert_allclose(U.conj().T @ U, np.eye(k), atol=1e-13)
+        else:
+            V = np.concatenate([got["B"][(m, s2)] for s2 in range(d) if (m, s2) in got["B"]],
+                               axis=1)
+            np.testing.assert_allclose(V @ V.conj().T, np.eye(k), atol=1e-13)
+
+
 @pytest.mark.parametrize("absorb", ["right", "left"])
 def test_svd_truncate_large_sectors_with_zero_rows(tnt, absorb):
     """Sectors of 100-200 rows (the eigensolver's divide-and-conquer range),
