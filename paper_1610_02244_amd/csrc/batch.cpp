@@ -63,28 +63,42 @@ void RunTable::run(Ctx& c, const std::vector<CopyRun>& runs) {
 
 void build_batch(Ctx& c, BatchHeff& b, const std::vector<std::shared_ptr<HeffOp>>& ops,
                  const std::vector<int64_t>& n, int prec) {
-  if (ops.empty() || ops.size() != n.size()) fail(TNT_E_ARG, "empty or inconsistent batch");
+  std::vector<const HeffPlan*> plans;
+  std::vector<int64_t> Lx, Rx;
+  for (const auto& op : ops) {
+    if (op->precision != prec) fail(TNT_E_STATE, "batch operators disagree in precision");
+    plans.push_back(&op->plan);
+    Lx.push_back(op->L_ext);
+    Rx.push_back(op->R_ext);
+  }
+  build_batch_plans(c, b, plans, Lx, Rx, n, prec, true);
+}
+
+void build_batch_plans(Ctx& c, BatchHeff& b, const std::vector<const HeffPlan*>& plans,
+                       const std::vector<int64_t>& L_ext, const std::vector<int64_t>& R_ext,
+                       const std::vector<int64_t>& n, int prec, bool tunable) {
+  if (plans.empty() || plans.size() != n.size() || L_ext.size() != n.size() ||
+      R_ext.size() != n.size())
+    fail(TNT_E_ARG, "empty or inconsistent batch");
   b.n = n;
   b.precision = prec;
   b.parts.clear();
   b.L_ext.clear();
   b.R_ext.clear();
   b.N = b.L_tot = b.R_tot = 0;
-  std::vector<const HeffPlan*> plans;
   std::vector<int64_t> off;
-  for (size_t i = 0; i < ops.size(); ++i) {
-    if (ops[i]->precision != prec) fail(TNT_E_STATE, "batch operators disagree in precision");
-    plans.push_back(&ops[i]->plan);
+  for (size_t i = 0; i < plans.size(); ++i) {
+    if (plans[i]->packed != (prec != TNT_FP64)) fail(TNT_E_STATE, "plan built for another precision");
     b.parts.push_back(BatchPart{b.N, b.L_tot, b.R_tot});
     off.push_back(b.N);
-    b.L_ext.push_back(ops[i]->L_ext);
-    b.R_ext.push_back(ops[i]->R_ext);
+    b.L_ext.push_back(L_ext[i]);
+    b.R_ext.push_back(R_ext[i]);
     b.N += n[i];
-    b.L_tot += ops[i]->L_ext;
-    b.R_tot += ops[i]->R_ext;
+    b.L_tot += L_ext[i];
+    b.R_tot += R_ext[i];
   }
   b.op = std::make_shared<HeffOp>();
-  b.op->build_plan(c, merge_heff_plans(plans, b.parts), prec);
+  b.op->build_plan(c, merge_heff_plans(plans, b.parts), prec, tunable);
   b.op->L_ext = b.L_tot;
   b.op->R_ext = b.R_tot;
   b.seg.build(c, off, n);

@@ -42,6 +42,12 @@ struct BatchHeff {
 // complex offset sum_{j<i} n[j].
 void build_batch(Ctx& c, BatchHeff& b, const std::vector<std::shared_ptr<HeffOp>>& ops,
                  const std::vector<int64_t>& n, int prec);
+// The same from the instances' host plans (no per-instance device tables);
+// L_ext / R_ext: each instance's environment extents; tunable: as for
+// HeffOp::build_plan (off for an operator used once).
+void build_batch_plans(Ctx& c, BatchHeff& b, const std::vector<const HeffPlan*>& plans,
+                       const std::vector<int64_t>& L_ext, const std::vector<int64_t>& R_ext,
+                       const std::vector<int64_t>& n, int prec, bool tunable);
 // Gather every instance's FP64 environments into the batch planes and bind
 // them (refreshes the packed copies).
 void bind_batch_envs(Ctx& c, BatchHeff& b, const std::vector<const double*>& Lre,

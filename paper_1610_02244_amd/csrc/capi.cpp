@@ -1,7 +1,9 @@
 // C-ABI: context and the two-site H_eff application.
 #include <cstring>
+#include <exception>
 #include <memory>
 #include <new>
+#include <thread>
 #include <unordered_map>
 
 #include "capi_util.h"
@@ -24,6 +26,14 @@ struct PlanCache {
   // the same operators by the hash of the raw host descriptors they were
   // parsed and validated from (skips the parse for a repeated call)
   std::unordered_map<uint64_t, std::shared_ptr<HeffOp>> raw;
+  // host plans alone (the lockstep sweep merges them into batch operators)
+  // by the operators' key, and those batch operators by plan identities
+  std::unordered_map<uint64_t, std::shared_ptr<HeffPlan>> plan;
+  struct PlanBatch {
+    std::vector<std::shared_ptr<HeffPlan>> plans;
+    std::shared_ptr<BatchHeff> b;
+  };
+  std::unordered_map<uint64_t, PlanBatch> plan_batch;
 };
 
 // Word-wise hash of the raw host metadata of an H_eff call: every field the
@@ -203,7 +213,38 @@ void copy_runs(Ctx& c, const std::vector<CopyRun>& runs) {
   TNT_HIP(hipStreamSynchronize(c.stream));
 }
 
-std::shared_ptr<HeffOp> cached_heff(Ctx& c, const HeffArgs& a, int prec) {
+// Host plans of args[miss[q]]: independent host work, built on up to
+// kPlanThreads threads (the planner has no shared state).
+static std::vector<HeffPlan> build_plans(const std::vector<const HeffArgs*>& args,
+                                         const std::vector<size_t>& miss, int prec) {
+  const bool packed = prec != TNT_FP64;
+  std::vector<HeffPlan> plans(miss.size());
+  auto plan_one = [&](size_t q) {
+    const HeffArgs& a = *args[miss[q]];
+    plans[q] = build_heff_plan(a.L, a.w1, a.w2, a.R, a.th, a.out, packed);
+  };
+  const size_t nth = std::min<size_t>(miss.size(), kPlanThreads);
+  if (nth <= 1) {
+    for (size_t q = 0; q < miss.size(); ++q) plan_one(q);
+    return plans;
+  }
+  std::vector<std::exception_ptr> err(nth);
+  std::vector<std::thread> th;
+  for (size_t w = 0; w < nth; ++w)
+    th.emplace_back([&, w]() {
+      try {
+        for (size_t q = w; q < miss.size(); q += nth) plan_one(q);
+      } catch (...) {
+        err[w] = std::current_exception();
+      }
+    });
+  for (auto& t : th) t.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+  return plans;
+}
+
+static uint64_t heff_key(const HeffArgs& a, int prec) {
   Hasher H;
   H.add(prec);
   hash_mpo(H, a.w1);
@@ -212,18 +253,113 @@ std::shared_ptr<HeffOp> cached_heff(Ctx& c, const HeffArgs& a, int prec) {
   hash_env(H, a.R);
   hash_theta(H, a.th);
   hash_theta(H, a.out);
+  return H.h;
+}
+
+std::shared_ptr<HeffOp> cached_heff(Ctx& c, const HeffArgs& a, int prec) {
+  return cached_heffs(c, {&a}, prec)[0];
+}
+
+std::vector<std::shared_ptr<HeffOp>> cached_heffs(Ctx& c, const std::vector<const HeffArgs*>& args,
+                                                  int prec) {
   if (!c.plans) c.plans = new PlanCache();
-  auto it = c.plans->heff.find(H.h);
-  if (it != c.plans->heff.end()) return it->second;
-  if (c.plans->heff.size() >= 1024) {
+  const size_t n = args.size();
+  std::vector<uint64_t> key(n);
+  std::vector<std::shared_ptr<HeffOp>> out(n);
+  std::vector<size_t> miss;
+  for (size_t i = 0; i < n; ++i) {
+    key[i] = heff_key(*args[i], prec);
+    auto it = c.plans->heff.find(key[i]);
+    if (it != c.plans->heff.end()) out[i] = it->second;
+    else miss.push_back(i);
+  }
+  if (miss.empty()) return out;
+  if (c.plans->heff.size() + miss.size() > 1024) {
     TNT_HIP(hipStreamSynchronize(c.stream));
     c.plans->heff.clear();
     c.plans->raw.clear();
   }
-  auto op = std::make_shared<HeffOp>();
-  op->build(c, a.L, a.w1, a.w2, a.R, a.th, a.out, prec);
-  c.plans->heff[H.h] = op;
-  return op;
+  std::vector<HeffPlan> plans = build_plans(args, miss, prec);
+  for (size_t q = 0; q < miss.size(); ++q) {
+    const size_t i = miss[q];
+    auto it = c.plans->heff.find(key[i]);  // an earlier miss of this call with the same key
+    if (it != c.plans->heff.end()) {
+      out[i] = it->second;
+      continue;
+    }
+    auto op = std::make_shared<HeffOp>();
+    op->build_plan(c, std::move(plans[q]), prec);
+    op->L_ext = args[i]->L.extent;
+    op->R_ext = args[i]->R.extent;
+    c.plans->heff[key[i]] = op;
+    out[i] = op;
+  }
+  return out;
+}
+
+std::vector<std::shared_ptr<HeffPlan>> cached_plans(Ctx& c,
+                                                   const std::vector<const HeffArgs*>& args,
+                                                   int prec) {
+  if (!c.plans) c.plans = new PlanCache();
+  const size_t n = args.size();
+  std::vector<uint64_t> key(n);
+  std::vector<std::shared_ptr<HeffPlan>> out(n);
+  std::vector<size_t> miss;
+  for (size_t i = 0; i < n; ++i) {
+    key[i] = heff_key(*args[i], prec);
+    auto it = c.plans->plan.find(key[i]);
+    if (it != c.plans->plan.end()) out[i] = it->second;
+    else miss.push_back(i);
+  }
+  if (miss.empty()) return out;
+  if (c.plans->plan.size() + miss.size() > 4096) {
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    c.plans->plan.clear();
+    c.plans->plan_batch.clear();
+  }
+  std::vector<HeffPlan> plans = build_plans(args, miss, prec);
+  for (size_t q = 0; q < miss.size(); ++q) {
+    const size_t i = miss[q];
+    auto it = c.plans->plan.find(key[i]);
+    if (it != c.plans->plan.end()) {
+      out[i] = it->second;
+      continue;
+    }
+    auto p = std::make_shared<HeffPlan>(std::move(plans[q]));
+    c.plans->plan[key[i]] = p;
+    out[i] = p;
+  }
+  return out;
+}
+
+std::shared_ptr<BatchHeff> cached_plan_batch(Ctx& c,
+                                             const std::vector<std::shared_ptr<HeffPlan>>& plans,
+                                             const std::vector<int64_t>& L_ext,
+                                             const std::vector<int64_t>& R_ext,
+                                             const std::vector<int64_t>& n, int prec) {
+  Hasher H;
+  H.add(prec);
+  for (size_t i = 0; i < plans.size(); ++i) {
+    H.add(plans[i].get());
+    H.add(n[i]);
+    H.add(L_ext[i]);
+    H.add(R_ext[i]);
+  }
+  if (!c.plans) c.plans = new PlanCache();
+  auto it = c.plans->plan_batch.find(H.h);
+  if (it != c.plans->plan_batch.end() && it->second.plans == plans) return it->second.b;
+  if (c.plans->plan_batch.size() >= 256) {
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    c.plans->plan_batch.clear();
+  }
+  auto b = std::make_shared<BatchHeff>();
+  std::vector<const HeffPlan*> pp;
+  for (const auto& p : plans) pp.push_back(p.get());
+  // a lockstep sweep builds a new batch operator at nearly every step: the
+  // tile shapes come from cached decisions or the defaults, not timing
+  build_batch_plans(c, *b, pp, L_ext, R_ext, n, prec, false);
+  c.plans->plan_batch[H.h] = PlanCache::PlanBatch{plans, b};
+  return b;
 }
 
 }  // namespace tnt

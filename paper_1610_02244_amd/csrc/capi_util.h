@@ -48,6 +48,22 @@ void check_precision(int32_t p);
 HeffArgs parse_heff_args(const tnt_btensor* L, const tnt_mpo_site* W1, const tnt_mpo_site* W2,
                          const tnt_btensor* R, const tnt_btensor* theta, const tnt_btensor* out);
 std::shared_ptr<HeffOp> cached_heff(Ctx& c, const HeffArgs& a, int prec);
+// Operators for several argument sets: cache hits as they are, the host
+// plans of the misses built on up to kPlanThreads threads, then their
+// device tables one after another.
+constexpr size_t kPlanThreads = 8;
+std::vector<std::shared_ptr<HeffOp>> cached_heffs(Ctx& c, const std::vector<const HeffArgs*>& args,
+                                                  int prec);
+// Host plans only (same key and threads as cached_heffs, no device tables),
+// and batch operators merged from such plans (cached by plan identities).
+std::vector<std::shared_ptr<HeffPlan>> cached_plans(Ctx& c,
+                                                   const std::vector<const HeffArgs*>& args,
+                                                   int prec);
+std::shared_ptr<BatchHeff> cached_plan_batch(Ctx& c,
+                                             const std::vector<std::shared_ptr<HeffPlan>>& plans,
+                                             const std::vector<int64_t>& L_ext,
+                                             const std::vector<int64_t>& R_ext,
+                                             const std::vector<int64_t>& n, int prec);
 
 // A batched C-ABI call remembered by the hash of all its raw descriptors:
 // the parsed instance layouts, operators, batch operator, and the call's own

@@ -530,7 +530,7 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
       act.push_back(Act{i, pass == 0 ? 1 + step : ms[i]->L - 1 - step, pass});
     }
     std::vector<ThetaH> ths;
-    std::vector<std::shared_ptr<HeffOp>> ops;
+    std::vector<HeffArgs> hargs;
     std::vector<int64_t> nn;
     std::vector<const double *> Lr, Li, Rr, Ri;
     for (const Act& a : act) {
@@ -547,7 +547,7 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
       h.out = th;
       h.L = e.Llay[a.j - 1];
       h.R = e.Rlay[a.j + 2];
-      ops.push_back(cached_heff(c, h, lp.precision));
+      hargs.push_back(std::move(h));
       t_setup += now_s() - tt1;
       nn.push_back(th.elems);
       ths.push_back(std::move(th));
@@ -556,8 +556,20 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
       Rr.push_back(e.Rre(a.j + 2));
       Ri.push_back(e.Rim(a.j + 2));
     }
+    const double tp0 = now_s();
+    // the chains' host plans (built on several host threads), merged into
+    // one batch operator: only the merged operator gets device tables
+    std::vector<const HeffArgs*> hp;
+    std::vector<int64_t> Lx, Rx;
+    for (const HeffArgs& h : hargs) {
+      hp.push_back(&h);
+      Lx.push_back(h.L.extent);
+      Rx.push_back(h.R.extent);
+    }
+    std::vector<std::shared_ptr<HeffPlan>> plans = cached_plans(c, hp, lp.precision);
+    t_setup += now_s() - tp0;
     const double tb0 = now_s();
-    auto B = cached_batch(c, ops, nn, lp.precision);
+    auto B = cached_plan_batch(c, plans, Lx, Rx, nn, lp.precision);
     bind_batch_envs(c, *B, Lr, Li, Rr, Ri);
     xall.ensure(&c.pool, std::max<int64_t>(1, 2 * B->N) * sizeof(double));
     double* x = xall.as<double>();
@@ -601,10 +613,10 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
       EnvS& e = *es[i];
       const tnt_sweep_params& p = ps[i];
       SweepStats& s = st[i];
-      const HeffOp& op = *ops[a];
+      const HeffPlan& pl = *plans[a];
       s.matvecs += lo[a].matvecs;
-      s.matvec_flops += (double)op.plan.flops() * (double)lo[a].matvecs;
-      s.gemm_flops += (double)(op.plan.flops_step1 + op.plan.flops_step4) * (double)lo[a].matvecs;
+      s.matvec_flops += (double)pl.flops() * (double)lo[a].matvecs;
+      s.gemm_flops += (double)(pl.flops_step1 + pl.flops_step4) * (double)lo[a].matvecs;
       DevBuf na, nb;
       const double ts0 = now_s();
       SvdOut r = svd_finish(c, *jobs[a], p.trunc, [&](const SvdOut& o) {

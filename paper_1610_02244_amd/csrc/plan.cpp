@@ -5,8 +5,11 @@
 
 #include <algorithm>
 #include <cstring>
+#include <exception>
+#include <functional>
 #include <numeric>
 #include <set>
+#include <thread>
 
 namespace tnt {
 
@@ -522,30 +525,79 @@ HeffPlan merge_heff_plans(const std::vector<const HeffPlan*>& plans,
   HeffPlan M;
   if (plans.empty()) return M;
   M.packed = plans[0]->packed;
-  for (size_t i = 0; i < plans.size(); ++i) {
+  // instance i's offsets inside the merged workspaces (prefix sums)
+  const size_t n = plans.size();
+  std::vector<int64_t> t1(n), t3(n), t3p(n), lp(n), xp(n), rp(n);
+  for (size_t i = 0; i < n; ++i) {
     const HeffPlan& P = *plans[i];
-    const BatchPart& w = where[i];
     if (P.packed != M.packed) fail(TNT_E_STATE, "batch plans disagree in precision");
-    append_gemm(M.step1, P.step1, M.t1_elems, w.L_off, w.x_off);
-    append_gemm(M.step4, P.step4, w.x_off, M.t3_elems, w.R_off);
-    append_comb(M.mpo, P.mpo, M.t3_elems, M.t1_elems);
-    if (M.packed) {
-      append_gemm(M.step1p, P.step1p, M.t1_elems, M.Lp.elems, M.Xp.elems);
-      append_gemm(M.step4p, P.step4p, w.x_off, M.t3p_elems, M.Rp.elems);
-      append_combp(M.mpop, P.mpop, M.t3p_elems, M.t1_elems);
-      append_pack(M.Lp, P.Lp, w.L_off);
-      append_pack(M.Rp, P.Rp, w.R_off);
-      append_pack(M.Xp, P.Xp, w.x_off);
-      M.t3p_elems += P.t3p_elems;
-    }
+    t1[i] = M.t1_elems;
+    t3[i] = M.t3_elems;
+    t3p[i] = M.t3p_elems;
+    lp[i] = M.Lp.elems;
+    xp[i] = M.Xp.elems;
+    rp[i] = M.Rp.elems;
     M.t1_elems += P.t1_elems;
     M.t3_elems += P.t3_elems;
+    if (M.packed) {
+      M.t3p_elems += P.t3p_elems;
+      M.Lp.elems += P.Lp.elems;
+      M.Xp.elems += P.Xp.elems;
+      M.Rp.elems += P.Rp.elems;
+    }
     M.flops_step1 += P.flops_step1;
     M.flops_mpo += P.flops_mpo;
     M.flops_step4 += P.flops_step4;
   }
-  M.mpo.finalize();
-  if (M.packed) M.mpop.finalize();
+  M.Lp.elems = M.Xp.elems = M.Rp.elems = 0;  // the appends below recount them
+  // each merged table is appended on its own host thread
+  std::vector<std::function<void()>> parts;
+  parts.push_back([&] {
+    for (size_t i = 0; i < n; ++i)
+      append_gemm(M.step1, plans[i]->step1, t1[i], where[i].L_off, where[i].x_off);
+  });
+  parts.push_back([&] {
+    for (size_t i = 0; i < n; ++i)
+      append_gemm(M.step4, plans[i]->step4, where[i].x_off, t3[i], where[i].R_off);
+  });
+  parts.push_back([&] {
+    for (size_t i = 0; i < n; ++i) append_comb(M.mpo, plans[i]->mpo, t3[i], t1[i]);
+    M.mpo.finalize();
+  });
+  if (M.packed) {
+    parts.push_back([&] {
+      for (size_t i = 0; i < n; ++i)
+        append_gemm(M.step1p, plans[i]->step1p, t1[i], lp[i], xp[i]);
+    });
+    parts.push_back([&] {
+      for (size_t i = 0; i < n; ++i)
+        append_gemm(M.step4p, plans[i]->step4p, where[i].x_off, t3p[i], rp[i]);
+    });
+    parts.push_back([&] {
+      for (size_t i = 0; i < n; ++i) append_combp(M.mpop, plans[i]->mpop, t3p[i], t1[i]);
+      M.mpop.finalize();
+    });
+    parts.push_back([&] {
+      for (size_t i = 0; i < n; ++i) {
+        append_pack(M.Lp, plans[i]->Lp, where[i].L_off);
+        append_pack(M.Rp, plans[i]->Rp, where[i].R_off);
+        append_pack(M.Xp, plans[i]->Xp, where[i].x_off);
+      }
+    });
+  }
+  std::vector<std::exception_ptr> err(parts.size());
+  std::vector<std::thread> th;
+  for (size_t k = 0; k < parts.size(); ++k)
+    th.emplace_back([&, k]() {
+      try {
+        parts[k]();
+      } catch (...) {
+        err[k] = std::current_exception();
+      }
+    });
+  for (auto& t : th) t.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
   return M;
 }
 
@@ -556,7 +608,7 @@ void HeffOp::build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const 
   R_ext = R.extent;
 }
 
-void HeffOp::build_plan(Ctx& c, HeffPlan&& p, int prec) {
+void HeffOp::build_plan(Ctx& c, HeffPlan&& p, int prec, bool tunable) {
   ctx = &c;
   precision = prec;
   const bool packed = prec != TNT_FP64;
@@ -565,27 +617,57 @@ void HeffOp::build_plan(Ctx& c, HeffPlan&& p, int prec) {
   // tile shape: a cached tuning decision for this shape bucket, else the
   // default, plus every candidate for the first application to time when
   // `tunable` (the operator's own precision)
-  bool tune = false;
-  auto setup = [&](HostGemm& h, int which, GemmPath path, bool tunable) {
-    auto it = c.tune_cache.find(tune_bucket(h, path, which));
-    h.finalize(it != c.tune_cache.end() ? it->second : default_tile_cfg(h, path));
-    if (tunable && it == c.tune_cache.end() && c.autotune) {
-      for (int cfg : tile_candidates(path)) h.add_variant(cfg);
-      tune = true;
-    }
+  struct Job {
+    HostGemm* h;
+    int which;
+    GemmPath path;
+    bool tunable, tune;
   };
   // FP64 tables: the FP64 operator, or the FP64 refinement of a
   // reduced-precision one
-  setup(plan.step1, 1, PATH_F64, !packed);
-  setup(plan.step4, 4, PATH_F64, !packed);
+  std::vector<Job> jobs = {{&plan.step1, 1, PATH_F64, tunable && !packed, false},
+                           {&plan.step4, 4, PATH_F64, tunable && !packed, false}};
   if (packed) {
-    setup(plan.step1p, 1, gemm_path(prec), true);
-    setup(plan.step4p, 4, gemm_path(prec), true);
+    jobs.push_back({&plan.step1p, 1, gemm_path(prec), tunable, false});
+    jobs.push_back({&plan.step4p, 4, gemm_path(prec), tunable, false});
+  }
+  // the tuning cache is only read here
+  auto setup = [&](Job& j) {
+    auto it = c.tune_cache.find(tune_bucket(*j.h, j.path, j.which));
+    j.h->finalize(it != c.tune_cache.end() ? it->second : default_tile_cfg(*j.h, j.path));
+    if (j.tunable && it == c.tune_cache.end() && c.autotune) {
+      for (int cfg : tile_candidates(j.path)) j.h->add_variant(cfg);
+      j.tune = true;
+    }
+  };
+  // tile tables of large plans (merged batch operators) on one host thread
+  // per table: independent sorts over tens of thousands of tasks
+  size_t ntask = 0;
+  for (const Job& j : jobs) ntask += j.h->tasks.size();
+  if (ntask >= 4096) {
+    std::vector<std::exception_ptr> err(jobs.size());
+    std::vector<std::thread> th;
+    for (size_t k = 0; k < jobs.size(); ++k)
+      th.emplace_back([&, k]() {
+        try {
+          setup(jobs[k]);
+        } catch (...) {
+          err[k] = std::current_exception();
+        }
+      });
+    for (auto& t : th) t.join();
+    for (auto& e : err)
+      if (e) std::rethrow_exception(e);
+  } else {
+    for (Job& j : jobs) setup(j);
+  }
+  bool tune = false;
+  for (const Job& j : jobs) tune = tune || j.tune;
+  if (packed)
     tab.upload(c, {&plan.step1, &plan.step4, &plan.step1p, &plan.step4p}, {&plan.mpo},
                {&plan.mpop}, {&plan.Lp, &plan.Rp, &plan.Xp});
-  } else {
+  else
     tab.upload(c, {&plan.step1, &plan.step4}, {&plan.mpo});
-  }
   tuned = !tune;
 }
 

@@ -183,7 +183,9 @@ struct HeffOp {
   void build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const EnvH& R,
              const ThetaH& th, const ThetaH& out, int prec);
   // the same for a ready plan (a merged batch plan)
-  void build_plan(Ctx& c, HeffPlan&& p, int prec);
+  // tunable: time the tile-shape candidates at the first application when
+  // the shape bucket has no cached decision (off for one-off operators)
+  void build_plan(Ctx& c, HeffPlan&& p, int prec, bool tunable = true);
   // point at the environments' FP64 planes (and refresh the packed copies)
   void bind_envs(const void* lre, const void* lim, const void* rre, const void* rim);
   PackFmt fmt() const { return precision == TNT_BF16X3 ? PK_BF16X3 : PK_F32; }

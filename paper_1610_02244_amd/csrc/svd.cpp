@@ -275,6 +275,8 @@ void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
     std::vector<PadTask> tasks;
     DevBuf slots, w, e, tab, info;
   };
+  // at most one bucket per side stream (the last stream runs the Jacobi launches)
+  constexpr int kMaxBuckets = Ctx::kSide - 1;
   std::vector<Ref> all, small[2];
   auto n_of = [](const Ref& r) { return r.job->secs[r.sec].n; };
   // Small sectors (order <= EIG_SMALL_MAX) go to the Jacobi kernel beside
@@ -289,21 +291,56 @@ void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
     }
   std::stable_sort(all.begin(), all.end(),
                    [&](const Ref& a, const Ref& b) { return n_of(a) > n_of(b); });
-  // A batched eigensolve costs about as much as one of its matrices (the
-  // launch chain is ~n steps long whatever the batch), and the GPU serves
-  // only a few streams concurrently, so the sectors form at most
-  // kMaxBuckets buckets: in descending size, a bucket takes every sector of
-  // at least a quarter of its largest one (the last takes the rest), all
-  // padded to the size class of that largest sector.
-  constexpr int kMaxBuckets = 3;
-  std::vector<Bucket> buckets;
-  for (size_t i = 0; i < all.size();) {
-    Bucket bk;
-    const int top = n_of(all[i]);
-    bk.npad = padded_size(top);
-    const bool last = (int)buckets.size() == kMaxBuckets - 1;
-    while (i < all.size() && (last || 4 * n_of(all[i]) >= top)) bk.secs.push_back(all[i++]);
-    buckets.push_back(std::move(bk));
+  // The large sectors form buckets, each one batched library call padded to
+  // the size class of its largest sector.  The calls' launch chains are
+  // enqueued one after another, so their times add up; a bucket of `cnt`
+  // matrices of padded order np is modelled as
+  //   latency 0.028 np ms  +  cnt x (0.020 (np / 128)^2.2 ms  for np > 64,
+  //                                  0.1 (np / 32)^2 ms      for np <= 64),
+  // fitted to timings of the library's batched Hermitian eigensolver on one
+  // MI355X (np = 32 .. 256, batches 1 .. 512; at np <= 64 its time grows
+  // linearly with the batch).  Few sectors (one chain) give one or two
+  // buckets; many sectors (many chains in a step) give more, so that small
+  // ones are not padded to the largest.  The bucketing that minimises the
+  // modelled time over contiguous runs of size classes (at most
+  // kMaxBuckets buckets) is found by dynamic programming.
+  auto cost = [](int np, int cnt) {
+    const double x = np;
+    const double per = np > 64 ? 0.020 * std::pow(x / 128.0, 2.2) : 0.1 * (x / 32.0) * (x / 32.0);
+    return 0.028 * x + cnt * per;
+  };
+  std::vector<std::pair<int, int>> cls;  // (padded order, first index into all), descending
+  for (size_t i = 0; i < all.size(); ++i) {
+    const int np = padded_size(n_of(all[i]));
+    if (cls.empty() || cls.back().first != np) cls.push_back({np, (int)i});
+  }
+  const int nc = (int)cls.size();
+  auto first = [&](int k) { return k < nc ? cls[k].second : (int)all.size(); };
+  // best[b][k]: least modelled time of classes [0, k) in b buckets
+  const double inf = 1e300;
+  std::vector<std::vector<double>> best(kMaxBuckets + 1, std::vector<double>(nc + 1, inf));
+  std::vector<std::vector<int>> from(kMaxBuckets + 1, std::vector<int>(nc + 1, -1));
+  best[0][0] = 0;
+  for (int b = 1; b <= kMaxBuckets; ++b)
+    for (int k = 1; k <= nc; ++k)
+      for (int a = 0; a < k; ++a) {
+        if (best[b - 1][a] >= inf) continue;
+        const double v = best[b - 1][a] + cost(cls[a].first, first(k) - first(a));
+        if (v < best[b][k]) {
+          best[b][k] = v;
+          from[b][k] = a;
+        }
+      }
+  int nb = 0;
+  for (int b = 1; b <= kMaxBuckets; ++b)
+    if (nc > 0 && (nb == 0 || best[b][nc] < best[nb][nc])) nb = b;
+  std::vector<Bucket> buckets(nb);
+  for (int b = nb, k = nc; b > 0; --b) {
+    const int a = from[b][k];
+    Bucket& bk = buckets[b - 1];
+    bk.npad = cls[a].first;
+    for (int i = first(a); i < first(k); ++i) bk.secs.push_back(all[i]);
+    k = a;
   }
   TNT_HIP(hipEventRecord(c.side_ev[Ctx::kSide], c.stream));
   bool used[Ctx::kSide] = {};
