@@ -83,9 +83,11 @@ tnt_status tnt_sync(tnt_ctx ctx);
 int64_t tnt_pool_bytes(tnt_ctx ctx);
 /* Tile-shape autotuning of the H_eff grouped GEMMs (on by default): the
  * first application of a new block structure times every candidate tile
- * shape and caches the choice per shape bucket.  Results do not depend on
- * the shape (the summation order over K is the same).  on = 0 disables
- * tuning (the planner's default shape is used) and clears the cache. */
+ * shape of each GEMM step of at least 1e9 flops and caches the choice per
+ * shape bucket (smaller steps are launch-latency bound and take the
+ * planner's default shape).  Results do not depend on the shape (the
+ * summation order over K is the same).  on = 0 disables tuning (the
+ * planner's default shape is used) and clears the cache. */
 tnt_status tnt_ctx_set_autotune(tnt_ctx ctx, int32_t on);
 
 /* HIP-graph execution of the Lanczos recurrence (off by default).  With

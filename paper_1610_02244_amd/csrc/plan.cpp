@@ -132,20 +132,32 @@ int64_t HostPack::add(int64_t src_off, int rows, int cols, int sld, bool trans) 
   return off;
 }
 
+// GEMM steps below this many flops are not tuned: such a launch takes a few
+// tens of microseconds, mostly dispatch and tail, and timing the candidates
+// (with a host wait per timed launch) costs more than a better shape saves.
+constexpr double kTuneMinFlops = 1e9;
+
+// Tile shape without timing.  The rule reproduces the autotuner's choices
+// over every GEMM step of a chi = 256 and a chi = 1024 sweep (about 210
+// steps per path, 1e3 .. 2e10 flops): on the FP32 and FP64 paths 32 x 32
+// tiles win unless the step is large in both tile count and block size
+// (more tiles fill the 256 CUs; only big L.theta steps gain from 64 x 64);
+// on the BF16x3 path 64 x 64 wins from a typical block size of about 48.
 int default_tile_cfg(const HostGemm& h, GemmPath path) {
-  // flop-weighted typical output dimension
+  // flop-weighted typical output dimension, and the 64 x 64 tile count
   double wsum = 0, dsum = 0;
+  int64_t tiles64 = 0;
   for (const GemmTask& t : h.tasks) {
     double k = 0;
     for (int s = 0; s < t.nseg; ++s) k += h.segs[t.seg0 + s].K;
     const double f = (double)t.M * t.N * k;
     wsum += f;
     dsum += f * std::min(t.M, t.N);
+    tiles64 += (int64_t)((t.M + 63) / 64) * ((t.N + 63) / 64);
   }
   const double typ = wsum > 0 ? dsum / wsum : 0;
-  if (typ < 48) return 1;                       // 32 x 32
-  if (path == PATH_F32 && typ >= 200) return 4;  // 128 x 128
-  return 0;                                      // 64 x 64
+  if (path == PATH_BF16X3) return typ < 48 ? 1 : 0;  // 32 x 32, else 64 x 64
+  return tiles64 >= 1024 && typ >= 100 ? 0 : 1;       // 64 x 64, else 32 x 32
 }
 
 // ---------------------------------------------------------------------------
@@ -635,7 +647,7 @@ void HeffOp::build_plan(Ctx& c, HeffPlan&& p, int prec, bool tunable) {
   auto setup = [&](Job& j) {
     auto it = c.tune_cache.find(tune_bucket(*j.h, j.path, j.which));
     j.h->finalize(it != c.tune_cache.end() ? it->second : default_tile_cfg(*j.h, j.path));
-    if (j.tunable && it == c.tune_cache.end() && c.autotune) {
+    if (j.tunable && it == c.tune_cache.end() && c.autotune && j.h->flops >= kTuneMinFlops) {
       for (int cfg : tile_candidates(j.path)) j.h->add_variant(cfg);
       j.tune = true;
     }
