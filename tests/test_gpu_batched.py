@@ -179,6 +179,35 @@ def test_sweep_batched_matches_single(tnt, precision):
     assert abs(e - er) <= 1e-9 * abs(er)
 
 
+def test_sweep_batched_many_sectors(tnt):
+    """Five chains (L 8..10, d 3..4) kept at full rank (no truncation rule
+    active, chi above every bond's rank): each lockstep step then has sectors
+    of Gram order 1..101, so the step's eigensolves use the small-sector
+    Jacobi launch and several library buckets at once.  Two FP64 sweeps
+    batched against the same sweeps chain by chain: equal bond dimensions,
+    energies to 1e-10."""
+    chains = [(10, 10, 3, 2.0, 2048, 21), (10, 10, 3, 4.0, 2048, 22), (9, 9, 3, 3.0, 2048, 23),
+              (8, 8, 3, 2.5, 2048, 24), (10, 10, 2, 3.0, 2048, 25)]
+    kw = dict(kmax=20, precision="fp64", rel_tol=-1.0)
+    single, batch_m, batch_e = [], [], []
+    for (L, N, nmax, U, chi, seed) in chains:
+        m, e = make_chain(tnt, L, N, nmax, U, chi, seed)
+        single.append([tnt.sweep(m, e, chi, **kw) for _ in range(2)])
+        m2, e2 = make_chain(tnt, L, N, nmax, U, chi, seed)
+        batch_m.append(m2)
+        batch_e.append(e2)
+    chis = [c[4] for c in chains]
+    batched = [tnt.sweep_batched(batch_m, batch_e, chis, **kw) for _ in range(2)]
+    for ci in range(len(chains)):
+        for sw in range(2):
+            a = np.array(batched[sw][ci]["bond_E"])
+            b = np.array(single[ci][sw]["bond_E"])
+            rel = np.max(np.abs(a - b) / np.abs(b))
+            print(f"  [many sectors] chain {ci} sweep {sw + 1}: max|dE/E| {rel:.2e}", flush=True)
+            assert rel <= 1e-10
+            assert list(batched[sw][ci]["bond_chi"]) == list(single[ci][sw]["bond_chi"])
+
+
 def test_many_chain_matvec_sampled_vs_oracle(tnt):
     """The 64-chain workload at every chain's middle bond in one batched
     application; four chains (one per chi) checked against the oracle."""
