@@ -174,6 +174,44 @@ def batched_sweep(tnt, B, torch, precision="fp32"):
                                                 for a, b in zip(rb, rs))}
 
 
+def spin1_sweeps(tnt, B, torch, precisions=("fp32", "fp64"), steps=2):
+    """The DMRG timing workload of the paper's Sec. 3 table: spin-1
+    Heisenberg chain, L = 101, chi = 200, U(1) blocks (S^z = 0 is total
+    charge L with s = S^z + 1), from a seeded random MPS; one warm-up sweep,
+    then `steps` timed sweeps per matvec precision."""
+    import synth
+    L, chi, kmax = 101, 200, 20
+    W, qw = tnt.spin1_heisenberg_mpo(1.0)
+    out = {"workload": f"spin-1 Heisenberg open chain L={L}, S^z=0, chi={chi}, "
+                       f"Lanczos kmax={kmax}, seeded random MPS (seed 5)",
+           "paper_s_per_sweep": {"cpu_mkl_nag": 135.0, "gpu_magma_k40": 161.0,
+                                 "cpu_arpack": 377.0}}
+    kw = dict(kmax=kmax, rel_tol=1e-12)
+    for prec in precisions:
+        bonds, sites = synth.random_mps(L, L, 2, chi, 5)
+        mps = tnt.mps(bonds, sites, 3)
+        mps.right_canonicalize()
+        env = B.Env(tnt, mps, [W] * L, qw, B.SPIN1_LEFT, B.SPIN1_RIGHT)
+        r0 = tnt.sweep(mps, env, chi, precision=prec, **kw)
+        log(f"  spin-1 warm-up sweep [{prec}]: E = {r0['energy']:.12f}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = [tnt.sweep(mps, env, chi, precision=prec, **kw) for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        r = rs[-1]
+        out[prec] = {"s_per_sweep": dt, "energy": r["energy"],
+                     "energy_per_bond": r["energy"] / (L - 1),
+                     "max_chi": int(max(r["bond_chi"])), "max_eps": float(max(r["bond_eps"])),
+                     "breakdown_s": {k: r[k] for k in ("seconds_svd", "seconds_lanczos",
+                                                       "seconds_matvec", "seconds_setup",
+                                                       "seconds_theta", "seconds_env")},
+                     "speedup_vs_paper_cpu": 135.0 / dt}
+        log(f"  spin-1 [{prec}]: {dt:.3f} s/sweep, E = {r['energy']:.12f}")
+        del mps, env
+    return out
+
+
 def batched_rates(tnt, B, torch, precision="fp32", reps=10):
     """The 64-chain workload (L 16..64, chi 64..384, seeded) at every chain's
     middle bond: one batched H_eff application over all chains, the same 64
@@ -441,6 +479,8 @@ def main():
     ap.add_argument("--batched-sweep", action="store_true",
                     help="only run one lockstep sweep of the 64 chains, batched and chain by "
                          "chain (prints its JSON and exits; takes about two minutes)")
+    ap.add_argument("--spin1", action="store_true",
+                    help="time sweeps of the spin-1 Heisenberg chain (L = 101, chi = 200)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 64-chain batched timing (prints its JSON and exits)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -486,6 +526,9 @@ def main():
     tnt = B.load()
     if args.batched_sweep:
         print(json.dumps(batched_sweep(tnt, B, torch, args.precision)), flush=True)
+        return
+    if args.spin1:
+        print(json.dumps(spin1_sweeps(tnt, B, torch)), flush=True)
         return
     if args.batched_only:
         print(json.dumps(batched_rates(tnt, B, torch, args.precision)), flush=True)

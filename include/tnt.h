@@ -144,6 +144,15 @@ typedef struct {
 tnt_status tnt_mpo_bose_hubbard(int32_t nmax, double J, double U, double mu, double* W,
                                 int32_t* bond_charge);
 
+/* Spin-1 isotropic Heisenberg MPO site (the DMRG timing workload of Sec. 3,
+ * Table tab:dmrgtimes): H = J sum S_j . S_{j+1}.  Local states s = m + 1 in
+ * {0, 1, 2} (m = S^z), so the U(1) charge of a site is s and total S^z = 0
+ * is total charge L.  Fills W (host, 225 doubles, layout of tnt_mpo_site
+ * with d = 3, D = 5) and bond_charge[5] = (0, +1, -1, 0, 0).  The chain
+ * operator uses the left boundary index 4 and the right boundary index 0.
+ * Host only.  Errors: TNT_E_ARG (NULL), TNT_E_NONFINITE. */
+tnt_status tnt_mpo_spin1_heisenberg(double J, double* W, int32_t* bond_charge);
+
 /* ------------------------------------------------------------------------
  * H_eff . theta (Sec. 4.2, the contractor, in two-site form)
  *

@@ -10,6 +10,8 @@ computes, written from the paper's statement of the method:
   - an iterative lowest-eigenpair solver driven by that contractor (Sec. 4.2),
   - the truncated SVD with the paper's four truncation rules and error
     definition (appendix B.1.2, Eq. trunc_err),
+  - the spin-1 Heisenberg chain of the paper's DMRG timing table (Sec. 3,
+    Table tab:dmrgtimes): its Hamiltonian, exact diagonalisation and MPO,
   - the variational sweep (Sec. 4.3), here in two-site form.
 
 Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may use

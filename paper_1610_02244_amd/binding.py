@@ -93,6 +93,7 @@ SIGNATURES = {
     "tnt_pool_bytes": (C.c_int64, [P]),
     "tnt_ctx_set_autotune": (C.c_int32, [P, C.c_int32]),
     "tnt_ctx_set_graphs": (C.c_int32, [P, C.c_int32]),
+    "tnt_mpo_spin1_heisenberg": (C.c_int32, [C.c_double, F64P, I32P]),
     "tnt_mpo_bose_hubbard": (C.c_int32, [C.c_int32, C.c_double, C.c_double, C.c_double, F64P,
                                          I32P]),
     "tnt_heff2_apply": (C.c_int32, [P, C.POINTER(BTensor), C.POINTER(MpoSite),
@@ -165,6 +166,7 @@ def open_library(path: str = LIBPATH) -> C.CDLL:
 
 
 MPO_LEFT, MPO_RIGHT = 3, 0  # boundary indices of the Bose-Hubbard MPO
+SPIN1_LEFT, SPIN1_RIGHT = 4, 0  # boundary indices of the spin-1 Heisenberg MPO
 
 
 def bose_hubbard_mpo(lib, nmax, J, U, mu=0.0):
@@ -176,6 +178,17 @@ def bose_hubbard_mpo(lib, nmax, J, U, mu=0.0):
                                     W.ctypes.data_as(F64P), qw.ctypes.data_as(I32P))
     if code != 0:
         raise TntError("tnt_mpo_bose_hubbard", code, "invalid model parameters")
+    return W, [int(x) for x in qw]
+
+
+def spin1_heisenberg_mpo(lib, J):
+    """(W[w, w', s', s], bond charges) of the spin-1 Heisenberg chain."""
+    W = np.zeros((5, 5, 3, 3))
+    qw = np.zeros(5, np.int32)
+    code = lib.tnt_mpo_spin1_heisenberg(float(J), W.ctypes.data_as(F64P),
+                                        qw.ctypes.data_as(I32P))
+    if code != 0:
+        raise TntError("tnt_mpo_spin1_heisenberg", code, "invalid model parameters")
     return W, [int(x) for x in qw]
 
 
@@ -259,6 +272,9 @@ class Tnt:
 
     def bose_hubbard_mpo(self, nmax, J, U, mu=0.0):
         return bose_hubbard_mpo(self.lib, nmax, J, U, mu)
+
+    def spin1_heisenberg_mpo(self, J=1.0):
+        return spin1_heisenberg_mpo(self.lib, J)
 
     # -- packing helpers ----------------------------------------------------
     def planes(self, n, dtype=None):

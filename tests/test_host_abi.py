@@ -3,6 +3,7 @@
 * libtnt_mi355x.so loads and exports every function include/tnt.h declares.
 * The library's integer FLOP counter equals the oracle's independent count.
 * Truncation-rule selection on the host equals the oracle's rules.
+* The model MPO builders equal the oracle's MPOs.
 * Descriptor validation returns the documented error codes.
 """
 import ctypes as C
@@ -14,7 +15,7 @@ import pytest
 
 import synth
 from oracle import flops as oflops
-from oracle import model, svd as osvd
+from oracle import model, spin1 as ospin1, svd as osvd
 from paper_1610_02244_amd import binding as B
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -115,6 +116,25 @@ def test_library_mpo_equals_oracle_mpo(lib, nmax, J, U, mu):
     np.testing.assert_array_equal(Wl, Wo)
     assert list(ql) == list(qo)
     assert (B.MPO_LEFT, B.MPO_RIGHT) == (model.MPO_LEFT, model.MPO_RIGHT)
+
+
+@pytest.mark.parametrize("J", [1.0, -0.3, 2.5])
+def test_library_spin1_mpo_equals_oracle_mpo(lib, J):
+    # the oracle's spin-1 MPO is pinned to Kronecker-product Hamiltonians
+    Wl, ql = B.spin1_heisenberg_mpo(lib, J)
+    Wo, qo = ospin1.mpo(J)
+    np.testing.assert_allclose(Wl, Wo, rtol=0, atol=1e-15)
+    assert list(ql) == list(qo)
+    assert (B.SPIN1_LEFT, B.SPIN1_RIGHT) == (ospin1.MPO_LEFT, ospin1.MPO_RIGHT)
+
+
+def test_spin1_mpo_rejects_nonfinite(lib):
+    W = np.zeros((5, 5, 3, 3))
+    qw = np.zeros(5, np.int32)
+    code = lib.tnt_mpo_spin1_heisenberg(float("nan"), W.ctypes.data_as(B.F64P),
+                                        qw.ctypes.data_as(B.I32P))
+    assert code != 0
+    assert lib.tnt_mpo_spin1_heisenberg(1.0, None, None) != 0
 
 
 @pytest.mark.parametrize("seed", range(6))
