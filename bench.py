@@ -212,6 +212,29 @@ def spin1_sweeps(tnt, B, torch, precisions=("fp32", "fp64"), steps=2):
     return out
 
 
+def observables_pass(tnt, B, torch, spec, reps=3):
+    """rho_ij = <b^dagger_i b_j> for every pair (and <n_j>) of the chain's
+    state after one sweep from the seeded random MPS: one
+    tnt_mps_correlation pass, timed `reps` times after a warm-up call."""
+    import numpy as np
+    mps, env = make_chain(tnt, B, spec)
+    tnt.sweep(mps, env, spec.chi, kmax=spec.lanczos_steps, precision="fp32",
+              rel_tol=spec.rel_cutoff)
+    b = np.zeros((spec.d, spec.d))
+    for n in range(1, spec.d):
+        b[n - 1, n] = n ** 0.5
+    rho, flops = mps.correlation(b, -1, with_flops=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rho, flops = mps.correlation(b, -1, with_flops=True)
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": f"rho_ij and <n_j> of the L={spec.L}, chi={spec.chi} Bose-Hubbard state "
+                        "after one sweep", "seconds": dt, "gflop": flops / 1e9,
+            "tflops": flops / dt / 1e12, "trace_rho": float(np.trace(rho).real),
+            "max_chi": max(sum(b.values()) for b in mps.bonds())}
+
+
 def batched_rates(tnt, B, torch, precision="fp32", reps=10):
     """The 64-chain workload (L 16..64, chi 64..384, seeded) at every chain's
     middle bond: one batched H_eff application over all chains, the same 64
@@ -479,6 +502,8 @@ def main():
     ap.add_argument("--batched-sweep", action="store_true",
                     help="only run one lockstep sweep of the 64 chains, batched and chain by "
                          "chain (prints its JSON and exits; takes about two minutes)")
+    ap.add_argument("--observables", action="store_true",
+                    help="time the rho_ij / <n_j> pass on the --config state")
     ap.add_argument("--spin1", action="store_true",
                     help="time sweeps of the spin-1 Heisenberg chain (L = 101, chi = 200)")
     ap.add_argument("--batched-only", action="store_true",
@@ -526,6 +551,9 @@ def main():
     tnt = B.load()
     if args.batched_sweep:
         print(json.dumps(batched_sweep(tnt, B, torch, args.precision)), flush=True)
+        return
+    if args.observables:
+        print(json.dumps(observables_pass(tnt, B, torch, spec)), flush=True)
         return
     if args.spin1:
         print(json.dumps(spin1_sweeps(tnt, B, torch)), flush=True)

@@ -339,6 +339,23 @@ tnt_status tnt_mps_get_site(tnt_mps mps, int32_t j, int32_t cap, int32_t* nblock
  * (untruncated) SVDs on the device. */
 tnt_status tnt_mps_right_canonicalize(tnt_ctx ctx, tnt_mps mps);
 
+/* Two-point correlations of the state for every pair of sites (the outputs
+ * of the ground-state example of Sec. 5, Fig. fig:ground_state_results):
+ *   out[(i-1) L + (j-1)] = <psi| O^dagger_i O_j |psi> / <psi|psi>,
+ * i, j = 1..L, with i = j giving <(O^dagger O)_i>.  With O = b this is the
+ * single-particle density matrix rho_ij = <b^dagger_i b_j>, whose diagonal
+ * is the density <n_j>.  `op` (host, d*d doubles, op[s' d + s] = <s'|O|s>,
+ * real) may be nonzero only where s' - s = dq.  out_re / out_im: host,
+ * L*L doubles each (the matrix is Hermitian; both triangles are filled).
+ * flops (host, may be NULL) receives the pass's algorithmic flops.  Any
+ * gauge of the MPS is accepted and it is left unchanged.  Runs one
+ * left-to-right pass of FP64 grouped GEMMs over all open strings at once
+ * and synchronises the context's stream.  Errors: TNT_E_ARG (NULL),
+ * TNT_E_STATE (a site not set, zero norm), TNT_E_CHARGE (an entry of op
+ * breaks dq), TNT_E_NONFINITE. */
+tnt_status tnt_mps_correlation(tnt_ctx ctx, tnt_mps mps, const double* op, int32_t dq,
+                               double* out_re, double* out_im, double* flops);
+
 /* Environments of a right-canonical MPS for the chain MPO `mpo` (L sites,
  * borrowed only during this call: the handle keeps its own copy).  Left
  * boundary selects MPO index `left_index`, right boundary `right_index`. */

@@ -45,22 +45,23 @@ def _network(bonds, sites, d, ops):
     return complex(sum(np.trace(v) for v in E.values()))
 
 
-def correlation_matrix(bonds, sites, d, op):
+def correlation_matrix(bonds, sites, d, op, pairs=None):
     """C[i, j] = <O^dagger_i O_j> / <psi|psi> (0-based i, j) for a real
-    operator matrix op[s', s] = <s'|O|s>."""
+    operator matrix op[s', s] = <s'|O|s>; with `pairs`, only those (i, j)
+    entries are computed (the rest stay zero)."""
     op = np.asarray(op, dtype=float)
     L = len(sites)
     nrm = _network(bonds, sites, d, [None] * L).real
     C = np.zeros((L, L), dtype=complex)
-    for i in range(L):
-        for j in range(L):
-            ops = [None] * L
-            if i == j:
-                ops[i] = op.T @ op
-            else:
-                ops[i] = op.T.copy()  # <s'|O^dagger|s> = O_{s s'} for a real O
-                ops[j] = op
-            C[i, j] = _network(bonds, sites, d, ops) / nrm
+    todo = pairs if pairs is not None else [(i, j) for i in range(L) for j in range(L)]
+    for i, j in todo:
+        ops = [None] * L
+        if i == j:
+            ops[i] = op.T @ op
+        else:
+            ops[i] = op.T.copy()  # <s'|O^dagger|s> = O_{s s'} for a real O
+            ops[j] = op
+        C[i, j] = _network(bonds, sites, d, ops) / nrm
     return C
 
 

@@ -119,6 +119,7 @@ SIGNATURES = {
     "tnt_mps_get_site": (C.c_int32, [P, C.c_int32, C.c_int32, I32P, I32P, I32P, C.c_int64,
                                      F64P, F64P]),
     "tnt_mps_right_canonicalize": (C.c_int32, [P, P]),
+    "tnt_mps_correlation": (C.c_int32, [P, P, F64P, C.c_int32, F64P, F64P, F64P]),
     "tnt_env_create": (C.c_int32, [P, P, C.POINTER(MpoSite), C.c_int32, C.c_int32,
                                    C.POINTER(P)]),
     "tnt_env_destroy": (None, [P]),
@@ -554,6 +555,20 @@ class Mps:
     def right_canonicalize(self):
         self.t._check("tnt_mps_right_canonicalize",
                       self.t.lib.tnt_mps_right_canonicalize(self.t.ctx, self.h))
+
+    def correlation(self, op, dq, with_flops=False):
+        """C[i, j] = <O^dagger_i O_j> (0-based) for a real operator matrix
+        op[s', s] = <s'|O|s> that changes the charge by dq."""
+        op = np.ascontiguousarray(op, dtype=np.float64)
+        L = self.L
+        re = np.zeros((L, L))
+        im = np.zeros((L, L))
+        fl = C.c_double()
+        self.t._check("tnt_mps_correlation", self.t.lib.tnt_mps_correlation(
+            self.t.ctx, self.h, op.ctypes.data_as(F64P), int(dq), re.ctypes.data_as(F64P),
+            im.ctypes.data_as(F64P), C.byref(fl)))
+        out = re + 1j * im
+        return (out, fl.value) if with_flops else out
 
     def bond(self, ell):
         n = self.t.lib.tnt_mps_bond_size(self.h, ell)

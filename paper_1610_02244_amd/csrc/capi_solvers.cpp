@@ -385,6 +385,35 @@ tnt_status tnt_mps_right_canonicalize(tnt_ctx ctx, tnt_mps mps) {
   TNT_API_END
 }
 
+tnt_status tnt_mps_correlation(tnt_ctx ctx, tnt_mps mps, const double* op, int32_t dq,
+                               double* out_re, double* out_im, double* flops) {
+  TNT_API_BEGIN(ctx)
+  if (!mps || !op || !out_re || !out_im) fail(TNT_E_ARG, "null argument");
+  MpsObj* o = reinterpret_cast<MpsObj*>(mps);
+  MpsH& m = o->m;
+  for (int j = 1; j <= m.L; ++j)
+    if (!m.dat[j - 1].ptr) fail(TNT_E_STATE, "site " + std::to_string(j) + " not set");
+  const int d = m.d;
+  std::vector<double> w(op, op + (size_t)d * d);
+  for (int sp = 0; sp < d; ++sp)
+    for (int s = 0; s < d; ++s) {
+      const double v = w[(size_t)sp * d + s];
+      if (!std::isfinite(v)) fail(TNT_E_NONFINITE, "operator entry not finite");
+      if (v != 0.0 && sp - s != dq)
+        fail(TNT_E_CHARGE, "operator entry (" + std::to_string(sp) + ", " + std::to_string(s) +
+                               ") breaks the charge change dq");
+    }
+  std::vector<std::complex<double>> C;
+  double fl = 0.0;
+  correlation_matrix(c, m, w, dq, C, &fl);
+  for (size_t i = 0; i < C.size(); ++i) {
+    out_re[i] = C[i].real();
+    out_im[i] = C[i].imag();
+  }
+  if (flops) *flops = fl;
+  TNT_API_END
+}
+
 // ---------------------------------------------------------------------------
 // environments and sweep
 // ---------------------------------------------------------------------------

@@ -1,6 +1,8 @@
 // MPS and environment storage, and the two-site sweep (Sec. 4.3).
 #pragma once
 
+#include <complex>
+
 #include <vector>
 
 #include "lanczos.h"
@@ -39,6 +41,11 @@ void update_left_env(Ctx& c, EnvS& e, int j);
 void update_right_env(Ctx& c, EnvS& e, int j);
 void build_boundaries(Ctx& c, EnvS& e);
 void right_canonicalize(Ctx& c, MpsH& m);
+// C[(i-1) L + (j-1)] = <O^dagger_i O_j> / <psi|psi> for a real d x d
+// operator op[s' d + s] whose nonzero entries all have s' - s = dq
+// (validated by the caller); *flops = the pass's algorithmic flops.
+void correlation_matrix(Ctx& c, MpsH& m, const std::vector<double>& op, int dq,
+                        std::vector<std::complex<double>>& C, double* flops);
 
 struct SweepStats {
   double energy = 0, max_residual = 0, max_eps = 0;

@@ -259,6 +259,17 @@ void launch_scatter_z(const ScatterTask* t, int ntask, int maxrows, int maxcols,
 // last n values, their vectors mapped through Q, first n rows) into an n x n
 // eigenvector matrix at z + src_off and n eigenvalues at w + w_dst.  Every task
 // names its own z and w, so one batch can serve several thetas.
+// One dot product of the observables pass: out[2t], out[2t+1] = re, im of
+// coef * sum_{e < n} x[x_off + e] conj(y[y_off + e]).
+struct DotTask {
+  int64_t x_off, y_off;
+  int32_t n;
+  int32_t pad;
+  double coef;
+};
+void launch_block_dots(const DotTask* tasks, int ntask, const double* xre, const double* xim,
+                       const double* yre, const double* yim, double* out, hipStream_t s);
+
 struct PadTask {
   double* z;         // the matrix's job buffer: interleaved Gram in, eigenvectors out
   double* w;         // the job's eigenvalue buffer

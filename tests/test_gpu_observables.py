@@ -1,0 +1,107 @@
+"""GPU correlation pass (tnt_mps_correlation) against the observables oracle.
+
+rho_ij = <b^dagger_i b_j> and <n_j> for every pair of sites, computed on the
+device in one left-to-right pass over all open strings, compared element by
+element with the oracle's pair-by-pair network contractions of the same MPS
+(downloaded from the device after the GPU sweeps, or the seeded random MPS
+itself, which is in no canonical gauge).  Bar: |dC| <= 1e-12 max|C| (FP64
+GEMMs on both sides; the pass sums O(chi) products per entry).  At the
+chi = 256 chain: Hermitian, trace = N, the diagonal equals the oracle's
+densities and sampled off-diagonal entries equal the oracle's.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dmrg as odmrg
+from oracle import observables as oobs
+from oracle import spin1 as ospin1
+
+pytestmark = pytest.mark.gpu
+
+
+def test_random_mps_density_matrix(tnt):
+    L, N, nmax, chi = 7, 5, 3, 12
+    print(f"[correlation] random MPS L={L} N={N} chi={chi}", flush=True)
+    bonds, sites = synth.random_mps(L, N, nmax, chi, 21)
+    mps = tnt.mps(bonds, sites, nmax + 1)
+    before = mps.sites()
+    b = oobs.annihilator(nmax)
+    got = mps.correlation(b, -1)
+    ref = oobs.correlation_matrix(bonds, sites, nmax + 1, b)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"  max|dC|/max|C| = {err:.2e}")
+    assert err <= 1e-12
+    assert np.trace(got).real == pytest.approx(N, abs=1e-11)
+    # the pass leaves the MPS as it was
+    after = mps.sites()
+    for x, y in zip(before, after):
+        assert x.keys() == y.keys()
+        for k in x:
+            np.testing.assert_array_equal(x[k], y[k])
+
+
+def test_swept_state_density_matrix(tnt):
+    from paper_1610_02244_amd import binding as B
+    s = synth.CONFIGS["cfg1"]
+    print("[correlation] cfg1 after two sweeps", flush=True)
+    W, qw = tnt.bose_hubbard_mpo(s.nmax, s.J, s.U, s.mu)
+    bonds, sites = synth.random_mps(s.L, s.N, s.nmax, 32, 3)
+    mps = tnt.mps(bonds, sites, s.d)
+    mps.right_canonicalize()
+    env = B.Env(tnt, mps, [W] * s.L, qw, B.MPO_LEFT, B.MPO_RIGHT)
+    for _ in range(2):
+        tnt.sweep(mps, env, 32)
+    b = oobs.annihilator(s.nmax)
+    got = mps.correlation(b, -1)
+    ref = oobs.correlation_matrix(mps.bonds(), mps.sites(), s.d, b)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"  max|dC|/max|C| = {err:.2e}")
+    assert err <= 1e-12
+    # the sweep can go on with the same environments afterwards
+    r = tnt.sweep(mps, env, 32)
+    assert np.isfinite(r["energy"])
+
+
+def test_spin1_lowering_correlation(tnt):
+    print("[correlation] spin-1 S^- random MPS", flush=True)
+    bonds, sites = synth.random_mps(6, 6, 2, 9, 4)
+    mps = tnt.mps(bonds, sites, 3)
+    _, sm, _, _ = ospin1.local_ops()
+    got = mps.correlation(sm, -1)
+    ref = oobs.correlation_matrix(bonds, sites, 3, sm)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_operator_charge_checked(tnt):
+    from paper_1610_02244_amd import binding as B
+    bonds, sites = synth.random_mps(4, 3, 2, 4, 1)
+    mps = tnt.mps(bonds, sites, 3)
+    bad = oobs.annihilator(2) + np.eye(3)  # mixes dq = -1 and dq = 0
+    with pytest.raises(B.TntError) as ei:
+        mps.correlation(bad, -1)
+    assert ei.value.code == -3  # TNT_E_CHARGE
+
+
+def test_cfg2_density_matrix_properties(tnt):
+    from paper_1610_02244_amd import binding as B
+    s = synth.CONFIGS["cfg2"]
+    print(f"[correlation] cfg2 L={s.L} chi={s.chi}", flush=True)
+    W, qw = tnt.bose_hubbard_mpo(s.nmax, s.J, s.U, s.mu)
+    bonds, sites = synth.random_mps(s.L, s.N, s.nmax, s.chi, s.seed)
+    mps = tnt.mps(bonds, sites, s.d)
+    mps.right_canonicalize()
+    env = B.Env(tnt, mps, [W] * s.L, qw, B.MPO_LEFT, B.MPO_RIGHT)
+    tnt.sweep(mps, env, s.chi, kmax=s.lanczos_steps, rel_tol=s.rel_cutoff)
+    b = oobs.annihilator(s.nmax)
+    got = mps.correlation(b, -1)
+    assert np.max(np.abs(got - got.conj().T)) <= 1e-12
+    assert np.trace(got).real == pytest.approx(s.N, abs=1e-9)
+    hb, hs = mps.bonds(), mps.sites()
+    dens = odmrg.site_densities(hb, hs, s.d)
+    assert np.max(np.abs(np.diag(got).real - dens)) <= 1e-11
+    pairs = [(0, s.L - 1), (3, 4), (s.L // 2, s.L // 2 + 7)]
+    ref = oobs.correlation_matrix(hb, hs, s.d, b, pairs=pairs)
+    for i, j in pairs:
+        print(f"  rho[{i},{j}] gpu {got[i, j].real:.14f} oracle {ref[i, j].real:.14f}")
+        assert abs(got[i, j] - ref[i, j]) <= 1e-12 * max(1.0, abs(ref[i, j]))
