@@ -199,6 +199,18 @@ def random_mps(L: int, N: int, nmax: int, chi: int, seed: int):
     return bonds, sites
 
 
+def product_mps(config):
+    """Product state |n_1 ... n_L> as a block MPS: every bond one sector of
+    dimension 1 (the charge to its left), every site one 1 x 1 block = 1."""
+    bonds, q = [{0: 1}], 0
+    sites = []
+    for s in config:
+        sites.append({(q, int(s)): np.ones((1, 1), dtype=complex)})
+        q += int(s)
+        bonds.append({q: 1})
+    return bonds, sites
+
+
 def random_theta(left, right, d, rng):
     return {k: _cnormal(rng, (left[k[0]], right[k[0] + k[1] + k[2]]))
             for k in theta_keys(left, right, d)}
