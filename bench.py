@@ -235,6 +235,51 @@ def observables_pass(tnt, B, torch, spec, reps=3):
             "max_chi": max(sum(b.values()) for b in mps.bonds())}
 
 
+def tebd_steps(tnt, B, torch):
+    """TEBD time steps (second-order: every bond gated twice per step).
+    (1) The timing-table shape: spin-1 Heisenberg, L = 101, chi = 1000, from
+    a seeded random MPS of that bond dimension (right-canonicalised), one
+    warm-up step and one timed step.  (2) The time-evolution example: hard-
+    core bosons, L = 51, CDW of 25 bosons, dt = 0.01, chi = 200, 100 steps."""
+    import synth
+    out = {"paper_s_per_step_u1": {"mkl_nag_magma": 59.0, "mkl_nag": 57.0, "mkl_arpack": 73.0}}
+    L, chi = 101, 1000
+    h = tnt.bond_hamiltonians_spin1(L)
+    bonds, sites = synth.random_mps(L, L, 2, chi, 6)
+    mps = tnt.mps(bonds, sites, 3)
+    mps.right_canonicalize()
+    r0 = tnt.tebd_step(mps, h, 0.01, chi)
+    log(f"  spin-1 TEBD warm-up step: {r0['seconds_total']:.2f} s, max chi {r0['max_chi']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = tnt.tebd_step(mps, h, 0.01, chi)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["spin1_L101_chi1000"] = {"s_per_step": dt, "seconds_svd": r["seconds_svd"],
+                                 "seconds_theta_gate": r["seconds_gate"],
+                                 "max_chi": r["max_chi"], "sum_eps": r["sum_eps"],
+                                 "gates_per_step": 2 * (L - 1),
+                                 "speedup_vs_paper_u1_best": 57.0 / dt}
+    log(f"  spin-1 TEBD step: {dt:.2f} s")
+    del mps
+    L = 51
+    h = tnt.bond_hamiltonians_bose_hubbard(L, 1, 1.0, 0.0)
+    bonds, sites = synth.product_mps(tuple(j % 2 for j in range(L)))
+    mps = tnt.mps(bonds, sites, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eps = 0.0
+    for _ in range(100):
+        r = tnt.tebd_step(mps, h, 0.01, 200, renormalise=False)
+        eps += r["sum_eps"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["hardcore_cdw_L51_chi200"] = {"s_per_step": dt / 100, "steps": 100,
+                                      "max_chi_at_t1": r["max_chi"], "accumulated_eps": eps}
+    log(f"  hard-core CDW: {dt / 100 * 1e3:.1f} ms per step")
+    return out
+
+
 def batched_rates(tnt, B, torch, precision="fp32", reps=10):
     """The 64-chain workload (L 16..64, chi 64..384, seeded) at every chain's
     middle bond: one batched H_eff application over all chains, the same 64
@@ -502,6 +547,8 @@ def main():
     ap.add_argument("--batched-sweep", action="store_true",
                     help="only run one lockstep sweep of the 64 chains, batched and chain by "
                          "chain (prints its JSON and exits; takes about two minutes)")
+    ap.add_argument("--tebd", action="store_true",
+                    help="time TEBD steps (spin-1 L = 101, chi = 1000; hard-core CDW L = 51)")
     ap.add_argument("--observables", action="store_true",
                     help="time the rho_ij / <n_j> pass on the --config state")
     ap.add_argument("--spin1", action="store_true",
@@ -551,6 +598,9 @@ def main():
     tnt = B.load()
     if args.batched_sweep:
         print(json.dumps(batched_sweep(tnt, B, torch, args.precision)), flush=True)
+        return
+    if args.tebd:
+        print(json.dumps(tebd_steps(tnt, B, torch)), flush=True)
         return
     if args.observables:
         print(json.dumps(observables_pass(tnt, B, torch, spec)), flush=True)

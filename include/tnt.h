@@ -153,6 +153,17 @@ tnt_status tnt_mpo_bose_hubbard(int32_t nmax, double J, double U, double mu, dou
  * Host only.  Errors: TNT_E_ARG (NULL), TNT_E_NONFINITE. */
 tnt_status tnt_mpo_spin1_heisenberg(double J, double* W, int32_t* bond_charge);
 
+/* Bond Hamiltonians for tnt_tebd_step: h (host, (L-1) d^4 doubles) gets
+ * h_j, j = 1..L-1, as d^2 x d^2 row-major matrices with row s1' d + s2' and
+ * column s1 d + s2, so that sum_j h_j = H.  Bose-Hubbard (Sec. 5, Eq. 2,
+ * V = 0, d = nmax + 1): the bond's hopping plus the on-site terms of its
+ * two sites, each shared equally with the site's other bond (an end site
+ * puts its whole term on its only bond).  Spin-1 Heisenberg (d = 3):
+ * h_j = J S_j . S_{j+1}.  Host only.  Errors: TNT_E_ARG, TNT_E_NONFINITE. */
+tnt_status tnt_bond_hamiltonians_bose_hubbard(int32_t L, int32_t nmax, double J, double U,
+                                              double mu, double* h);
+tnt_status tnt_bond_hamiltonians_spin1(int32_t L, double J, double* h);
+
 /* ------------------------------------------------------------------------
  * H_eff . theta (Sec. 4.2, the contractor, in two-site form)
  *
@@ -353,6 +364,27 @@ tnt_status tnt_mps_right_canonicalize(tnt_ctx ctx, tnt_mps mps);
  * and synchronises the context's stream.  Errors: TNT_E_ARG (NULL),
  * TNT_E_STATE (a site not set, zero norm), TNT_E_CHARGE (an entry of op
  * breaks dq), TNT_E_NONFINITE. */
+/* One TEBD time step (time evolution by two-site Trotter gates, Sec. 1 and
+ * the example of Sec. 5, Fig. fig:time_evolve_results): with the bond
+ * Hamiltonians h (host, layout of tnt_bond_hamiltonians_*; each real
+ * symmetric and charge-conserving), applies exp(-i h_j dt/2) to
+ * theta = A_j B_{j+1} and splits it by the truncated SVD (`trunc`,
+ * appendix B.1.2) for j = 1..L-1 (centre moving right), then for
+ * j = L-1..1 (centre moving back): a second-order Trotter step.  The MPS
+ * must be right-canonical with its centre on site 1 (tnt_mps_right_
+ * canonicalize, a product state, or the state a sweep or a previous step
+ * leaves) and is left the same way.  bond_eps / bond_chi (host, may be
+ * NULL, capacity record_cap >= 2(L-1)) receive the truncation error and
+ * kept dimension of each gate in order; stats (host, may be NULL, 6
+ * doubles): seconds total, seconds theta + gate, seconds SVD, sum of the
+ * truncation errors, largest truncation error, largest kept chi.
+ * Synchronises the context's stream.  Errors: TNT_E_ARG (NULL, chi_max < 1,
+ * h not symmetric), TNT_E_CHARGE (h mixes charges), TNT_E_CAPACITY,
+ * TNT_E_STATE (a site not set), TNT_E_NONFINITE. */
+tnt_status tnt_tebd_step(tnt_ctx ctx, tnt_mps mps, const double* h, double dt,
+                         const tnt_trunc_params* trunc, int32_t record_cap, double* bond_eps,
+                         int32_t* bond_chi, double* stats);
+
 tnt_status tnt_mps_correlation(tnt_ctx ctx, tnt_mps mps, const double* op, int32_t dq,
                                double* out_re, double* out_im, double* flops);
 

@@ -120,6 +120,10 @@ SIGNATURES = {
                                      F64P, F64P]),
     "tnt_mps_right_canonicalize": (C.c_int32, [P, P]),
     "tnt_mps_correlation": (C.c_int32, [P, P, F64P, C.c_int32, F64P, F64P, F64P]),
+    "tnt_tebd_step": (C.c_int32, [P, P, F64P, C.c_double, P, C.c_int32, F64P, I32P, F64P]),
+    "tnt_bond_hamiltonians_bose_hubbard": (C.c_int32, [C.c_int32, C.c_int32, C.c_double,
+                                                       C.c_double, C.c_double, F64P]),
+    "tnt_bond_hamiltonians_spin1": (C.c_int32, [C.c_int32, C.c_double, F64P]),
     "tnt_env_create": (C.c_int32, [P, P, C.POINTER(MpoSite), C.c_int32, C.c_int32,
                                    C.POINTER(P)]),
     "tnt_env_destroy": (None, [P]),
@@ -191,6 +195,25 @@ def spin1_heisenberg_mpo(lib, J):
     if code != 0:
         raise TntError("tnt_mpo_spin1_heisenberg", code, "invalid model parameters")
     return W, [int(x) for x in qw]
+
+
+def bond_hamiltonians_bose_hubbard(lib, L, nmax, J, U, mu=0.0):
+    """(L-1, d^2, d^2) bond Hamiltonians of the Bose-Hubbard chain."""
+    d = nmax + 1
+    h = np.zeros((L - 1, d * d, d * d))
+    code = lib.tnt_bond_hamiltonians_bose_hubbard(int(L), int(nmax), float(J), float(U),
+                                                  float(mu), h.ctypes.data_as(F64P))
+    if code != 0:
+        raise TntError("tnt_bond_hamiltonians_bose_hubbard", code, "invalid model parameters")
+    return h
+
+
+def bond_hamiltonians_spin1(lib, L, J=1.0):
+    h = np.zeros((L - 1, 9, 9))
+    code = lib.tnt_bond_hamiltonians_spin1(int(L), float(J), h.ctypes.data_as(F64P))
+    if code != 0:
+        raise TntError("tnt_bond_hamiltonians_spin1", code, "invalid model parameters")
+    return h
 
 
 def _i32(a):
@@ -496,6 +519,29 @@ class Tnt:
             d.update({"bond_E": E, "bond_eps": eps, "bond_chi": chi, "bond_steps": steps})
             out.append(d)
         return out
+
+    def tebd_step(self, mps, h, dt, chi_max, rel_tol=-1.0, abs_tol=-1.0, err_tol=-1.0,
+                  err_type=TNT_ERR_2NORM, renormalise=True):
+        """One second-order TEBD step of dt with bond Hamiltonians h
+        (L-1, d^2, d^2); returns per-gate truncation errors, kept dims, stats."""
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        cap = 2 * (mps.L - 1)
+        eps = np.zeros(cap)
+        chi = np.zeros(cap, np.int32)
+        stats = np.zeros(6)
+        tp = TruncParams(int(chi_max), err_type, abs_tol, rel_tol, err_tol, int(bool(renormalise)))
+        self._check("tnt_tebd_step", self.lib.tnt_tebd_step(
+            self.ctx, mps.h, h.ctypes.data_as(F64P), float(dt), C.byref(tp), cap,
+            eps.ctypes.data_as(F64P), chi.ctypes.data_as(I32P), stats.ctypes.data_as(F64P)))
+        return {"bond_eps": eps.tolist(), "bond_chi": chi.tolist(), "seconds_total": stats[0],
+                "seconds_gate": stats[1], "seconds_svd": stats[2], "sum_eps": stats[3],
+                "max_eps": stats[4], "max_chi": int(stats[5])}
+
+    def bond_hamiltonians_bose_hubbard(self, L, nmax, J, U, mu=0.0):
+        return bond_hamiltonians_bose_hubbard(self.lib, L, nmax, J, U, mu)
+
+    def bond_hamiltonians_spin1(self, L, J=1.0):
+        return bond_hamiltonians_spin1(self.lib, L, J)
 
     def sweep(self, mps, env, chi_max, kmax=20, precision="fp64", rel_tol=1e-12, abs_tol=-1.0,
               err_tol=-1.0, err_type=TNT_ERR_2NORM, beta_tol=1e-12):

@@ -414,6 +414,50 @@ tnt_status tnt_mps_correlation(tnt_ctx ctx, tnt_mps mps, const double* op, int32
   TNT_API_END
 }
 
+tnt_status tnt_tebd_step(tnt_ctx ctx, tnt_mps mps, const double* h, double dt,
+                         const tnt_trunc_params* trunc, int32_t record_cap, double* bond_eps,
+                         int32_t* bond_chi, double* stats) {
+  TNT_API_BEGIN(ctx)
+  if (!mps || !h || !trunc) fail(TNT_E_ARG, "null argument");
+  MpsObj* o = reinterpret_cast<MpsObj*>(mps);
+  MpsH& m = o->m;
+  for (int j = 1; j <= m.L; ++j)
+    if (!m.dat[j - 1].ptr) fail(TNT_E_STATE, "site " + std::to_string(j) + " not set");
+  if (!std::isfinite(dt)) fail(TNT_E_NONFINITE, "dt not finite");
+  if (trunc->chi_max < 1) fail(TNT_E_ARG, "chi_max < 1");
+  if ((bond_eps || bond_chi) && record_cap < 2 * (m.L - 1))
+    fail(TNT_E_CAPACITY, "record arrays shorter than 2(L-1)");
+  const int d = m.d, n = d * d;
+  for (int b = 0; b < m.L - 1; ++b) {
+    const double* hb = h + (size_t)b * n * n;
+    double scale = 0.0;
+    for (int i = 0; i < n * n; ++i) {
+      if (!std::isfinite(hb[i])) fail(TNT_E_NONFINITE, "bond Hamiltonian entry not finite");
+      scale = std::max(scale, std::fabs(hb[i]));
+    }
+    for (int r = 0; r < n; ++r)
+      for (int col = 0; col < n; ++col) {
+        const double v = hb[(size_t)r * n + col];
+        if (std::fabs(v - hb[(size_t)col * n + r]) > 1e-12 * scale)
+          fail(TNT_E_ARG, "bond Hamiltonian " + std::to_string(b + 1) + " not symmetric");
+        if (v != 0.0 && r / d + r % d != col / d + col % d)
+          fail(TNT_E_CHARGE, "bond Hamiltonian " + std::to_string(b + 1) +
+                                 " does not conserve the charge");
+      }
+  }
+  TebdStats st;
+  tebd_step(c, m, h, dt, *trunc, st, bond_eps, bond_chi);
+  if (stats) {
+    stats[0] = st.t_total;
+    stats[1] = st.t_gate;
+    stats[2] = st.t_svd;
+    stats[3] = st.sum_eps;
+    stats[4] = st.max_eps;
+    stats[5] = st.max_chi;
+  }
+  TNT_API_END
+}
+
 // ---------------------------------------------------------------------------
 // environments and sweep
 // ---------------------------------------------------------------------------

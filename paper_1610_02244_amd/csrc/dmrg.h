@@ -44,6 +44,19 @@ void right_canonicalize(Ctx& c, MpsH& m);
 // C[(i-1) L + (j-1)] = <O^dagger_i O_j> / <psi|psi> for a real d x d
 // operator op[s' d + s] whose nonzero entries all have s' - s = dq
 // (validated by the caller); *flops = the pass's algorithmic flops.
+// theta of sites (j, j+1) into `out` (grown as needed), canonical layout
+ThetaH form_theta(Ctx& c, MpsH& m, int j, DevBuf& out);
+
+struct TebdStats {
+  double t_total = 0, t_gate = 0, t_svd = 0;
+  double sum_eps = 0, max_eps = 0;
+  int max_chi = 0;
+};
+// One second-order TEBD step (bond Hamiltonians h: (L-1) blocks of d^2 x d^2
+// real symmetric, charge-conserving, validated by the caller).
+void tebd_step(Ctx& c, MpsH& m, const double* h, double dt, const tnt_trunc_params& tp,
+               TebdStats& st, double* bond_eps, int32_t* bond_chi);
+
 void correlation_matrix(Ctx& c, MpsH& m, const std::vector<double>& op, int dq,
                         std::vector<std::complex<double>>& C, double* flops);
 

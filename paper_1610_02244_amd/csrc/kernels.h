@@ -270,6 +270,24 @@ struct DotTask {
 void launch_block_dots(const DotTask* tasks, int ntask, const double* xre, const double* xim,
                        const double* yre, const double* yim, double* out, hipStream_t s);
 
+// Two-site gate on theta (TEBD): destination block t = sum over its terms
+// of (cr + i ci) * source block, elementwise over `size` elements; chunks
+// are (task, chunk index) pairs of GATE_CHUNK elements.
+constexpr int GATE_CHUNK = 1024;
+struct GateTask {
+  int64_t dst_off;
+  int32_t size;
+  int32_t term0, nterm;
+  int32_t pad;
+};
+struct GateTerm {
+  int64_t src_off;
+  double cr, ci;
+};
+void launch_gate_apply(const GateTask* tasks, const GateTerm* terms, const int2* chunks,
+                       int nchunks, const double* sre, const double* sim, double* dre,
+                       double* dim, hipStream_t s);
+
 struct PadTask {
   double* z;         // the matrix's job buffer: interleaved Gram in, eigenvectors out
   double* w;         // the job's eigenvalue buffer

@@ -70,3 +70,54 @@ extern "C" tnt_status tnt_mpo_spin1_heisenberg(double J, double* W, int32_t* bon
   bond_charge[4] = 0;
   return TNT_OK;
 }
+
+// Bond Hamiltonians for a TEBD step, h_j on sites (j, j+1) as d^2 x d^2
+// matrices, row (s1' d + s2'), column (s1 d + s2); sum_j h_j = H.
+// Bose-Hubbard (Sec. 5, Eq. 2 with V = 0): the hopping of the bond plus the
+// on-site terms of its two sites, each shared equally with the site's other
+// bond (an end site puts its whole term on its only bond).
+extern "C" tnt_status tnt_bond_hamiltonians_bose_hubbard(int32_t L, int32_t nmax, double J,
+                                                         double U, double mu, double* h) {
+  if (!h || L < 2 || nmax < 1) return TNT_E_ARG;
+  if (!std::isfinite(J) || !std::isfinite(U) || !std::isfinite(mu)) return TNT_E_NONFINITE;
+  const int d = nmax + 1, n = d * d;
+  auto onsite = [&](int k) { return 0.5 * U * k * (k - 1.0) - mu * k; };
+  for (int b = 1; b < L; ++b) {
+    double* hb = h + (size_t)(b - 1) * n * n;
+    for (int i = 0; i < n * n; ++i) hb[i] = 0.0;
+    const double wl = b == 1 ? 1.0 : 0.5, wr = b + 1 == L ? 1.0 : 0.5;
+    for (int s1 = 0; s1 < d; ++s1)
+      for (int s2 = 0; s2 < d; ++s2) {
+        const int col = s1 * d + s2;
+        hb[(size_t)col * n + col] = wl * onsite(s1) + wr * onsite(s2);
+        // -J b^dagger_1 b_2: (s1 + 1, s2 - 1), amplitude sqrt((s1 + 1) s2)
+        if (s1 + 1 < d && s2 >= 1)
+          hb[(size_t)((s1 + 1) * d + (s2 - 1)) * n + col] = -J * std::sqrt((s1 + 1.0) * s2);
+        // -J b_1 b^dagger_2
+        if (s1 >= 1 && s2 + 1 < d)
+          hb[(size_t)((s1 - 1) * d + (s2 + 1)) * n + col] = -J * std::sqrt(s1 * (s2 + 1.0));
+      }
+  }
+  return TNT_OK;
+}
+
+// Spin-1 isotropic Heisenberg (Table tab:tebdtimes): h_j = J S_j . S_{j+1}
+// on s = S^z + 1, the same on every bond.
+extern "C" tnt_status tnt_bond_hamiltonians_spin1(int32_t L, double J, double* h) {
+  if (!h || L < 2) return TNT_E_ARG;
+  if (!std::isfinite(J)) return TNT_E_NONFINITE;
+  const int d = 3, n = 9;
+  for (int b = 1; b < L; ++b) {
+    double* hb = h + (size_t)(b - 1) * n * n;
+    for (int i = 0; i < n * n; ++i) hb[i] = 0.0;
+    for (int s1 = 0; s1 < d; ++s1)
+      for (int s2 = 0; s2 < d; ++s2) {
+        const int col = s1 * d + s2;
+        hb[(size_t)col * n + col] = J * (s1 - 1.0) * (s2 - 1.0);
+        // J/2 S+_1 S-_2 and J/2 S-_1 S+_2; every spin-1 ladder element is sqrt(2)
+        if (s1 + 1 < d && s2 >= 1) hb[(size_t)((s1 + 1) * d + (s2 - 1)) * n + col] = J;
+        if (s1 >= 1 && s2 + 1 < d) hb[(size_t)((s1 - 1) * d + (s2 + 1)) * n + col] = J;
+      }
+  }
+  return TNT_OK;
+}

@@ -128,6 +128,18 @@ def test_library_spin1_mpo_equals_oracle_mpo(lib, J):
     assert (B.SPIN1_LEFT, B.SPIN1_RIGHT) == (ospin1.MPO_LEFT, ospin1.MPO_RIGHT)
 
 
+@pytest.mark.parametrize("L,nmax,J,U,mu", [(2, 1, 1.0, 0.0, 0.0), (5, 2, 0.8, 2.5, 0.3),
+                                           (4, 4, 1.0, 4.0, -0.2)])
+def test_library_bond_hamiltonians_equal_oracle(lib, L, nmax, J, U, mu):
+    from oracle import tebd as otebd
+    got = B.bond_hamiltonians_bose_hubbard(lib, L, nmax, J, U, mu)
+    want = otebd.bond_hamiltonians_bh(L, nmax, J, U, mu)
+    np.testing.assert_allclose(got, np.array(want), rtol=0, atol=1e-14)
+    got1 = B.bond_hamiltonians_spin1(lib, L, J)
+    np.testing.assert_allclose(got1, np.array(otebd.bond_hamiltonians_spin1(L, J)), rtol=0,
+                               atol=1e-14)
+
+
 def test_spin1_mpo_rejects_nonfinite(lib):
     W = np.zeros((5, 5, 3, 3))
     qw = np.zeros(5, np.int32)
