@@ -385,6 +385,31 @@ tnt_status tnt_tebd_step(tnt_ctx ctx, tnt_mps mps, const double* h, double dt,
                          const tnt_trunc_params* trunc, int32_t record_cap, double* bond_eps,
                          int32_t* bond_chi, double* stats);
 
+/* Truncated SVD of a matrix with no known symmetry through automatic
+ * blocking (the library's auto-blocking mode, Fig. fig:autoblocking, Table
+ * tab:tebdtimes): entries with |a_ij| <= tol are dropped; rows and columns
+ * are grouped into the connected components of the bipartite graph of the
+ * remaining entries (the block-diagonal form after permutations); every
+ * block gets the block SVD of the U(1) sectors, and all blocks' singular
+ * values are cut together by `trunc` (appendix B.1.2).
+ * a_re / a_im: device planes, m x n, row stride lda >= n (borrowed).
+ * Outputs (device planes, overwritten): U (m rows, stride ldu >= chi_max)
+ * with orthonormal columns, B = S V^+ (chi_max rows, stride ldb >= n), so
+ * that U B is the truncated matrix (renormalised if trunc->renormalise);
+ * columns of U / rows of B beyond chi are zero.  Host outputs: S (chi_max
+ * doubles: the kept singular values, grouped by block in the order of each
+ * block's smallest row index, descending within a block, column c of U
+ * belonging to S[c]), chi, nblocks (may be NULL), eps (may be NULL:
+ * truncation error of the trunc->err_type kind).  Singular values below
+ * about 1e-7 of the largest are not resolved (they count as zero).
+ * Synchronises the context's stream.  Errors: TNT_E_ARG (NULL, shapes,
+ * strides, chi_max < 1, tol < 0), TNT_E_NONFINITE. */
+tnt_status tnt_auto_block_svd(tnt_ctx ctx, const double* a_re, const double* a_im, int32_t m,
+                              int32_t n, int64_t lda, double tol, const tnt_trunc_params* trunc,
+                              double* u_re, double* u_im, int64_t ldu, double* b_re,
+                              double* b_im, int64_t ldb, double* S, int32_t* chi,
+                              int32_t* nblocks, double* eps);
+
 tnt_status tnt_mps_correlation(tnt_ctx ctx, tnt_mps mps, const double* op, int32_t dq,
                                double* out_re, double* out_im, double* flops);
 

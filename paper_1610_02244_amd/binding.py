@@ -120,6 +120,9 @@ SIGNATURES = {
                                      F64P, F64P]),
     "tnt_mps_right_canonicalize": (C.c_int32, [P, P]),
     "tnt_mps_correlation": (C.c_int32, [P, P, F64P, C.c_int32, F64P, F64P, F64P]),
+    "tnt_auto_block_svd": (C.c_int32, [P, F64P, F64P, C.c_int32, C.c_int32, C.c_int64,
+                                       C.c_double, P, F64P, F64P, C.c_int64, F64P, F64P,
+                                       C.c_int64, F64P, I32P, I32P, F64P]),
     "tnt_tebd_step": (C.c_int32, [P, P, F64P, C.c_double, P, C.c_int32, F64P, I32P, F64P]),
     "tnt_bond_hamiltonians_bose_hubbard": (C.c_int32, [C.c_int32, C.c_int32, C.c_double,
                                                        C.c_double, C.c_double, F64P]),
@@ -399,6 +402,38 @@ class Tnt:
         return {"E_ritz": r.E_ritz, "E": r.E_refined, "residual": r.residual,
                 "steps": r.steps, "status": code}
 
+
+    def auto_block_svd(self, A, tol, chi_max, abs_tol=-1.0, rel_tol=-1.0, err_tol=-1.0,
+                       err_type=TNT_ERR_2NORM, renormalise=False):
+        """Truncated SVD of a dense complex matrix A (host array, m x n) through
+        automatic blocking; returns dict(U, B, S, chi, nblocks, eps) with U (m x chi)
+        and B (chi x n) on the host, U @ B the truncated matrix."""
+        import torch
+        A = np.asarray(A, dtype=complex)
+        m, n = A.shape
+        are = torch.from_numpy(np.ascontiguousarray(A.real)).to(self.dev)
+        aim = torch.from_numpy(np.ascontiguousarray(A.imag)).to(self.dev)
+        ure = torch.empty((m, chi_max), dtype=torch.float64, device=self.dev)
+        uim = torch.empty_like(ure)
+        bre = torch.empty((chi_max, n), dtype=torch.float64, device=self.dev)
+        bim = torch.empty_like(bre)
+        S = np.zeros(chi_max)
+        chi = C.c_int32()
+        nb = C.c_int32()
+        eps = C.c_double()
+        tp = TruncParams(int(chi_max), err_type, abs_tol, rel_tol, err_tol, int(bool(renormalise)))
+
+        def fp(t):
+            return C.cast(C.c_void_p(t.data_ptr()), F64P)
+
+        self._check("tnt_auto_block_svd", self.lib.tnt_auto_block_svd(
+            self.ctx, fp(are), fp(aim), m, n, n, float(tol), C.byref(tp), fp(ure), fp(uim),
+            chi_max, fp(bre), fp(bim), n, S.ctypes.data_as(F64P), C.byref(chi), C.byref(nb),
+            C.byref(eps)))
+        k = chi.value
+        U = (ure.cpu().numpy() + 1j * uim.cpu().numpy())[:, :k]
+        Bm = (bre.cpu().numpy() + 1j * bim.cpu().numpy())[:k]
+        return {"U": U, "B": Bm, "S": S[:k], "chi": k, "nblocks": nb.value, "eps": eps.value}
 
     def svd_truncate(self, theta, chi_max, abs_tol=-1.0, rel_tol=-1.0, err_tol=-1.0,
                      err_type=TNT_ERR_2NORM, renormalise=True, absorb="right"):

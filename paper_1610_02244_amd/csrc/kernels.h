@@ -288,6 +288,27 @@ void launch_gate_apply(const GateTask* tasks, const GateTerm* terms, const int2*
                        int nchunks, const double* sre, const double* sim, double* dre,
                        double* dim, hipStream_t s);
 
+// Automatic blocking: mask[i n + j] = |a_ij|^2 > tol^2 for an m x n matrix
+// (row stride ld); and a block copy dst(r, c) = src(r, c) for r < rows,
+// c < cols, where a row (column) index of either side is idx[list + r] when
+// its list offset is >= 0, else r (source) or base + r (destination);
+// entries with |x|^2 <= tol2 are copied as zero (tol2 < 0: none).
+// rows[i] = (task, row) pairs, one workgroup each.
+struct IndexCopyTask {
+  int64_t src_off, src_ld;
+  int64_t dst_off, dst_ld;
+  int32_t src_ridx, src_cidx;
+  int32_t dst_ridx, dst_cidx;
+  int32_t dst_rbase, dst_cbase;
+  int32_t rows, cols;
+  double tol2;
+};
+void launch_nonzero_mask(const double* re, const double* im, int m, int n, int64_t ld,
+                         double tol, unsigned char* mask, hipStream_t s);
+void launch_index_copy(const IndexCopyTask* tasks, const int2* rows, int nrows,
+                       const int32_t* idx, const double* sre, const double* sim, double* dre,
+                       double* dim, hipStream_t s);
+
 struct PadTask {
   double* z;         // the matrix's job buffer: interleaved Gram in, eigenvectors out
   double* w;         // the job's eigenvalue buffer
