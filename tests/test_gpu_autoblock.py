@@ -57,3 +57,15 @@ def test_auto_block_svd_all_below_tolerance(tnt):
     M = 1e-9 * np.ones((4, 5))
     got = tnt.auto_block_svd(M, 1e-6, 3)
     assert got["chi"] == 0 and got["nblocks"] == 0
+
+
+@pytest.mark.parametrize("shape", [(1, 7), (9, 1), (40, 25)])
+def test_auto_block_svd_dense_and_thin(tnt, shape):
+    # no structure: one block, the plain truncated SVD
+    rng = np.random.default_rng(sum(shape))
+    M = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    got = tnt.auto_block_svd(M, 0.0, 50)
+    S = np.linalg.svd(M, compute_uv=False)
+    assert got["nblocks"] == 1 and got["chi"] == min(shape)
+    np.testing.assert_allclose(np.sort(got["S"])[::-1], S, atol=1e-10 * S[0])
+    np.testing.assert_allclose(got["U"] @ got["B"], M, atol=1e-10 * S[0])

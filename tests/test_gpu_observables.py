@@ -105,3 +105,15 @@ def test_cfg2_density_matrix_properties(tnt):
     for i, j in pairs:
         print(f"  rho[{i},{j}] gpu {got[i, j].real:.14f} oracle {ref[i, j].real:.14f}")
         assert abs(got[i, j] - ref[i, j]) <= 1e-12 * max(1.0, abs(ref[i, j]))
+
+
+def test_two_site_chain_and_hardcore(tnt):
+    # smallest chain, and d = 2
+    for L, N, nmax, chi, seed in [(2, 1, 1, 2, 5), (2, 3, 2, 3, 6), (9, 4, 1, 16, 7)]:
+        print(f"[correlation] L={L} N={N} nmax={nmax}", flush=True)
+        bonds, sites = synth.random_mps(L, N, nmax, chi, seed)
+        mps = tnt.mps(bonds, sites, nmax + 1)
+        b = oobs.annihilator(nmax)
+        got = mps.correlation(b, -1)
+        ref = oobs.correlation_matrix(bonds, sites, nmax + 1, b)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))

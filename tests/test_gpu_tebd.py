@@ -87,3 +87,25 @@ def test_tebd_rejects_charge_mixing(tnt):
     with pytest.raises(B.TntError) as ei:
         tnt.tebd_step(mps, h, 0.01, 4)
     assert ei.value.code == -3  # TNT_E_CHARGE
+
+
+def test_tebd_two_site_chain(tnt):
+    # L = 2: one bond, gated twice with dt/2 = one exact gate of dt
+    print("[tebd] L=2", flush=True)
+    h = tnt.bond_hamiltonians_bose_hubbard(2, 2, 1.0, 1.5, 0.2)
+    bonds, sites = synth.product_mps((2, 0))
+    mps = tnt.mps(bonds, sites, 3)
+    tnt.tebd_step(mps, h, 0.3, 9)
+    hs = otebd.bond_hamiltonians_bh(2, 2, 1.0, 1.5, 0.2)
+    G = otebd.gate(hs[0], 0.3)
+    # the state of two sites as a 3 x 3 matrix psi[s1, s2]
+    psi0 = np.zeros(9, complex)
+    psi0[2 * 3 + 0] = 1.0
+    want = (G @ psi0).reshape(3, 3)
+    got = np.zeros((3, 3), complex)
+    hb, hsites = mps.bonds(), mps.sites()
+    for (q, s1), A in hsites[0].items():
+        for (q2, s2), Bm in hsites[1].items():
+            if q2 == q + s1:
+                got[s1, s2] += (A @ Bm)[0, 0]
+    np.testing.assert_allclose(got, want, atol=1e-12)

@@ -95,3 +95,14 @@ def test_free_boson_condensate_closed_form():
                     for j in range(1, L + 1)])
     np.testing.assert_allclose(C.real, N * np.outer(phi, phi), atol=1e-8)
     assert np.max(np.abs(C.imag)) < 1e-10
+
+
+def test_reflection_symmetry_of_ground_state():
+    # Eq. 2 with V = 0 on an open chain is symmetric under j -> L + 1 - j, so the
+    # (non-degenerate) ground state has rho_ij = rho_{L+1-i, L+1-j}
+    L, N, nmax = 6, 4, 2
+    bonds, sites, _ = odmrg.run_dmrg(L, N, nmax, 1.0, 3.0, 0.0, 64, seed=8, sweeps=3,
+                                      random_mps=synth.random_mps)
+    C = oobs.correlation_matrix(bonds, sites, nmax + 1, oobs.annihilator(nmax))
+    np.testing.assert_allclose(C, C[::-1, ::-1], atol=1e-8)
+    assert np.trace(C).real == pytest.approx(N, abs=1e-10)
