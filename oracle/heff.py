@@ -89,3 +89,41 @@ def heff2_matrix_dense(Ld, W1, W2, Rd):
     M = np.einsum('xwa,wvSs,vuTt,yub->xSTyastb', Ld, W1, W2, Rd, optimize=True)
     n = Da * d * d * Db
     return M.reshape(n, n)
+
+
+def heff1_block(L, W, R, A, qw, d):
+    """One-site form of the contractor (Sec. 4.2, Listing lis:varmincontract):
+    y[a', s', b'] = sum L[a', w, a] W[w, u, s', s] R[b', u, b] A[a, s, b].
+
+    L: {(w, q_a): (dim(q_a+qw[w]), dim(q_a))}; R likewise on the right bond;
+    A: {(q_a, s): (dim(q_a), dim(q_a+s))}.  Returns y with A's keys.
+    """
+    D = len(qw)
+    # T1[w; a', s, b] = sum_a L[a', w, a] A[a, s, b]  (key: w, q_a', s)
+    T1 = {}
+    for (qa, s), a in A.items():
+        for w in range(D):
+            blk = L.get((w, qa))
+            if blk is not None:
+                T1[(w, qa + qw[w], s)] = blk @ a
+    # T2[u; a', s', b] = sum_{w, s} W[w, u, s', s] T1[w; a', s, b]
+    T2 = {}
+    for (w, qap, s), t in T1.items():
+        for u in range(D):
+            for sp in range(d):
+                c = W[w, u, sp, s]
+                if c == 0.0:
+                    continue
+                key = (u, qap, sp)
+                T2[key] = T2[key] + c * t if key in T2 else c * t
+    # y[a', s', b'] = sum_{u, b} T2[u; a', s', b] R[b', u, b]; b = a' + s' - qw[u]
+    y = {k: np.zeros_like(v) for k, v in A.items()}
+    for (u, qap, sp), t in T2.items():
+        key = (qap, sp)
+        if key not in y:
+            continue
+        rblk = R.get((u, qap + sp - qw[u]))
+        if rblk is None:
+            continue
+        y[key] += t @ rblk.T
+    return y
