@@ -164,6 +164,18 @@ tnt_status tnt_bond_hamiltonians_bose_hubbard(int32_t L, int32_t nmax, double J,
                                               double mu, double* h);
 tnt_status tnt_bond_hamiltonians_spin1(int32_t L, double J, double* h);
 
+/* One-site H_eff . A (Sec. 4.2, the contractor, in its one-site form, as
+ * used by single-site updates):
+ *   out[a', s', b'] = sum L[a', w, a] W[w, u, s', s] R[b', u, b] A[a, s, b].
+ * A and out are rank-3 site tensors: labels (q_a, s, q_b), extents
+ * (dim_a, 1, dim_b), rule q_b = q_a + s, TNT_DT_F64, the same block set and
+ * extents (offsets may differ).  L, R: environments as for tnt_heff2_apply.
+ * FP64 arithmetic.  Output blocks no term reaches are written as zeros.
+ * Synchronises the context's stream.  Errors: TNT_E_ARG, TNT_E_SHAPE,
+ * TNT_E_CHARGE, TNT_E_CAPACITY. */
+tnt_status tnt_heff1_apply(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_site* W,
+                           const tnt_btensor* R, const tnt_btensor* A, const tnt_btensor* out);
+
 /* ------------------------------------------------------------------------
  * H_eff . theta (Sec. 4.2, the contractor, in two-site form)
  *

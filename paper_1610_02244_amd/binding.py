@@ -120,6 +120,7 @@ SIGNATURES = {
                                      F64P, F64P]),
     "tnt_mps_right_canonicalize": (C.c_int32, [P, P]),
     "tnt_mps_correlation": (C.c_int32, [P, P, F64P, C.c_int32, F64P, F64P, F64P]),
+    "tnt_heff1_apply": (C.c_int32, [P, P, P, P, P, P]),
     "tnt_auto_block_svd": (C.c_int32, [P, F64P, F64P, C.c_int32, C.c_int32, C.c_int64,
                                        C.c_double, P, F64P, F64P, C.c_int64, F64P, F64P,
                                        C.c_int64, F64P, I32P, I32P, F64P]),
@@ -337,6 +338,32 @@ class Tnt:
         d.keys = keys
         d.shapes = [th[k].shape for k in keys]
         return d
+
+    def site(self, A: dict, keys=None):
+        """Descriptor of a site tensor {(q_a, s): (dim_a, dim_b)}."""
+        keys = sorted(A) if keys is None else keys
+        qn, ext, off, pos = [], [], [], 0
+        for (qa, s) in keys:
+            r, c = A[(qa, s)].shape
+            qn.append((qa, s, qa + s))
+            ext.append((r, 1, c))
+            off.append(pos)
+            pos += r * c
+        re, im = self._upload([A[k] for k in keys])
+        d = Descriptor(3, qn, ext, off, re, im)
+        d.keys = keys
+        d.shapes = [A[k].shape for k in keys]
+        return d
+
+    def site_like(self, desc: Descriptor):
+        re, im = self.planes(int(desc.re.numel()))
+        d = Descriptor(3, desc.qn.reshape(-1, 3), desc.ext.reshape(-1, 3), desc.off, re, im)
+        d.keys, d.shapes = desc.keys, desc.shapes
+        return d
+
+    def heff1_apply(self, L, W, R, A, out):
+        return self._check("tnt_heff1_apply",
+                           self.lib.tnt_heff1_apply(self.ctx, L.ref, W.ref, R.ref, A.ref, out.ref))
 
     def theta_like(self, desc: Descriptor):
         re, im = self.planes(int(desc.re.numel()))
