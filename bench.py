@@ -248,11 +248,11 @@ def tebd_steps(tnt, B, torch):
     bonds, sites = synth.random_mps(L, L, 2, chi, 6)
     mps = tnt.mps(bonds, sites, 3)
     mps.right_canonicalize()
-    r0 = tnt.tebd_step(mps, h, 0.01, chi)
+    r0 = tnt.tebd_step(mps, h, 0.01, chi, rel_tol=-1.0)
     log(f"  spin-1 TEBD warm-up step: {r0['seconds_total']:.2f} s, max chi {r0['max_chi']}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = tnt.tebd_step(mps, h, 0.01, chi)
+    r = tnt.tebd_step(mps, h, 0.01, chi, rel_tol=-1.0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     out["spin1_L101_chi1000"] = {"s_per_step": dt, "seconds_svd": r["seconds_svd"],
@@ -264,19 +264,22 @@ def tebd_steps(tnt, B, torch):
     del mps
     L = 51
     h = tnt.bond_hamiltonians_bose_hubbard(L, 1, 1.0, 0.0)
-    bonds, sites = synth.product_mps(tuple(j % 2 for j in range(L)))
-    mps = tnt.mps(bonds, sites, 2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    eps = 0.0
-    for _ in range(100):
-        r = tnt.tebd_step(mps, h, 0.01, 200, renormalise=False)
-        eps += r["sum_eps"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out["hardcore_cdw_L51_chi200"] = {"s_per_step": dt / 100, "steps": 100,
-                                      "max_chi_at_t1": r["max_chi"], "accumulated_eps": eps}
-    log(f"  hard-core CDW: {dt / 100 * 1e3:.1f} ms per step")
+    for name, rel in (("chi_only", -1.0), ("rel_cut_1e-12", 1e-12)):
+        bonds, sites = synth.product_mps(tuple(j % 2 for j in range(L)))
+        mps = tnt.mps(bonds, sites, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eps = 0.0
+        for _ in range(100):
+            r = tnt.tebd_step(mps, h, 0.01, 200, rel_tol=rel, renormalise=False)
+            eps += r["sum_eps"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"hardcore_cdw_L51_chi200_{name}"] = {"s_per_step": dt / 100, "steps": 100,
+                                                  "max_chi_at_t1": r["max_chi"],
+                                                  "accumulated_eps": eps}
+        log(f"  hard-core CDW ({name}): {dt / 100 * 1e3:.1f} ms per step, chi {r['max_chi']}")
+        del mps
     return out
 
 

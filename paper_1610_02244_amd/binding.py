@@ -582,10 +582,12 @@ class Tnt:
             out.append(d)
         return out
 
-    def tebd_step(self, mps, h, dt, chi_max, rel_tol=-1.0, abs_tol=-1.0, err_tol=-1.0,
+    def tebd_step(self, mps, h, dt, chi_max, rel_tol=1e-12, abs_tol=-1.0, err_tol=-1.0,
                   err_type=TNT_ERR_2NORM, renormalise=True):
         """One second-order TEBD step of dt with bond Hamiltonians h
-        (L-1, d^2, d^2); returns per-gate truncation errors, kept dims, stats."""
+        (L-1, d^2, d^2); returns per-gate truncation errors, kept dims, stats.
+        The default relative cut (as in sweep) drops singular values that are
+        zero to working precision; rel_tol=-1 keeps up to chi_max values."""
         h = np.ascontiguousarray(h, dtype=np.float64)
         cap = 2 * (mps.L - 1)
         eps = np.zeros(cap)
