@@ -283,6 +283,51 @@ def tebd_steps(tnt, B, torch):
     return out
 
 
+def heff1_rates(tnt, B, torch, spec, reps=20):
+    """One-site H_eff . A (tnt_heff1_apply, FP64) at the middle site of the
+    chain's sector recipe: seeded random environments and site tensor.
+    Each call builds its task lists on the host and synchronises, so the
+    per-call time includes that host work; algorithmic flops counted from
+    the block structure (8 real flops per complex MAC)."""
+    import numpy as np
+    import synth
+    W, qw = tnt.bose_hubbard_mpo(spec.nmax, spec.J, spec.U, spec.mu)
+    bonds = synth.chain_bonds(spec.L, spec.N, spec.nmax, spec.chi)
+    j = spec.L // 2
+    left, right = bonds[j - 1], bonds[j]
+    rng = np.random.Generator(np.random.PCG64(spec.seed * 7919 + 29))
+    Lenv = synth.random_env(left, qw, rng, HERM_PAIRS)
+    Renv = synth.random_env(right, qw, rng, HERM_PAIRS)
+    A = {k: rng.normal(size=(left[k[0]], right[k[0] + k[1]])) + 0j
+         for k in synth.site_keys(left, right, spec.d)}
+    D, d = len(qw), spec.d
+    flops, ykeys = 0.0, {}
+    for (qa, s), a in A.items():
+        for w in range(D):
+            if (w, qa) in Lenv:
+                flops += 8.0 * Lenv[(w, qa)].shape[0] * a.shape[1] * a.shape[0]
+                for u in range(D):
+                    for sp in range(d):
+                        if W[w, u, sp, s] != 0.0:
+                            ykeys[(u, qa + qw[w], sp)] = a.shape[1]
+    for (u, qap, sp), K in ykeys.items():
+        if (qap, sp) in A and (u, qap + sp - qw[u]) in Renv:
+            flops += 8.0 * A[(qap, sp)].shape[0] * A[(qap, sp)].shape[1] * K
+    mpo = B.Mpo(W, qw)
+    Ld, Rd, Ad = tnt.env(Lenv, qw), tnt.env(Renv, qw), tnt.site(A)
+    out = tnt.site_like(Ad)
+    tnt.heff1_apply(Ld, mpo, Rd, Ad, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        tnt.heff1_apply(Ld, mpo, Rd, Ad, out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": f"one-site H_eff at site {j} of the L={spec.L}, chi={spec.chi} recipe",
+            "seconds_per_call": dt, "gflop": flops / 1e9, "tflops_fp64": flops / dt / 1e12,
+            "site_elems": int(sum(a.size for a in A.values()))}
+
+
 def autoblock_svd_rates(tnt, B, torch, reps=3):
     """Truncated SVD of a 3000 x 3000 complex matrix whose block structure
     (20 blocks of 60..240 rows and columns) is hidden by random row and column
@@ -588,6 +633,8 @@ def main():
     ap.add_argument("--batched-sweep", action="store_true",
                     help="only run one lockstep sweep of the 64 chains, batched and chain by "
                          "chain (prints its JSON and exits; takes about two minutes)")
+    ap.add_argument("--heff1", action="store_true",
+                    help="time the one-site H_eff at the --config chain's middle site")
     ap.add_argument("--autoblock", action="store_true",
                     help="time the auto-blocking SVD of a matrix with hidden blocks")
     ap.add_argument("--tebd", action="store_true",
@@ -641,6 +688,9 @@ def main():
     tnt = B.load()
     if args.batched_sweep:
         print(json.dumps(batched_sweep(tnt, B, torch, args.precision)), flush=True)
+        return
+    if args.heff1:
+        print(json.dumps(heff1_rates(tnt, B, torch, spec)), flush=True)
         return
     if args.autoblock:
         print(json.dumps(autoblock_svd_rates(tnt, B, torch)), flush=True)
