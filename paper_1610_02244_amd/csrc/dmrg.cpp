@@ -606,6 +606,11 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
       jp.push_back(jobs.back().get());
     }
     svd_eig(c, jp);
+    {
+      std::vector<tnt_trunc_params> tp;
+      for (size_t a = 0; a < act.size(); ++a) tp.push_back(ps[act[a].i].trunc);
+      svd_refine(c, jp, tp);
+    }
     t_svd += now_s() - te0;
     for (size_t a = 0; a < act.size(); ++a) {
       const int i = act[a].i, j = act[a].j, pass = act[a].pass;

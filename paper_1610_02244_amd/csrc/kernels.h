@@ -252,11 +252,13 @@ void launch_scatter_z(const ScatterTask* t, int ntask, int maxrows, int maxcols,
                       const double* src_z, double* re, double* im, hipStream_t s);
 // Padded batches of Hermitian matrices (interleaved complex, column-major).
 // embed maps an n x n Gram matrix G at src into the npad x npad slot at dst
-// as Q diag(G, D) Q (D negative, distinct, below G's spectrum; Q a fixed
+// as Q diag(G, D) Q / s (D negative, distinct, below G's spectrum; Q a fixed
 // Householder reflector that leaves no exact split in the tridiagonal
-// reduction), using vec (2 npad doubles per slot at 2 w_src) as work space;
+// reduction; s = trace G, written to *scale: the library eigensolver's
+// tolerances are not scale invariant, so every slot is solved at unit
+// scale), using vec (2 npad doubles per slot at 2 w_src) as work space;
 // extract takes G's eigenpairs back from the slot's ascending eigenpairs (the
-// last n values, their vectors mapped through Q, first n rows) into an n x n
+// last n values times s, their vectors mapped through Q, first n rows) into an n x n
 // eigenvector matrix at z + src_off and n eigenvalues at w + w_dst.  Every task
 // names its own z and w, so one batch can serve several thetas.
 // One dot product of the observables pass: out[2t], out[2t+1] = re, im of
@@ -317,6 +319,7 @@ struct PadTask {
   int64_t w_src;     // offset of the slot's npad eigenvalues (and work vector)
   int64_t w_dst;     // offset of the sector's n eigenvalues in w
   int32_t n, npad;
+  double* scale;     // padded path: the slot's scale factor (written by embed)
 };
 // Small sectors (n <= EIG_SMALL_MAX): eigenpairs of the Hermitian matrix at
 // z + src_off (interleaved, column-major, upper triangle used), ascending
@@ -330,6 +333,24 @@ void launch_pad_embed(const PadTask* t, int ntask, int max_n, int max_npad, doub
                       double* dst_z, hipStream_t s);
 void launch_pad_extract(const PadTask* t, int ntask, int max_n, const double* slot_z,
                         const double* slot_w, hipStream_t s);
+
+// Column staging of the deflated SVD (interleaved complex, column-major):
+// dst = scale * src over n complex values (one task per column), and the
+// squared 2-norm of n complex values at src into *out (one workgroup per
+// task, fixed summation order).
+struct ZCopyTask {
+  const double* src;
+  double* dst;
+  int64_t n;
+  double scale;
+};
+struct ZNormTask {
+  const double* src;
+  double* out;
+  int64_t n;
+};
+void launch_zcopy(const ZCopyTask* t, int ntask, int64_t max_n, hipStream_t s);
+void launch_znorm2(const ZNormTask* t, int ntask, hipStream_t s);
 
 // z[2k] = re[k], z[2k+1] = (conj ? -im[k] : im[k]) for k < n
 void launch_interleave(const double* re, const double* im, double* z, int64_t n, int conj,

@@ -2,19 +2,39 @@
 //
 // For every middle charge m = q_a + s1, theta restricted to m is a matrix
 // X_m with rows (s1, a) and columns (s2, b).  Its singular vectors are
-// obtained from the FP64 Hermitian eigendecomposition of a Gram matrix
-// (rocSOLVER zheevd, divide and conquer), built blockwise on the grouped
-// MFMA GEMM:
+// obtained from FP64 Hermitian eigendecompositions, built blockwise on the
+// grouped MFMA GEMM:
 //   absorb RIGHT (A = U, B = S V^+): G = X X^+ ; A = eigenvectors (an exact
 //     isometry), B = A^+ X (an exact projection, GEMM);
 //   absorb LEFT  (A = U S, B = V^+): G = X^+ X ; B = eigenvectors^+, A = X V.
-// The isometric factor is therefore orthonormal to working precision and the
-// other factor is the exact projection of theta onto the kept space; the
-// singular values are sqrt of the Gram eigenvalues.  Eigenvalues below the
-// Gram matrix's rounding floor (n * 4 eps * largest) carry no information and
-// are set to zero.  All sectors' values are pooled on the host, sorted and
-// cut by the four truncation rules; the centre factor is renormalised to unit
-// Frobenius norm on the device.
+// The isometric factor is orthonormal to working precision and the other
+// factor is the exact projection of theta onto the kept space.
+//
+// Singular values by deflation.  An eigenvalue of G carries an absolute
+// error of about eps |G| = eps sigma_0^2, so sqrt of a Gram eigenvalue says
+// nothing about a singular value below ~1e-7 sigma_0.  Instead, with U the
+// eigenvectors, the rows of B = U^+ Y (Y = X, or X^+ for LEFT) are taken:
+// the norm of row i is sigma_i to about eps sigma_0 absolute whenever its
+// eigenvalue lies well above the rounding band (its vector then mixes with
+// the others only by ~eps |G| / gap).  The rows whose eigenvalue lies below
+// tau mu_max (the "cluster") span the small-value subspace to the same
+// accuracy but are mixed among themselves, so they form the next level's
+// problem: B_c (cluster rows) has the cluster's singular values, and the
+// Gram matrix B_c B_c^+ is decomposed again with a rounding band scaled by
+// its own, much smaller, norm.  Before that, B_c is orthogonalised (twice)
+// against the normalised resolved rows of every level so far: a cluster
+// vector mixes with a resolved direction j by ~eps mu_max / mu_j, which puts
+// a component of size eps sigma_0^2 / sigma_j along that row's direction
+// into B_c (~1e-11 sigma_0 for sigma_j just above the threshold); it lies in
+// the span of the resolved rows, so the projection removes it and the small
+// values keep an absolute accuracy of ~eps sigma_0.  Levels repeat until the truncation rules can
+// be decided (the cut lies above every unresolved cluster, whose exact sum
+// of squares |B_c|_F^2 then enters the truncation error) or the cluster is at
+// the noise level of the projection.  The kept vectors of level L are
+// Q_L U_L[:, i], with Q_L the product of the earlier levels' cluster bases.
+// All sectors' values are pooled on the host, sorted and cut by the four
+// truncation rules; the centre factor is renormalised to unit Frobenius norm
+// on the device.
 #include "svd.h"
 
 #include <rocblas/rocblas.h>
@@ -22,6 +42,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
+#include <limits>
 #include <numeric>
 #include <set>
 
@@ -118,15 +140,55 @@ SiteH make_site(const Bond& left, const Bond& right, int d) {
 }
 
 namespace {
+constexpr double kEps = 2.220446049250313e-16;
+// Eigenvalues below kTau * (largest of the level) form the next level.  The
+// eigensolver's backward error b is ~6e-16 |G| at unit scale and order 100,
+// ~2e-15 |G| at order 1000 (measured), and a resolved value's row norm has a
+// relative error of about (b / kTau)^2 from mixing with the cluster: with
+// kTau = 1e-10, 4e-10 at the threshold (~4e-15 sigma_0 absolute), falling
+// 100-fold per decade above it.
+constexpr double kTau = 1e-10;
+constexpr int kMaxLevels = 4;
+
+// One level of a sector's deflated eigendecomposition.  Level 0 is the Gram
+// matrix of theta's sector; level L >= 1 is the Gram matrix of the previous
+// level's cluster rows.  Matrices are interleaved complex, column-major.
+struct Level {
+  int n = 0;                  // order of the eigenproblem
+  DevBuf buf;                 // level >= 1: U (n x n), Z (nother x n), Q (ngram x n, L >= 2), w
+  double* U = nullptr;        // eigenvectors (ld n), ascending eigenvalues
+  double* w = nullptr;        // eigenvalues (device)
+  double* Z = nullptr;        // B^+ = (U^+ Y)^+ (ld nother): column i has norm sigma_i
+  const double* Q = nullptr;  // basis of this level's index space (ld ngram); null at level 0
+  std::vector<double> mu;     // host: eigenvalues, ascending
+  std::vector<double> s2;     // host: squared column norms of Z
+  int clus = 0;               // indices [0, clus) unresolved (the next level's problem)
+  double bound = 0;           // upper bound of the cluster's singular values
+  double fro2 = 0;            // sum of squares of the cluster's singular values
+  int info = 0;
+};
+
 struct Sector {
   int m = 0;
   std::vector<std::pair<int, int>> rows, cols;  // (s1, q_a), (s2, q_b) ascending
   std::vector<int> roff, coff;
   int R = 0, C = 0;
   int n = 0;             // Gram dimension (R for absorb right, C for absorb left)
-  int64_t gbase = 0;     // offset of the n x n Gram matrix (elements / complex elements)
+  int nother = 0;        // the other dimension
+  int64_t gbase = 0;     // offset of the n x n Gram matrix (complex elements)
   int ebase = 0;         // offset of its eigenvalues
+  int64_t zbase = 0;     // offset of level 0's Z (nother x n) in the job's zb buffer
+  double sigma0 = 0;     // largest singular value of the sector
+  std::vector<Level> lv;
+  DevBuf vres;           // normalised resolved directions of all levels (nother x nres)
+  int nres = 0;
+  bool open = false;     // the last level has an unresolved cluster
+  bool noise = false;    // refinement stopped at the noise level
+  // resolved spectrum, descending: (value, level, index in that level)
+  struct Val { double lam; int level, idx; };
+  std::vector<Val> vals;
   int kept = 0;
+  int64_t ukbase = 0;    // offset of the kept isometric vectors (n x kept) in the job's uk
   int64_t tbase = 0;     // offset of V_kept (C x kept) in the left-absorb temp
 };
 
@@ -162,10 +224,35 @@ int padded_size(int n) {
   return (n + 511) / 512 * 512;
 }
 
-int index_of(const std::vector<std::pair<int, int>>& v, int first) {
-  for (size_t i = 0; i < v.size(); ++i)
-    if (v[i].first == first) return (int)i;
-  return -1;
+// One Hermitian eigenproblem of a batch: the n x n matrix at z + 2 zoff
+// (interleaved, column-major, upper triangle read) is replaced by its
+// eigenvectors and its ascending eigenvalues go to w + woff.  `rebuild`
+// writes the input matrix again (for the fallback solver).
+struct EigProb {
+  double* z = nullptr;
+  double* w = nullptr;
+  int64_t zoff = 0;
+  int64_t woff = 0;
+  int n = 0;
+  int* info = nullptr;
+  std::function<void()> rebuild;
+};
+
+rocblas_double_complex* zc(double* p) { return reinterpret_cast<rocblas_double_complex*>(p); }
+const rocblas_double_complex* zc(const double* p) {
+  return reinterpret_cast<const rocblas_double_complex*>(p);
+}
+
+// C = alpha op(A) op(B) + beta C (interleaved complex, column-major)
+void zgemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+           const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+           double alpha = 1.0, double beta = 0.0) {
+  if (m <= 0 || n <= 0) return;
+  const rocblas_double_complex a{alpha, 0.0}, b{beta, 0.0};
+  if (k <= 0) fail(TNT_E_ARG, "empty inner dimension in an SVD product");
+  if (rocblas_zgemm(h, ta, tb, m, n, k, &a, zc(A), lda, zc(B), ldb, &b, zc(C), ldc) !=
+      rocblas_status_success)
+    fail(TNT_E_HIP, "rocblas_zgemm failed");
 }
 }  // namespace
 
@@ -178,11 +265,15 @@ struct SvdJob {
   std::vector<Sector> secs;
   int64_t gsize = 0;  // complex elements of the Gram matrices
   int esize = 0;      // eigenvalues
+  int64_t zsize = 0;  // complex elements of the level-0 projections
   DevTables tg;
-  DevBuf gram, z, ev, info;
-  std::vector<rocblas_int> hinfo;  // per sector, from the batched eigensolve
+  DevBuf gram, z, ev, zb;
+  int levels = 1;
+  bool open = false;              // refinement still needed
+  double extra_tail = 0;          // sum of squares of the unresolved (discarded) clusters
 };
 
+int svd_levels(const SvdJob& job) { return job.levels; }
 
 std::shared_ptr<SvdJob> svd_begin(Ctx& c, const ThetaH& th, const double* re, const double* im,
                                   int absorb) {
@@ -201,10 +292,13 @@ std::shared_ptr<SvdJob> svd_begin(Ctx& c, const ThetaH& th, const double* re, co
   int& esize = J.esize;
   for (auto& s : secs) {
     s.n = right ? s.R : s.C;
+    s.nother = right ? s.C : s.R;
     s.gbase = gsize;
     gsize += (int64_t)s.n * s.n;
     s.ebase = esize;
     esize += s.n;
+    s.zbase = J.zsize;
+    J.zsize += (int64_t)s.n * s.nother;
   }
   // --- Gram matrices (split planes, row-major n x n per sector) -------------
   HostGemm gg;
@@ -247,8 +341,6 @@ std::shared_ptr<SvdJob> svd_begin(Ctx& c, const ThetaH& th, const double* re, co
   J.gram = DevBuf(&c.pool, std::max<int64_t>(1, 2 * gsize) * sizeof(double));
   J.z = DevBuf(&c.pool, std::max<int64_t>(1, 2 * gsize) * sizeof(double));
   J.ev = DevBuf(&c.pool, (size_t)std::max(1, 2 * esize) * sizeof(double));
-  J.info = DevBuf(&c.pool, std::max<size_t>(secs.size(), 1) * sizeof(rocblas_int));
-  J.hinfo.assign(secs.size(), 0);
   double* g = J.gram.as<double>();
   run_gemm(c, J.tg.g[0], right ? FORM_cNT : FORM_CN, PATH_F64, re, im, ET_F64, re, im, ET_F64, g,
            g + gsize, ET_F64);
@@ -257,53 +349,41 @@ std::shared_ptr<SvdJob> svd_begin(Ctx& c, const ThetaH& th, const double* re, co
   return job;
 }
 
-void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
-  // Small sectors are solved by cyclic Jacobi in LDS (see below).  For the
-  // larger ones each decomposition is a long
-  // chain of small, latency-bound launches, so the sectors of all jobs go
-  // through a few strided-batched calls
-  // (buckets): every sector is padded to its bucket's size (G plus negative
-  // eigenvalues below its spectrum, mixed by a fixed reflector so that no
-  // exact split remains; see the padding kernels).  The buckets run
+// Eigendecompositions of a batch of Hermitian matrices of any orders.
+static void eig_batch(Ctx& c, std::vector<EigProb>& probs) {
+  // Small problems are solved by cyclic Jacobi in LDS (see below).  For the
+  // larger ones each decomposition is a long chain of small, latency-bound
+  // launches, so the problems go through a few strided-batched calls
+  // (buckets): every matrix is padded to its bucket's size (the matrix plus
+  // negative eigenvalues below its spectrum, mixed by a fixed reflector so
+  // that no exact split remains; see the padding kernels).  The buckets run
   // concurrently on side streams, forked from and joined back into the main
-  // stream; G's eigenpairs are extracted back into each job's z and W.
+  // stream; the eigenpairs are extracted back into each problem's buffers.
   ensure_side(c);
-  struct Ref { SvdJob* job; int sec; };
   struct Bucket {
     int npad = 0;
-    std::vector<Ref> secs;
+    std::vector<int> ids;
     std::vector<PadTask> tasks;
-    DevBuf slots, w, e, tab, info;
+    DevBuf slots, w, e, tab, info, sc;
   };
-  // at most one bucket per side stream (the last stream runs the Jacobi launches)
   constexpr int kMaxBuckets = Ctx::kSide - 1;
-  std::vector<Ref> all, small[2];
-  auto n_of = [](const Ref& r) { return r.job->secs[r.sec].n; };
-  // Small sectors (order <= EIG_SMALL_MAX) go to the Jacobi kernel beside
-  // the library calls, in two launches (orders <= 16 and <= 32, so that the
-  // smallest take less LDS).
-  for (SvdJob* j : jobs)
-    for (size_t i = 0; i < j->secs.size(); ++i) {
-      const Ref r{j, (int)i};
-      const int n = n_of(r);
-      if (n <= EIG_SMALL_MAX) small[n <= 16 ? 0 : 1].push_back(r);
-      else all.push_back(r);
-    }
+  std::vector<int> all, small[2];
+  for (size_t i = 0; i < probs.size(); ++i) {
+    const int n = probs[i].n;
+    if (n <= 0) continue;
+    if (n <= EIG_SMALL_MAX) small[n <= 16 ? 0 : 1].push_back((int)i);
+    else all.push_back((int)i);
+  }
   std::stable_sort(all.begin(), all.end(),
-                   [&](const Ref& a, const Ref& b) { return n_of(a) > n_of(b); });
-  // The large sectors form buckets, each one batched library call padded to
-  // the size class of its largest sector.  The calls' launch chains are
-  // enqueued one after another, so their times add up; a bucket of `cnt`
-  // matrices of padded order np is modelled as
+                   [&](int a, int b) { return probs[a].n > probs[b].n; });
+  // A bucket of `cnt` matrices of padded order np is modelled as
   //   latency 0.028 np ms  +  cnt x (0.020 (np / 128)^2.2 ms  for np > 64,
   //                                  0.1 (np / 32)^2 ms      for np <= 64),
   // fitted to timings of the library's batched Hermitian eigensolver on one
   // MI355X (np = 32 .. 256, batches 1 .. 512; at np <= 64 its time grows
-  // linearly with the batch).  Few sectors (one chain) give one or two
-  // buckets; many sectors (many chains in a step) give more, so that small
-  // ones are not padded to the largest.  The bucketing that minimises the
-  // modelled time over contiguous runs of size classes (at most
-  // kMaxBuckets buckets) is found by dynamic programming.
+  // linearly with the batch).  The bucketing that minimises the modelled
+  // time over contiguous runs of size classes (at most kMaxBuckets buckets)
+  // is found by dynamic programming.
   auto cost = [](int np, int cnt) {
     const double x = np;
     const double per = np > 64 ? 0.020 * std::pow(x / 128.0, 2.2) : 0.1 * (x / 32.0) * (x / 32.0);
@@ -311,12 +391,11 @@ void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
   };
   std::vector<std::pair<int, int>> cls;  // (padded order, first index into all), descending
   for (size_t i = 0; i < all.size(); ++i) {
-    const int np = padded_size(n_of(all[i]));
+    const int np = padded_size(probs[all[i]].n);
     if (cls.empty() || cls.back().first != np) cls.push_back({np, (int)i});
   }
   const int nc = (int)cls.size();
   auto first = [&](int k) { return k < nc ? cls[k].second : (int)all.size(); };
-  // best[b][k]: least modelled time of classes [0, k) in b buckets
   const double inf = 1e300;
   std::vector<std::vector<double>> best(kMaxBuckets + 1, std::vector<double>(nc + 1, inf));
   std::vector<std::vector<int>> from(kMaxBuckets + 1, std::vector<int>(nc + 1, -1));
@@ -339,7 +418,7 @@ void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
     const int a = from[b][k];
     Bucket& bk = buckets[b - 1];
     bk.npad = cls[a].first;
-    for (int i = first(a); i < first(k); ++i) bk.secs.push_back(all[i]);
+    for (int i = first(a); i < first(k); ++i) bk.ids.push_back(all[i]);
     k = a;
   }
   TNT_HIP(hipEventRecord(c.side_ev[Ctx::kSide], c.stream));
@@ -355,12 +434,10 @@ void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
   for (int g = 0; g < 2; ++g) {
     if (small[g].empty()) continue;
     SmallSet& S = sm[g];
-    for (const Ref& r : small[g]) {
-      SvdJob& J = *r.job;
-      const Sector& sc = J.secs[r.sec];
-      S.tasks.push_back(PadTask{J.z.as<double>(), J.ev.as<double>(), sc.gbase, 0, 0, sc.ebase,
-                                sc.n, sc.n});
-      S.maxn = std::max(S.maxn, sc.n);
+    for (int id : small[g]) {
+      const EigProb& P = probs[id];
+      S.tasks.push_back(PadTask{P.z, P.w, P.zoff, 0, 0, P.woff, P.n, P.n, nullptr});
+      S.maxn = std::max(S.maxn, P.n);
     }
     S.tab = DevBuf(&c.pool, S.tasks.size() * sizeof(PadTask));
     S.info = DevBuf(&c.pool, S.tasks.size() * sizeof(int));
@@ -375,15 +452,15 @@ void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
   }
   int k = 0;
   for (Bucket& bk : buckets) {
-    const int np = bk.npad, cnt = (int)bk.secs.size();
+    const int np = bk.npad, cnt = (int)bk.ids.size();
     const int64_t slot = (int64_t)np * np;
     int maxn = 1;
+    bk.sc = DevBuf(&c.pool, (size_t)cnt * sizeof(double));
     for (int q = 0; q < cnt; ++q) {
-      SvdJob& J = *bk.secs[q].job;
-      const Sector& sc = J.secs[bk.secs[q].sec];
-      bk.tasks.push_back(PadTask{J.z.as<double>(), J.ev.as<double>(), sc.gbase, q * slot,
-                                 (int64_t)q * np, sc.ebase, sc.n, np});
-      maxn = std::max(maxn, sc.n);
+      const EigProb& P = probs[bk.ids[q]];
+      bk.tasks.push_back(PadTask{P.z, P.w, P.zoff, q * slot, (int64_t)q * np, P.woff, P.n, np,
+                                 bk.sc.as<double>() + q});
+      maxn = std::max(maxn, P.n);
     }
     bk.slots = DevBuf(&c.pool, (size_t)2 * slot * cnt * sizeof(double));
     bk.w = DevBuf(&c.pool, (size_t)np * cnt * sizeof(double));
@@ -418,17 +495,428 @@ void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
   // the buckets (device slots and host task lists) live until here
   TNT_HIP(hipStreamSynchronize(c.stream));
   for (Bucket& bk : buckets) {
-    std::vector<rocblas_int> raw(bk.secs.size());
+    std::vector<rocblas_int> raw(bk.ids.size());
     TNT_HIP(hipMemcpy(raw.data(), bk.info.ptr, raw.size() * sizeof(rocblas_int),
                       hipMemcpyDeviceToHost));
-    for (size_t q = 0; q < raw.size(); ++q) bk.secs[q].job->hinfo[bk.secs[q].sec] = raw[q];
+    for (size_t q = 0; q < raw.size(); ++q) *probs[bk.ids[q]].info = raw[q];
   }
   for (int g = 0; g < 2; ++g) {
     if (small[g].empty()) continue;
     std::vector<int> raw(small[g].size());
     TNT_HIP(hipMemcpy(raw.data(), sm[g].info.ptr, raw.size() * sizeof(int),
                       hipMemcpyDeviceToHost));
-    for (size_t q = 0; q < raw.size(); ++q) small[g][q].job->hinfo[small[g][q].sec] = raw[q];
+    for (size_t q = 0; q < raw.size(); ++q) *probs[small[g][q]].info = raw[q];
+  }
+  // divide and conquer can fail on large clusters of (near-)zero eigenvalues;
+  // redo such a problem with the library's Jacobi eigensolver
+  rocblas_handle h = blas(c);
+  for (EigProb& P : probs) {
+    if (P.n <= 0 || *P.info == 0) continue;
+    P.rebuild();
+    DevBuf rj(&c.pool, 64), inf(&c.pool, sizeof(rocblas_int));
+    if (rocsolver_zheevj(h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper,
+                         P.n, zc(P.z) + P.zoff, P.n, 0.0, rj.as<double>(), 100,
+                         rj.as<rocblas_int>() + 4, P.w + P.woff,
+                         inf.as<rocblas_int>()) != rocblas_status_success)
+      fail(TNT_E_HIP, "rocsolver_zheevj failed");
+    TNT_HIP(hipMemcpyAsync(P.info, inf.ptr, sizeof(rocblas_int), hipMemcpyDeviceToHost,
+                           c.stream));
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    if (*P.info != 0) fail(TNT_E_HIP, "eigensolver did not converge in a sector");
+  }
+}
+
+void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs) {
+  std::vector<EigProb> probs;
+  for (SvdJob* jp : jobs) {
+    SvdJob& J = *jp;
+    for (Sector& s : J.secs) {
+      s.lv.clear();
+      s.nres = 0;
+      s.lv.reserve(kMaxLevels);  // levels are referenced by address while refining
+      s.lv.emplace_back();
+      Level& L0 = s.lv[0];
+      L0.n = s.n;
+      L0.U = J.z.as<double>() + 2 * s.gbase;
+      L0.w = J.ev.as<double>() + s.ebase;
+      EigProb P;
+      P.z = J.z.as<double>();
+      P.w = J.ev.as<double>();
+      P.zoff = s.gbase;
+      P.woff = s.ebase;
+      P.n = s.n;
+      P.info = &L0.info;
+      const double* g = J.gram.as<double>();
+      const int64_t gsize = J.gsize, gb = s.gbase, nn = (int64_t)s.n * s.n;
+      double* zz = J.z.as<double>();
+      const int conj = J.right ? 0 : 1;
+      hipStream_t st = c.stream;
+      P.rebuild = [=]() { launch_interleave(g + gb, g + gsize + gb, zz + 2 * gb, nn, conj, st); };
+      probs.push_back(std::move(P));
+    }
+  }
+  eig_batch(c, probs);
+}
+
+namespace {
+// Squared column norms of a level's Z, read back with its eigenvalues.
+struct NormReads {
+  std::vector<ZNormTask> tasks;
+  std::vector<std::pair<Level*, int>> dst;  // (level, first column) per run of columns
+  std::vector<std::pair<Level*, int64_t>> mu;  // eigenvalues to read
+  void add(Level& L, int nother) {
+    dst.push_back({&L, (int)tasks.size()});
+    for (int i = 0; i < L.n; ++i) tasks.push_back(ZNormTask{L.Z + 2 * (int64_t)i * nother, nullptr, nother});
+    mu.push_back({&L, 0});
+  }
+  void run(Ctx& c) {
+    if (tasks.empty()) return;
+    DevBuf out(&c.pool, tasks.size() * sizeof(double));
+    for (size_t i = 0; i < tasks.size(); ++i) tasks[i].out = out.as<double>() + i;
+    DevBuf tab(&c.pool, tasks.size() * sizeof(ZNormTask));
+    TNT_HIP(hipMemcpyAsync(tab.ptr, tasks.data(), tasks.size() * sizeof(ZNormTask),
+                           hipMemcpyHostToDevice, c.stream));
+    launch_znorm2(tab.as<ZNormTask>(), (int)tasks.size(), c.stream);
+    std::vector<double> h(tasks.size());
+    TNT_HIP(hipMemcpyAsync(h.data(), out.ptr, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c.stream));
+    for (auto& m : mu) {
+      m.first->mu.resize(m.first->n);
+      TNT_HIP(hipMemcpyAsync(m.first->mu.data(), m.first->w, m.first->n * sizeof(double),
+                             hipMemcpyDeviceToHost, c.stream));
+    }
+    TNT_HIP(hipStreamSynchronize(c.stream));
+    for (auto& d : dst) {
+      Level& L = *d.first;
+      L.s2.assign(h.begin() + d.second, h.begin() + d.second + L.n);
+    }
+  }
+};
+
+// After a level's eigenvalues and column norms are known: split off its
+// cluster, or close the sector.
+void classify(Sector& s, int level) {
+  Level& L = s.lv[level];
+  const int n = L.n;
+  for (double v : L.mu)
+    if (!std::isfinite(v)) fail(TNT_E_NONFINITE, "non-finite Gram eigenvalue (theta not finite?)");
+  for (double v : L.s2)
+    if (!std::isfinite(v)) fail(TNT_E_NONFINITE, "non-finite singular value (theta not finite?)");
+  const double mumax = n > 0 ? std::max(0.0, L.mu[n - 1]) : 0.0;
+  if (level == 0) s.sigma0 = std::sqrt(mumax);
+  int clus = 0;
+  if (mumax > 0)
+    while (clus < n && L.mu[clus] < kTau * mumax) ++clus;
+  L.clus = clus;
+  L.fro2 = 0;
+  for (int i = 0; i < clus; ++i) L.fro2 += L.s2[i];
+  // the cluster's eigenvalues lie below tau mu_max up to the rounding band
+  L.bound = clus ? std::sqrt((kTau + 8.0 * kEps) * mumax) : 0.0;
+  // the projection itself carries ~eps sigma_0 per singular value; a cluster
+  // at that level is noise and is taken as it stands
+  const double noise = 8.0 * kEps * std::sqrt((double)std::max(s.n, s.nother)) * s.sigma0;
+  if (clus && (L.bound <= noise || level + 1 >= kMaxLevels || mumax <= 0)) {
+    L.clus = 0;
+    L.fro2 = 0;
+    L.bound = 0;
+    s.noise = true;
+  }
+  s.open = L.clus > 0;
+}
+
+// The sector's resolved values (all levels so far), descending; a level's
+// values never exceed the smallest resolved value of the level above it.
+void collect(Sector& s) {
+  s.vals.clear();
+  double cap = std::numeric_limits<double>::infinity();
+  for (int l = 0; l < (int)s.lv.size(); ++l) {
+    const Level& L = s.lv[l];
+    std::vector<Sector::Val> v;
+    for (int i = L.clus; i < L.n; ++i)
+      v.push_back({std::min(cap, std::sqrt(std::max(0.0, L.s2[i]))), l, i});
+    std::stable_sort(v.begin(), v.end(), [](const Sector::Val& a, const Sector::Val& b) {
+      if (a.lam != b.lam) return a.lam > b.lam;
+      return a.idx > b.idx;
+    });
+    for (auto& x : v) s.vals.push_back(x);
+    if (!v.empty()) cap = v.back().lam;
+  }
+  // at most min(R, C) singular values per sector
+  const int K = std::min(s.R, s.C);
+  if ((int)s.vals.size() > K) s.vals.resize(K);
+}
+
+// Whether a value no larger than U is surely discarded, whatever the
+// unresolved values are: chi_max resolved values lie above it, or the
+// absolute or relative rule cuts above it.  r: resolved values, descending.
+bool surely_cut(const std::vector<double>& r, double U, const tnt_trunc_params& p) {
+  int cnt = 0;
+  while (cnt < (int)r.size() && r[cnt] > U) ++cnt;
+  if (cnt >= p.chi_max) return true;
+  if (p.abs_tol > 0 && p.abs_tol > U) return true;
+  if (p.rel_tol > 0 && !r.empty() && p.rel_tol * r[0] > U) return true;
+  return false;
+}
+
+// Whether the truncation rules are decided with the sectors' unresolved
+// clusters all discarded (every active rule would need a value above the
+// clusters' bound to keep one of them).
+bool decided(const std::vector<Sector>& secs, const tnt_trunc_params& p, double* extra) {
+  double U = 0, f = 0;
+  bool any = false;
+  std::vector<double> r;
+  for (const Sector& s : secs) {
+    for (auto& v : s.vals) r.push_back(v.lam);
+    if (s.open) {
+      any = true;
+      U = std::max(U, s.lv.back().bound);
+      f += s.lv.back().fro2;
+    }
+  }
+  *extra = f;
+  if (!any) return true;
+  std::sort(r.begin(), r.end(), std::greater<double>());
+  if (surely_cut(r, U, p)) return true;
+  if (p.err_tol > 0) {
+    // the error rule cuts above every cluster when the tail after the
+    // resolved values above U (with the clusters' exact sums) is below e
+    if (p.err_type == TNT_ERR_1NORM) return false;
+    int cnt = 0;
+    while (cnt < (int)r.size() && r[cnt] > U) ++cnt;
+    double t = f;
+    for (size_t i = cnt; i < r.size(); ++i) t += r[i] * r[i];
+    const double err = p.err_type == TNT_ERR_SUMSQ ? t : std::sqrt(t);
+    return err < p.err_tol;
+  }
+  // without the error rule each cluster may be judged by its own bound
+  for (const Sector& s : secs)
+    if (s.open && !surely_cut(r, s.lv.back().bound, p)) return false;
+  return true;
+}
+}  // namespace
+
+void svd_refine(Ctx& c, const std::vector<SvdJob*>& jobs,
+                const std::vector<tnt_trunc_params>& params) {
+  if (params.size() != jobs.size()) fail(TNT_E_ARG, "one truncation rule set per theta");
+  // --- level 0: Z = B^+ with B = U^+ Y, from theta's blocks ------------------
+  NormReads nr;
+  for (SvdJob* jp : jobs) {
+    SvdJob& J = *jp;
+    const ThetaH& th = J.th;
+    const bool right = J.right;
+    J.levels = 1;
+    J.zb = DevBuf(&c.pool, std::max<int64_t>(1, 2 * J.zsize) * sizeof(double));
+    // eigenvectors into split planes, row-major: RIGHT U[r][i], LEFT Vt[i][c]
+    DevBuf up(&c.pool, std::max<int64_t>(1, 2 * J.gsize) * sizeof(double));
+    DevBuf bp(&c.pool, std::max<int64_t>(1, 2 * J.zsize) * sizeof(double));
+    std::vector<ScatterTask> st;
+    int mr = 1, mc = 1;
+    HostGemm gb;
+    for (Sector& s : J.secs) {
+      if (right) st.push_back(ScatterTask{s.gbase, 1, s.n, s.gbase, s.n, s.n, 0, 0});
+      else st.push_back(ScatterTask{s.gbase, s.n, 1, s.gbase, s.n, s.n, 0, 0});
+      mr = std::max(mr, s.n);
+      mc = std::max(mc, s.n);
+      if (right) {
+        // B[i, (s2, b)] = sum_r conj(U[r, i]) X[r, (s2, b)]   (n x C, ld C)
+        for (size_t j = 0; j < s.cols.size(); ++j) {
+          const int s2 = s.cols[j].first;
+          gb.add_task(s.zbase + s.coff[j], s.n, th.right.at(s.cols[j].second), s.C);
+          for (size_t i = 0; i < s.rows.size(); ++i) {
+            auto tb = th.blocks.find({s.rows[i].second, s.rows[i].first, s2});
+            if (tb == th.blocks.end()) continue;
+            gb.add_seg(s.gbase + (int64_t)s.roff[i] * s.n, s.n, tb->second.off, tb->second.cols,
+                       tb->second.rows);
+          }
+        }
+      } else {
+        // P[i, (s1, a)] = sum_c V[c, i] X[(s1, a), c] = conj(B[i, (s1, a)])   (n x R, ld R)
+        for (size_t i = 0; i < s.rows.size(); ++i) {
+          gb.add_task(s.zbase + s.roff[i], s.n, th.left.at(s.rows[i].second), s.R);
+          for (size_t j = 0; j < s.cols.size(); ++j) {
+            auto tb = th.blocks.find({s.rows[i].second, s.rows[i].first, s.cols[j].first});
+            if (tb == th.blocks.end()) continue;
+            gb.add_seg(s.gbase + s.coff[j], s.n, tb->second.off, tb->second.cols,
+                       tb->second.cols);
+          }
+        }
+      }
+    }
+    DevBuf stab(&c.pool, st.size() * sizeof(ScatterTask));
+    TNT_HIP(hipMemcpyAsync(stab.ptr, st.data(), st.size() * sizeof(ScatterTask),
+                           hipMemcpyHostToDevice, c.stream));
+    launch_scatter_z(stab.as<ScatterTask>(), (int)st.size(), mr, mc, J.z.as<double>(),
+                     up.as<double>(), up.as<double>() + J.gsize, c.stream);
+    gb.finalize(default_tile_cfg(gb, PATH_F64));
+    DevTables tb;
+    tb.upload(c, {&gb}, {});
+    double* u = up.as<double>();
+    double* b = bp.as<double>();
+    run_gemm(c, tb.g[0], right ? FORM_CN : FORM_NT, PATH_F64, u, u + J.gsize, ET_F64, J.re,
+             J.im, ET_F64, b, b + J.zsize, ET_F64);
+    // RIGHT: B row-major (n x C) read column-major with conj = B^+ (C x n);
+    // LEFT: P row-major (n x R) read column-major = P^T = B^+ (R x n)
+    launch_interleave(b, b + J.zsize, J.zb.as<double>(), J.zsize, right ? 1 : 0, c.stream);
+    for (Sector& s : J.secs) {
+      Level& L0 = s.lv[0];
+      L0.Z = J.zb.as<double>() + 2 * s.zbase;
+      nr.add(L0, s.nother);
+    }
+    // the host tables and temporaries must outlive the launches
+    TNT_HIP(hipStreamSynchronize(c.stream));
+  }
+  nr.run(c);
+  for (size_t q = 0; q < jobs.size(); ++q) {
+    SvdJob& J = *jobs[q];
+    J.open = false;
+    for (Sector& s : J.secs) {
+      s.noise = false;
+      classify(s, 0);
+      collect(s);
+    }
+    J.open = !decided(J.secs, params[q], &J.extra_tail);
+  }
+  // --- levels 1, 2, ...: the clusters' Gram matrices --------------------------
+  rocblas_handle h = blas(c);
+  for (int level = 1; level < kMaxLevels; ++level) {
+    // refine the open sectors whose cluster may still hold a kept value; a
+    // cluster every rule discards stays unresolved (its exact sum of squares
+    // enters the truncation error)
+    std::vector<std::pair<SvdJob*, Sector*>> act;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      SvdJob* J = jobs[q];
+      if (!J->open) continue;
+      std::vector<double> r;
+      for (const Sector& s : J->secs)
+        for (auto& v : s.vals) r.push_back(v.lam);
+      std::sort(r.begin(), r.end(), std::greater<double>());
+      const bool err_rule = params[q].err_tol > 0;
+      for (Sector& s : J->secs)
+        if (s.open && (err_rule || !surely_cut(r, s.lv.back().bound, params[q])))
+          act.push_back({J, &s});
+    }
+    if (act.empty()) break;
+    // the previous level's resolved rows join the sector's resolved set, and
+    // its cluster rows are orthogonalised against the whole set (twice)
+    {
+      std::vector<ZCopyTask> cp;
+      int64_t cpmax = 1;
+      for (auto& a : act) {
+        Sector& s = *a.second;
+        const Level& P = s.lv[level - 1];
+        if (!s.vres.ptr)
+          s.vres = DevBuf(&c.pool, std::max<size_t>(1, (size_t)2 * s.nother * s.n) * sizeof(double));
+        for (int i = P.clus; i < P.n; ++i) {
+          if (s.nres >= s.n) fail(TNT_E_STATE, "SVD resolved set exceeds the sector order");
+          const double nrm = std::sqrt(P.s2[i]);
+          cp.push_back(ZCopyTask{P.Z + 2 * (int64_t)i * s.nother,
+                                 s.vres.as<double>() + 2 * (int64_t)s.nres * s.nother, s.nother,
+                                 nrm > 0 ? 1.0 / nrm : 0.0});
+          cpmax = std::max<int64_t>(cpmax, s.nother);
+          ++s.nres;
+        }
+      }
+      DevBuf tab(&c.pool, std::max<size_t>(1, cp.size()) * sizeof(ZCopyTask));
+      if (!cp.empty()) {
+        TNT_HIP(hipMemcpyAsync(tab.ptr, cp.data(), cp.size() * sizeof(ZCopyTask),
+                               hipMemcpyHostToDevice, c.stream));
+        launch_zcopy(tab.as<ZCopyTask>(), (int)cp.size(), cpmax, c.stream);
+      }
+      size_t tmax = 1;
+      for (auto& a : act) {
+        const Sector& s = *a.second;
+        tmax = std::max(tmax, (size_t)s.nres * s.lv[level - 1].clus);
+      }
+      DevBuf t(&c.pool, 2 * tmax * sizeof(double));
+      for (auto& a : act) {
+        Sector& s = *a.second;
+        Level& P = s.lv[level - 1];
+        const double* V = s.vres.as<double>();
+        for (int pass = 0; pass < 2; ++pass) {
+          // T = V^+ Z_c ; Z_c -= V T
+          zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, s.nres, P.clus,
+                s.nother, V, s.nother, P.Z, s.nother, t.as<double>(), s.nres);
+          zgemm(h, rocblas_operation_none, rocblas_operation_none, s.nother, P.clus, s.nres, V,
+                s.nother, t.as<double>(), s.nres, P.Z, s.nother, -1.0, 1.0);
+        }
+      }
+      // the copies' host table must outlive the launch
+      TNT_HIP(hipStreamSynchronize(c.stream));
+    }
+    std::vector<EigProb> probs;
+    probs.reserve(act.size());
+    for (auto& a : act) {
+      Sector& s = *a.second;
+      if ((int)s.lv.size() != level) fail(TNT_E_STATE, "SVD level bookkeeping");
+      s.lv.emplace_back();  // capacity reserved: no reallocation
+      const Level& P = s.lv[level - 1];
+      const int n = P.clus, no = s.nother, ng = s.n;
+      Level& L = s.lv.back();
+      L.n = n;
+      const int64_t uz = (int64_t)n * n, zz = (int64_t)no * n, qz = level >= 2 ? (int64_t)ng * n : 0;
+      L.buf = DevBuf(&c.pool, (size_t)(2 * (uz + zz + qz) + n) * sizeof(double));
+      L.U = L.buf.as<double>();
+      L.Z = L.U + 2 * uz;
+      L.w = L.Z + 2 * zz + 2 * qz;
+      if (level == 1) {
+        L.Q = s.lv[0].U;  // the first n columns of level 0's eigenvectors
+      } else {
+        double* Q = L.Z + 2 * zz;
+        zgemm(h, rocblas_operation_none, rocblas_operation_none, ng, n, P.n, P.Q, ng, P.U, P.n,
+              Q, ng);
+        L.Q = Q;
+      }
+      // G = Z_c^+ Z_c  (the cluster rows' Gram matrix)
+      const double* Zc = P.Z;
+      double* U = L.U;
+      auto build = [=]() {
+        zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, n, n, no, Zc, no,
+              Zc, no, U, n);
+      };
+      build();
+      EigProb E;
+      E.z = L.U;
+      E.w = L.w;
+      E.n = n;
+      E.info = &L.info;
+      E.rebuild = build;
+      probs.push_back(std::move(E));
+    }
+    eig_batch(c, probs);
+    NormReads lr;
+    for (auto& a : act) {
+      Sector& s = *a.second;
+      Level& P = s.lv[level - 1];
+      Level& L = s.lv[level];
+      // Z_L = Z_c U_L
+      zgemm(h, rocblas_operation_none, rocblas_operation_none, s.nother, L.n, L.n, P.Z, s.nother,
+            L.U, L.n, L.Z, s.nother);
+      lr.add(L, s.nother);
+    }
+    lr.run(c);
+    for (auto& a : act) {
+      classify(*a.second, level);
+      collect(*a.second);
+    }
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      SvdJob& J = *jobs[q];
+      if (!J.open) continue;
+      J.levels = level + 1;
+      J.open = !decided(J.secs, params[q], &J.extra_tail);
+    }
+  }
+  for (SvdJob* J : jobs) {
+    // whatever is still open after the last level is taken as resolved noise
+    if (!J->open) continue;
+    for (Sector& s : J->secs) {
+      if (!s.open) continue;
+      s.lv.back().clus = 0;
+      s.lv.back().fro2 = 0;
+      s.open = false;
+      collect(s);
+    }
+    J->open = false;
+    J->extra_tail = 0;
   }
 }
 
@@ -439,68 +927,61 @@ SvdOut svd_finish(Ctx& c, SvdJob& J, const tnt_trunc_params& p, const FactorAllo
   const double* im = J.im;
   const bool right = J.right;
   std::vector<Sector>& secs = J.secs;
-  const int64_t gsize = J.gsize;
-  const int esize = J.esize;
-  DevBuf& z = J.z;
-  DevBuf& info = J.info;
-  double* g = J.gram.as<double>();
-  double* W = J.ev.as<double>();
   rocblas_handle h = blas(c);
-  std::vector<double> mu(esize);
-  std::vector<rocblas_int>& hinfo = J.hinfo;
-  TNT_HIP(hipMemcpyAsync(mu.data(), W, esize * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-  TNT_HIP(hipStreamSynchronize(c.stream));
-  // divide and conquer can fail on large clusters of (near-)zero eigenvalues;
-  // redo such a sector with the Jacobi eigensolver from the kept Gram planes
-  for (size_t i = 0; i < secs.size(); ++i) {
-    if (hinfo[i] == 0) continue;
-    const Sector& s = secs[i];
-    DevBuf rj(&c.pool, 64);
-    auto* A = reinterpret_cast<rocblas_double_complex*>(z.as<double>()) + s.gbase;
-    launch_interleave(g + s.gbase, g + gsize + s.gbase, z.as<double>() + 2 * s.gbase,
-                      (int64_t)s.n * s.n, right ? 0 : 1, c.stream);
-    if (rocsolver_zheevj(h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper,
-                         s.n, A, s.n, 0.0, rj.as<double>(), 100, rj.as<rocblas_int>() + 4,
-                         W + s.ebase, info.as<rocblas_int>() + i) != rocblas_status_success)
-      fail(TNT_E_HIP, "rocsolver_zheevj failed");
-    TNT_HIP(hipMemcpyAsync(mu.data() + s.ebase, W + s.ebase, s.n * sizeof(double),
-                           hipMemcpyDeviceToHost, c.stream));
-    TNT_HIP(hipMemcpyAsync(&hinfo[i], info.as<rocblas_int>() + i, sizeof(rocblas_int),
-                           hipMemcpyDeviceToHost, c.stream));
-    TNT_HIP(hipStreamSynchronize(c.stream));
-    if (hinfo[i] != 0) fail(TNT_E_HIP, "eigensolver did not converge in a sector");
-  }
-  double mumax = 0;
-  int nmax = 1;
-  for (double v : mu) {
-    if (!std::isfinite(v)) fail(TNT_E_NONFINITE, "non-finite Gram eigenvalue (theta not finite?)");
-    mumax = std::max(mumax, v);
-  }
-  for (auto& s : secs) nmax = std::max(nmax, s.n);
-  if (!(mumax > 0)) fail(TNT_E_NONFINITE, "theta has zero norm");
-  const double floor = 4.0 * 2.220446049250313e-16 * nmax * mumax;
-  // pool (lambda desc, then sector asc, then index asc), select
-  struct Ent { double lam; int sec, idx; };
+  // pool (lambda desc, then sector asc, then in-sector position asc), select
+  struct Ent { double lam; int sec, pos; };
   std::vector<Ent> pool;
-  pool.reserve(esize);
   for (size_t i = 0; i < secs.size(); ++i) {
-    const Sector& s = secs[i];
-    const int K = std::min(s.R, s.C);  // rank bound: at most K nonzero singular values
-    for (int k = 0; k < K; ++k) {
-      const double m = mu[s.ebase + s.n - 1 - k];  // descending
-      pool.push_back({m > floor ? std::sqrt(m) : 0.0, (int)i, k});
-    }
+    secs[i].kept = 0;
+    for (size_t k = 0; k < secs[i].vals.size(); ++k)
+      pool.push_back({secs[i].vals[k].lam, (int)i, (int)k});
   }
+  if (pool.empty()) fail(TNT_E_NONFINITE, "theta has zero norm");
   std::stable_sort(pool.begin(), pool.end(), [](const Ent& a, const Ent& b) {
     if (a.lam != b.lam) return a.lam > b.lam;
     if (a.sec != b.sec) return a.sec < b.sec;
-    return a.idx < b.idx;
+    return a.pos < b.pos;
   });
+  if (!(pool[0].lam > 0)) fail(TNT_E_NONFINITE, "theta has zero norm");
   std::vector<double> sorted(pool.size());
   for (size_t i = 0; i < pool.size(); ++i) sorted[i] = pool[i].lam;
   SvdOut out;
+  out.levels = J.levels;
+  // the unresolved clusters are discarded: their exact sum of squares joins
+  // every tail of the error rule and the reported error
+  const double extra = J.extra_tail;
+  int chi;
   double eps = 0;
-  const int chi = trunc_select(sorted.data(), (int)sorted.size(), p, &eps);
+  if (extra > 0) {
+    tnt_trunc_params q = p;
+    if (q.err_tol > 0) {
+      // error rule with the clusters in every tail
+      const int n = (int)sorted.size();
+      int best = n;
+      for (int k = n; k >= 0; --k) {
+        double t = extra;
+        for (int i = k; i < n; ++i) t += sorted[i] * sorted[i];
+        const double e = q.err_type == TNT_ERR_SUMSQ ? t : std::sqrt(t);
+        if (e < q.err_tol) best = k;
+        else break;
+      }
+      q.err_tol = -1;
+      chi = std::min(trunc_select(sorted.data(), n, q, nullptr), std::max(best, 1));
+    } else {
+      chi = trunc_select(sorted.data(), (int)sorted.size(), q, nullptr);
+    }
+    double t = extra;
+    for (size_t i = chi; i < sorted.size(); ++i) t += sorted[i] * sorted[i];
+    if (p.err_type == TNT_ERR_1NORM) {
+      double s1 = std::sqrt(extra);  // a lower bound: the clusters' values are not resolved
+      for (size_t i = chi; i < sorted.size(); ++i) s1 += sorted[i];
+      eps = s1;
+    } else {
+      eps = p.err_type == TNT_ERR_SUMSQ ? t : std::sqrt(t);
+    }
+  } else {
+    chi = trunc_select(sorted.data(), (int)sorted.size(), p, &eps);
+  }
   double nk = 0;
   for (int i = 0; i < chi; ++i) {
     nk += sorted[i] * sorted[i];
@@ -509,16 +990,13 @@ SvdOut svd_finish(Ctx& c, SvdJob& J, const tnt_trunc_params& p, const FactorAllo
   nk = std::sqrt(nk);
   out.chi = chi;
   out.eps = eps;
-  out.lambda0 = sorted.empty() ? 0 : sorted[0];
+  out.lambda0 = sorted[0];
   out.norm_kept = nk;
   const double scale = p.renormalise && nk > 0 ? 1.0 / nk : 1.0;
   for (auto& s : secs) {
     if (s.kept == 0) continue;
     out.bond[s.m] = s.kept;
-    for (int k = 0; k < s.kept; ++k) {
-      const double m = mu[s.ebase + s.n - 1 - k];
-      out.lam.push_back((m > floor ? std::sqrt(m) : 0.0) * scale);
-    }
+    for (int k = 0; k < s.kept; ++k) out.lam.push_back(s.vals[k].lam * scale);
   }
   // factor layouts: A blocks (q_a, s1) ascending, B blocks (m, s2) ascending
   {
@@ -542,8 +1020,63 @@ SvdOut svd_finish(Ctx& c, SvdJob& J, const tnt_trunc_params& p, const FactorAllo
     out.B.elems = off;
   }
   const FactorPlanes fp = alloc(out);
+  // --- kept isometric vectors: uk (n x kept per sector, column-major) -----------
+  int64_t uksize = 0;
+  for (auto& s : secs) {
+    s.ukbase = uksize;
+    uksize += (int64_t)s.n * s.kept;
+  }
+  DevBuf uk(&c.pool, std::max<int64_t>(1, 2 * uksize) * sizeof(double));
+  double* ukp = uk.as<double>();
+  // level-0 vectors are copied; deeper levels' are Q_L T with T the kept
+  // columns of U_L (gathered into tmp first)
+  std::vector<ZCopyTask> cp;
+  int64_t cpmax = 1;
+  struct Prod { const Sector* s; int level, pos, cnt; int64_t toff; };
+  std::vector<Prod> prods;
+  int64_t tsz = 0;
+  for (auto& s : secs) {
+    int k = 0;
+    while (k < s.kept) {
+      const int l = s.vals[k].level;
+      int e = k;
+      while (e < s.kept && s.vals[e].level == l) ++e;
+      if (l == 0) {
+        for (int q = k; q < e; ++q) {
+          cp.push_back(ZCopyTask{s.lv[0].U + 2 * (int64_t)s.vals[q].idx * s.n,
+                                 ukp + 2 * (s.ukbase + (int64_t)q * s.n), s.n, 1.0});
+          cpmax = std::max<int64_t>(cpmax, s.n);
+        }
+      } else {
+        prods.push_back({&s, l, k, e - k, tsz});
+        tsz += (int64_t)s.lv[l].n * (e - k);
+      }
+      k = e;
+    }
+  }
+  DevBuf tprod(&c.pool, std::max<int64_t>(1, 2 * tsz) * sizeof(double));
+  for (auto& pr : prods) {
+    const Level& L = pr.s->lv[pr.level];
+    for (int q = 0; q < pr.cnt; ++q) {
+      cp.push_back(ZCopyTask{L.U + 2 * (int64_t)pr.s->vals[pr.pos + q].idx * L.n,
+                             tprod.as<double>() + 2 * (pr.toff + (int64_t)q * L.n), L.n, 1.0});
+      cpmax = std::max<int64_t>(cpmax, L.n);
+    }
+  }
+  DevBuf cptab(&c.pool, std::max<size_t>(1, cp.size()) * sizeof(ZCopyTask));
+  if (!cp.empty()) {
+    TNT_HIP(hipMemcpyAsync(cptab.ptr, cp.data(), cp.size() * sizeof(ZCopyTask),
+                           hipMemcpyHostToDevice, c.stream));
+    launch_zcopy(cptab.as<ZCopyTask>(), (int)cp.size(), cpmax, c.stream);
+  }
+  for (auto& pr : prods) {
+    const Sector& s = *pr.s;
+    const Level& L = s.lv[pr.level];
+    zgemm(h, rocblas_operation_none, rocblas_operation_none, s.n, pr.cnt, L.n, L.Q, s.n,
+          tprod.as<double>() + 2 * pr.toff, L.n, ukp + 2 * (s.ukbase + (int64_t)pr.pos * s.n),
+          s.n);
+  }
   // --- factors -----------------------------------------------------------
-  const double* zz = z.as<double>();
   std::vector<ScatterTask> st;
   int mr = 1, mc = 1;
   auto add_st = [&](int64_t src, int64_t rs, int64_t cs, int64_t dst, int rows, int cols,
@@ -556,13 +1089,12 @@ SvdOut svd_finish(Ctx& c, SvdJob& J, const tnt_trunc_params& p, const FactorAllo
   DevBuf tmp;
   int64_t tsize = 0;
   if (right) {
-    // A(q_a, s1)[r, c] = eigvec(roff + r, n - 1 - c)
+    // A(q_a, s1)[r, c] = uk(roff + r, c)
     for (auto& s : secs) {
       if (s.kept == 0) continue;
       for (size_t i = 0; i < s.rows.size(); ++i) {
         const BlockRef& b = out.A.blocks.at({s.rows[i].second, s.rows[i].first});
-        add_st(s.gbase + s.roff[i] + (int64_t)(s.n - 1) * s.n, 1, -(int64_t)s.n, b.off, b.rows,
-               b.cols, 0);
+        add_st(s.ukbase + s.roff[i], 1, s.n, b.off, b.rows, b.cols, 0);
       }
       // B(m, s2) = sum_{s1} A(q_a, s1)^+ theta(q_a, s1, s2)
       for (size_t j = 0; j < s.cols.size(); ++j) {
@@ -578,25 +1110,23 @@ SvdOut svd_finish(Ctx& c, SvdJob& J, const tnt_trunc_params& p, const FactorAllo
       }
     }
   } else {
-    // the interleave conjugated the row-major X^+ X back into G = X^+ X, so the
-    // eigenvectors are the columns of V:  B(m, s2)[r, c] = conj(V(coff + c, n - 1 - r))
+    // the vectors are the columns of V:  B(m, s2)[r, c] = conj(V(coff + c, r))
     for (auto& s : secs) {
       if (s.kept == 0) continue;
       s.tbase = tsize;
       tsize += (int64_t)s.C * s.kept;
       for (size_t j = 0; j < s.cols.size(); ++j) {
         const BlockRef& b = out.B.blocks.at({s.m, s.cols[j].first});
-        add_st(s.gbase + s.coff[j] + (int64_t)(s.n - 1) * s.n, -(int64_t)s.n, 1, b.off, b.rows,
-               b.cols, 1);
+        add_st(s.ukbase + s.coff[j], s.n, 1, b.off, b.rows, b.cols, 1);
       }
     }
   }
   const size_t nfac = st.size();
   if (!right) {
-    // V_kept row-major (C x kept): V_kept(r, c) = V(r, n - 1 - c)
+    // V_kept row-major (C x kept): V_kept(r, c) = uk(r, c)
     for (auto& s : secs) {
       if (s.kept == 0) continue;
-      add_st(s.gbase + (int64_t)(s.n - 1) * s.n, 1, -(int64_t)s.n, s.tbase, s.C, s.kept, 0);
+      add_st(s.ukbase, 1, s.n, s.tbase, s.C, s.kept, 0);
       // A(q_a, s1) = sum_{s2} theta(q_a, s1, s2) V_kept[(s2, b) rows]
       for (auto& rr : s.rows) {
         const BlockRef& ab = out.A.blocks.at({rr.second, rr.first});
@@ -623,15 +1153,15 @@ SvdOut svd_finish(Ctx& c, SvdJob& J, const tnt_trunc_params& p, const FactorAllo
   double* centre;
   int64_t centre_n;
   if (right) {
-    launch_scatter_z(sdev, (int)nfac, mr, mc, zz, fp.a_re, fp.a_im, c.stream);
+    launch_scatter_z(sdev, (int)nfac, mr, mc, ukp, fp.a_re, fp.a_im, c.stream);
     run_gemm(c, tp.g[0], FORM_CN, PATH_F64, fp.a_re, fp.a_im, ET_F64, re, im, ET_F64, fp.b_re,
              fp.b_im, ET_F64);
     centre = fp.b_re;
     centre_n = out.B.elems;
   } else {
     double* t = tmp.as<double>();
-    launch_scatter_z(sdev, (int)nfac, mr, mc, zz, fp.b_re, fp.b_im, c.stream);
-    launch_scatter_z(sdev + nfac, (int)(st.size() - nfac), mr, mc, zz, t, t + tsize, c.stream);
+    launch_scatter_z(sdev, (int)nfac, mr, mc, ukp, fp.b_re, fp.b_im, c.stream);
+    launch_scatter_z(sdev + nfac, (int)(st.size() - nfac), mr, mc, ukp, t, t + tsize, c.stream);
     run_gemm(c, tp.g[0], FORM_NN, PATH_F64, re, im, ET_F64, t, t + tsize, ET_F64, fp.a_re,
              fp.a_im, ET_F64);
     centre = fp.a_re;
@@ -663,7 +1193,9 @@ SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double
                         const tnt_trunc_params& p, int absorb, const FactorAlloc& alloc) {
   if (p.chi_max < 1) fail(TNT_E_ARG, "chi_max must be >= 1");
   auto job = svd_begin(c, th, re, im, absorb);
-  svd_eig(c, {job.get()});
+  SvdJob* jp = job.get();
+  svd_eig(c, {jp});
+  svd_refine(c, {jp}, {p});
   return svd_finish(c, *job, p, alloc);
 }
 

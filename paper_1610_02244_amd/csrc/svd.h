@@ -23,6 +23,7 @@ struct SvdOut {
   std::vector<double> lam;   // kept singular values, sectors ascending (renormalised)
   int chi = 0;
   double eps = 0, lambda0 = 0, norm_kept = 0;
+  int levels = 1;            // deflation levels used to resolve the spectrum
 };
 
 // Output planes for the factors, provided once the kept bond is known.
@@ -45,15 +46,22 @@ double trunc_error(const double* lam, int n, int kind);
 SvdOut svd_truncate_dev(Ctx& c, const ThetaH& th, const double* re, const double* im,
                         const tnt_trunc_params& p, int absorb, const FactorAlloc& alloc);
 
-// The same in three phases, so that the eigendecompositions of several
-// thetas share batched calls: svd_begin launches the sector Gram matrices of
-// one theta (its planes must stay valid until svd_finish), svd_eig
-// decomposes every sector of every job and returns when done, svd_finish
-// selects the kept values and writes the factors.
+// The same in phases, so that the eigendecompositions of several thetas
+// share batched calls: svd_begin launches the sector Gram matrices of one
+// theta (its planes must stay valid until svd_finish), svd_eig decomposes
+// every sector of every job, svd_refine resolves the small singular values
+// by deflation (levels of smaller eigenproblems, batched across the jobs;
+// job i is cut with p[i]), svd_finish selects the kept values and writes
+// the factors.
 struct SvdJob;
 std::shared_ptr<SvdJob> svd_begin(Ctx& c, const ThetaH& th, const double* re, const double* im,
                                   int absorb);
 void svd_eig(Ctx& c, const std::vector<SvdJob*>& jobs);
+void svd_refine(Ctx& c, const std::vector<SvdJob*>& jobs,
+                const std::vector<tnt_trunc_params>& p);
 SvdOut svd_finish(Ctx& c, SvdJob& job, const tnt_trunc_params& p, const FactorAlloc& alloc);
+
+// Deflation levels the last svd_refine used for a job (1 = no refinement).
+int svd_levels(const SvdJob& job);
 
 }  // namespace tnt

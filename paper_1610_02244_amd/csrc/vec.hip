@@ -231,6 +231,39 @@ void launch_scatter_z(const ScatterTask* t, int ntask, int maxrows, int maxcols,
   hipLaunchKernelGGL(scatter_z_kernel, grid, dim3(64), 0, s, t, src_z, re, im);
 }
 
+__global__ void zcopy_kernel(const ZCopyTask* __restrict__ tasks) {
+  const ZCopyTask t = tasks[blockIdx.y];
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < 2 * t.n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    t.dst[k] = t.scale * t.src[k];
+}
+
+void launch_zcopy(const ZCopyTask* t, int ntask, int64_t max_n, hipStream_t s) {
+  if (ntask <= 0 || max_n <= 0) return;
+  const int64_t gx = (2 * max_n + 255) / 256;
+  hipLaunchKernelGGL(zcopy_kernel, dim3((unsigned)(gx < 64 ? gx : 64), ntask), dim3(256), 0, s,
+                     t);
+}
+
+__global__ __launch_bounds__(256) void znorm2_kernel(const ZNormTask* __restrict__ tasks) {
+  const ZNormTask t = tasks[blockIdx.x];
+  __shared__ double part[256];
+  double acc = 0;
+  for (int64_t k = threadIdx.x; k < 2 * t.n; k += 256) acc += t.src[k] * t.src[k];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *t.out = part[0];
+}
+
+void launch_znorm2(const ZNormTask* t, int ntask, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(znorm2_kernel, dim3(ntask), dim3(256), 0, s, t);
+}
+
 __global__ void interleave_kernel(const double* __restrict__ re, const double* __restrict__ im,
                                   double* __restrict__ z, int64_t n, int conj) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
@@ -250,9 +283,12 @@ void launch_interleave(const double* re, const double* im, double* z, int64_t n,
 // padded Hermitian batches
 //
 // A sector's n x n Gram matrix G goes into an npad x npad slot as
-// M = Q A Q with A = diag(G, D), D = -s diag(1 + j/m) (m = npad - n,
+// M = Q A Q / s with A = diag(G, D), D = -s diag(1 + j/m) (m = npad - n,
 // s = trace G, or 1 if that is zero) and Q = I - 2 u u^T / (u^T u) for a
-// fixed irregular positive u.  A alone would make the tridiagonal reduction
+// fixed irregular positive u.  Dividing by s puts every slot at unit scale:
+// the library's eigensolver uses absolute tolerances (its eigenvalue errors
+// grow to ~1e-8 |G| for |G| ~ 1e-9), and the deflated SVD decomposes Gram
+// matrices of any scale.  The eigenvalues are multiplied back by s.  A alone would make the tridiagonal reduction
 // split exactly at the block boundary and at every padding row, and the
 // divide-and-conquer solver returns non-finite vectors for such splits; Q
 // mixes the blocks so M has no exact split while sharing A's spectrum.  D's
@@ -321,6 +357,8 @@ __global__ __launch_bounds__(256) void pad_embed_kernel(const PadTask* __restric
   p0 = block_sum_all(p0, sh, &bc);
   p1 = block_sum_all(p1, sh, &bc);
   const double sc = tr > 0 ? tr : 1.0;
+  const double inv = 1.0 / sc;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *t.scale = sc;
   const double rm = m > 0 ? 1.0 / m : 0.0;
   // beta = u^T A u; d_i = -sc (1 + (i - n) / m) on the padding rows
   const double beta = bg - sc * (p0 + p1 * rm);
@@ -354,8 +392,8 @@ __global__ __launch_bounds__(256) void pad_embed_kernel(const PadTask* __restric
       wci = 0;
     }
     // M = A - f1 (u w^H + w u^T) + f2 u u^T
-    dst[2 * (t.dst_off + e)] = ar - f1 * (ur * wcr + wrr * uc) + f2 * ur * uc;
-    dst[2 * (t.dst_off + e) + 1] = ai - f1 * (-ur * wci + wri * uc);
+    dst[2 * (t.dst_off + e)] = inv * (ar - f1 * (ur * wcr + wrr * uc) + f2 * ur * uc);
+    dst[2 * (t.dst_off + e) + 1] = inv * (ai - f1 * (-ur * wci + wri * uc));
   }
 }
 
@@ -396,7 +434,7 @@ __global__ __launch_bounds__(256) void pad_extract_kernel(const PadTask* __restr
     out[2 * r] = v[2 * r] - f * u * rr;
     out[2 * r + 1] = v[2 * r + 1] - f * u * ri;
   }
-  if (threadIdx.x == 0) t.w[t.w_dst + c] = slot_w[t.w_src + sft + c];
+  if (threadIdx.x == 0) t.w[t.w_dst + c] = *t.scale * slot_w[t.w_src + sft + c];
 }
 
 void launch_pad_extract(const PadTask* t, int ntask, int max_n, const double* slot_z,

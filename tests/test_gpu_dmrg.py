@@ -52,14 +52,11 @@ def test_sweep_fp64_matches_oracle(tnt, case):
         rel = np.max(np.abs(e - er) / np.abs(er))
         print(f"  sweep {k + 1}: E {e[-1]:.15f} oracle {er[-1]:.15f} max|dE/E| {rel:.2e}")
         assert rel <= 1e-10
-        if case == "cfg1":
-            # chi-limited cut: the kept set is decided far above rounding level
-            assert list(r["bond_chi"]) == ref["chi"]
-        else:
-            # exact chi: Schmidt values under the FP64 Gram floor (~3e-7 lambda_0)
-            # are dropped on the GPU; the oracle keeps values down to 1e-12
-            assert all(a <= b for a, b in zip(r["bond_chi"], ref["chi"]))
-            assert max(r["bond_eps"]) < 1e-6
+        # kept dims at every bond, also at exact chi (cfg1_exact: the relative
+        # cut 1e-12 decides, 81 at the middle bond)
+        assert list(r["bond_chi"]) == ref["chi"]
+        # truncation errors to the FP64 backward error of the SVD
+        np.testing.assert_allclose(r["bond_eps"], ref["eps"], rtol=1e-6, atol=1e-13)
 
 
 def test_sweep_cfg1_exact_reaches_ed(tnt):
@@ -136,3 +133,28 @@ def test_sweep_cfg2_converged(tnt, precision):
     print(f"  E {e:.15f} oracle {er:.15f} |dE/E| {rel_last:.2e} "
           f"sweep {res[-1]['seconds_total']:.2f}s")
     assert rel_last <= 1e-9
+    # the last (converged) sweep bond by bond: energies, kept dims, errors
+    eb = np.array(res[-1]["bond_E"])
+    ebr = np.array(g["sweeps"][-1]["E"])
+    rel = np.max(np.abs(eb - ebr) / np.abs(ebr))
+    print(f"  last sweep max|dE/E| over bonds {rel:.2e}")
+    assert rel <= 1e-9
+    got_chi, ref_chi = list(res[-1]["bond_chi"]), g["sweeps"][-1]["chi"]
+    diff = [(b, int(x), y, float(e), f) for b, (x, y, e, f) in
+            enumerate(zip(got_chi, ref_chi, res[-1]["bond_eps"], g["sweeps"][-1]["eps"]))
+            if x != y]
+    print(f"  kept-dim differences (bond, gpu, oracle, eps gpu, eps oracle): {diff}")
+    if precision == "fp64":
+        assert got_chi == ref_chi
+        np.testing.assert_allclose(res[-1]["bond_eps"], g["sweeps"][-1]["eps"], rtol=1e-3,
+                                   atol=1e-10)
+    else:
+        # A ground vector from reduced-precision matvecs carries rounding noise
+        # (~1e-9 lambda_0 for FP32, ~1e-8 for BF16x3) in directions where the
+        # FP64 state has exactly nothing; at bonds the oracle does not fill
+        # (its 1e-12 relative cut keeps fewer than chi_max states) that noise
+        # is kept as extra states.  Where the oracle fills chi_max the kept
+        # dims must agree; elsewhere the GPU keeps at least the oracle's states.
+        chi_max = g["chi"]
+        for x, y in zip(got_chi, ref_chi):
+            assert (x == y) if y == chi_max else (x >= y)
