@@ -49,6 +49,11 @@ extern "C" tnt_status tnt_heff1_apply(tnt_ctx ctx, const tnt_btensor* L, const t
                                       const tnt_btensor* out) {
   TNT_API_BEGIN(ctx)
   if (!L || !W || !R || !A || !out) fail(TNT_E_ARG, "null argument");
+  // every operand is read (and out written) as FP64 planes
+  for (const tnt_btensor* t : {L, R, A, out}) {
+    if (t->dtype != TNT_DT_F64) fail(TNT_E_ARG, "L, R, A and out must be FP64 planes");
+    if (!t->re || !t->im) fail(TNT_E_ARG, "null plane");
+  }
   const MpoH w = parse_mpo(W, "W");
   const EnvH le = parse_env(L, w, "L");
   const EnvH re = parse_env(R, w, "R");

@@ -60,3 +60,26 @@ def test_heff1_rejects_mismatched_output(tnt):
     with pytest.raises(B.TntError) as ei:
         tnt.heff1_apply(tnt.env(Lenv, qg), mpo, tnt.env(Renv, qg), Ad, tnt.site(A2))
     assert ei.value.code == -2  # TNT_E_SHAPE
+
+
+def test_heff1_rejects_non_fp64_or_null_planes(tnt):
+    """Environments described as FP32 (or with a missing plane) are refused
+    before anything runs: the contraction reads FP64 planes only."""
+    from paper_1610_02244_amd import binding as B
+    W, qw, d, Lenv, Renv, A = site_inputs(6, 4, 2, 9, 3, 1)
+    Wg, qg = tnt.bose_hubbard_mpo(2, 1.0, 2.5, 0.3)
+    mpo = B.Mpo(Wg, qg)
+    Ad, od = tnt.site(A), tnt.site(A)
+    for which in ("L", "R"):
+        Ld, Rd = tnt.env(Lenv, qg), tnt.env(Renv, qg)
+        (Ld if which == "L" else Rd).c.dtype = B.TNT_DT_F32
+        with pytest.raises(B.TntError) as ei:
+            tnt.heff1_apply(Ld, mpo, Rd, Ad, od)
+        assert ei.value.code == -1  # TNT_E_ARG
+    Ld, Rd = tnt.env(Lenv, qg), tnt.env(Renv, qg)
+    Rd.c.im = None
+    with pytest.raises(B.TntError) as ei:
+        tnt.heff1_apply(Ld, mpo, Rd, Ad, od)
+    assert ei.value.code == -1
+    # the context stays usable
+    tnt.heff1_apply(tnt.env(Lenv, qg), mpo, tnt.env(Renv, qg), Ad, od)
