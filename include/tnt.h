@@ -195,6 +195,24 @@ tnt_status tnt_heff2_apply(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_site
                            const tnt_mpo_site* W2, const tnt_btensor* R,
                            const tnt_btensor* theta, tnt_btensor* out, int32_t precision);
 
+/* tnt_heff2_apply for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation).
+ * Same operands, result and errors as tnt_heff2_apply; the operator's task
+ * tables, intermediate slabs and packed operand copies are placed in one
+ * device array of 64 MiB that the library holds on each GPU it runs on until
+ * the process ends, so the call makes no device allocation (no hipMalloc,
+ * hipFree or allocating library routine).  Operators whose tables and
+ * workspaces exceed 64 MiB are refused with TNT_E_CAPACITY before anything
+ * is launched (an FP64 two-site operator of a chi = 256 chain needs about
+ * 25 MB).  Every call on one GPU reuses that GPU's array: calls that overlap
+ * on one GPU (from two contexts or threads) race and give undefined results.
+ * The plan is built on the host at every call, with default tile shapes (no
+ * timing launches).  Synchronises the context's stream before returning. */
+tnt_status tnt_heff2_apply_noalloc(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_site* W1,
+                                   const tnt_mpo_site* W2, const tnt_btensor* R,
+                                   const tnt_btensor* theta, tnt_btensor* out,
+                                   int32_t precision);
+
 /* n independent applications (arrays of n operands, each with the meaning
  * of tnt_heff2_apply: different chains, bonds and block structures) packed
  * into one grouped launch per contraction step.  Inputs are gathered into a

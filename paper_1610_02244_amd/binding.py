@@ -99,6 +99,9 @@ SIGNATURES = {
     "tnt_heff2_apply": (C.c_int32, [P, C.POINTER(BTensor), C.POINTER(MpoSite),
                                     C.POINTER(MpoSite), C.POINTER(BTensor),
                                     C.POINTER(BTensor), C.POINTER(BTensor), C.c_int32]),
+    "tnt_heff2_apply_noalloc": (C.c_int32, [P, C.POINTER(BTensor), C.POINTER(MpoSite),
+                                    C.POINTER(MpoSite), C.POINTER(BTensor),
+                                    C.POINTER(BTensor), C.POINTER(BTensor), C.c_int32]),
     "tnt_heff2_flops": (C.c_int64, [C.POINTER(BTensor), C.POINTER(MpoSite), C.POINTER(MpoSite),
                                     C.POINTER(BTensor), C.POINTER(BTensor), I64P]),
     "tnt_lanczos_ground": (C.c_int32, [P, C.POINTER(BTensor), C.POINTER(MpoSite),
@@ -411,6 +414,12 @@ class Tnt:
         code = self.lib.tnt_heff2_apply(self.ctx, L.ref, W1.ref, W2.ref, R.ref, theta.ref,
                                         out.ref, PRECISIONS[precision])
         return self._check("tnt_heff2_apply", code)
+
+    def heff2_apply_noalloc(self, L, W1, W2, R, theta, out, precision="fp64"):
+        """tnt_heff2_apply through the allocation-free entry point (blocks)."""
+        code = self.lib.tnt_heff2_apply_noalloc(self.ctx, L.ref, W1.ref, W2.ref, R.ref,
+                                                theta.ref, out.ref, PRECISIONS[precision])
+        return self._check("tnt_heff2_apply_noalloc", code)
 
     def heff2_flops(self, L, W1, W2, R, theta):
         parts = np.zeros(3, dtype=np.int64)

@@ -386,6 +386,12 @@ tnt_status tnt_ctx_create(int32_t device, void* hip_stream, tnt_ctx* out) {
       delete c;
       return TNT_E_HIP;
     }
+  try {
+    c->scratch = scratch_address(device);
+  } catch (const Error& e) {
+    delete c;
+    return e.code;
+  }
   *out = reinterpret_cast<tnt_ctx>(c);
   return TNT_OK;
 }

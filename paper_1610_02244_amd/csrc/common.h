@@ -111,8 +111,14 @@ struct Ctx {
   hipStream_t side[kSide] = {};
   void* side_blas[kSide] = {};
   hipEvent_t side_ev[kSide + 1] = {};
+  // this device's copy of the allocation-free path's scratch array
+  void* scratch = nullptr;
   ~Ctx();
 };
+
+// Device address of the scratch array on `device` (which must be current).
+void* scratch_address(int device);
+size_t scratch_bytes();
 
 // Pinned host staging for small device->host reads (Lanczos scalars).
 struct HostStage {

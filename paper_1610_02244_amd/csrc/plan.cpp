@@ -165,10 +165,39 @@ int default_tile_cfg(const HostGemm& h, GemmPath path) {
 // ---------------------------------------------------------------------------
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+size_t DevTables::image_bytes(const std::vector<const HostGemm*>& gs,
+                              const std::vector<const HostComb*>& cs,
+                              const std::vector<const HostCombP*>& cps,
+                              const std::vector<const HostPack*>& pks) {
+  size_t total = 0;
+  auto add = [&](size_t bytes) { total = align256(total + bytes); };
+  for (auto* h : gs) {
+    add(h->tasks.size() * sizeof(GemmTask));
+    add(h->segs.size() * sizeof(GemmSeg));
+    add(h->tiles.size() * sizeof(int2));
+    for (auto& vt : h->var_tiles) add(vt.size() * sizeof(int2));
+  }
+  for (auto* h : cs) {
+    add(h->tasks.size() * sizeof(CombTask));
+    add(h->terms.size() * sizeof(CombTerm));
+    add(h->chunks.size() * sizeof(int2));
+  }
+  for (auto* h : cps) {
+    add(h->tasks.size() * sizeof(CombPTask));
+    add(h->terms.size() * sizeof(CombTerm));
+    add(h->chunks.size() * sizeof(int2));
+  }
+  for (auto* h : pks) {
+    add(h->tasks.size() * sizeof(PackTask));
+    add(h->tiles.size() * sizeof(int2));
+  }
+  return std::max<size_t>(total, 256);
+}
+
 void DevTables::upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
                        const std::vector<const HostComb*>& cs,
                        const std::vector<const HostCombP*>& cps,
-                       const std::vector<const HostPack*>& pks) {
+                       const std::vector<const HostPack*>& pks, void* dst) {
   size_t total = 0;
   auto add = [&](size_t bytes) { size_t o = total; total = align256(total + bytes); return o; };
   struct GO { size_t t, s, l; std::vector<size_t> v; };
@@ -222,9 +251,15 @@ void DevTables::upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
     put(po[i].t, pks[i]->tasks.data(), pks[i]->tasks.size() * sizeof(PackTask));
     put(po[i].l, pks[i]->tiles.data(), pks[i]->tiles.size() * sizeof(int2));
   }
-  buf = DevBuf(&ctx.pool, total);
-  TNT_HIP(hipMemcpyAsync(buf.ptr, host.data(), total, hipMemcpyHostToDevice, ctx.stream));
-  char* base = buf.as<char>();
+  char* base;
+  if (dst) {
+    buf.reset();
+    base = static_cast<char*>(dst);
+  } else {
+    buf = DevBuf(&ctx.pool, total);
+    base = buf.as<char>();
+  }
+  TNT_HIP(hipMemcpyAsync(base, host.data(), total, hipMemcpyHostToDevice, ctx.stream));
   g.clear();
   c.clear();
   cp.clear();
@@ -621,6 +656,43 @@ void HeffOp::build(Ctx& c, const EnvH& L, const MpoH& W1, const MpoH& W2, const 
 }
 
 void HeffOp::build_plan(Ctx& c, HeffPlan&& p, int prec, bool tunable) {
+  plan_tables(c, std::move(p), prec, tunable);
+  upload_tables(nullptr);
+}
+
+size_t HeffOp::table_bytes() const {
+  if (plan.packed)
+    return DevTables::image_bytes({&plan.step1, &plan.step4, &plan.step1p, &plan.step4p},
+                                  {&plan.mpo}, {&plan.mpop}, {&plan.Lp, &plan.Rp, &plan.Xp});
+  return DevTables::image_bytes({&plan.step1, &plan.step4}, {&plan.mpo});
+}
+
+void HeffOp::upload_tables(void* dst) {
+  Ctx& c = *ctx;
+  if (plan.packed)
+    tab.upload(c, {&plan.step1, &plan.step4, &plan.step1p, &plan.step4p}, {&plan.mpo},
+               {&plan.mpop}, {&plan.Lp, &plan.Rp, &plan.Xp}, dst);
+  else
+    tab.upload(c, {&plan.step1, &plan.step4}, {&plan.mpo}, {}, {}, dst);
+}
+
+void HeffOp::ws_bytes(int prec, int64_t out[5]) const {
+  for (int i = 0; i < 5; ++i) out[i] = 0;
+  if (prec == TNT_FP64 || !plan.packed) {
+    out[0] = std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(double);
+    out[1] = std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(double);
+    return;
+  }
+  const PackFmt f = fmt();
+  const int64_t pb = (int64_t)pack_planes(f) * pack_elem_bytes(f);
+  out[0] = std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(float);
+  out[1] = std::max<int64_t>(16, plan.t3p_elems * pb);
+  out[2] = std::max<int64_t>(16, plan.Lp.elems * pb);
+  out[3] = std::max<int64_t>(16, plan.Rp.elems * pb);
+  out[4] = std::max<int64_t>(16, plan.Xp.elems * pb);
+}
+
+void HeffOp::plan_tables(Ctx& c, HeffPlan&& p, int prec, bool tunable) {
   ctx = &c;
   precision = prec;
   const bool packed = prec != TNT_FP64;
@@ -675,12 +747,14 @@ void HeffOp::build_plan(Ctx& c, HeffPlan&& p, int prec, bool tunable) {
   }
   bool tune = false;
   for (const Job& j : jobs) tune = tune || j.tune;
-  if (packed)
-    tab.upload(c, {&plan.step1, &plan.step4, &plan.step1p, &plan.step4p}, {&plan.mpo},
-               {&plan.mpop}, {&plan.Lp, &plan.Rp, &plan.Xp});
-  else
-    tab.upload(c, {&plan.step1, &plan.step4}, {&plan.mpo});
   tuned = !tune;
+}
+
+void* HeffOp::wsp(int i) const { return ext_ws[i] ? ext_ws[i] : ctx->ws[i].ptr; }
+
+void HeffOp::ensure_ws(int i, int64_t bytes) {
+  if (ext_ws[i]) return;  // sized by the caller (ws_bytes)
+  ctx->ws[i].ensure(&ctx->pool, bytes);
 }
 
 void HeffOp::bind_envs(const void* lre, const void* lim, const void* rre, const void* rim) {
@@ -690,20 +764,20 @@ void HeffOp::bind_envs(const void* lre, const void* lim, const void* rre, const 
   if (!plan.packed) return;
   const PackFmt f = fmt();
   const int64_t pb = (int64_t)pack_planes(f) * pack_elem_bytes(f);
-  c.ws[2].ensure(&c.pool, std::max<int64_t>(16, plan.Lp.elems * pb));
-  c.ws[3].ensure(&c.pool, std::max<int64_t>(16, plan.Rp.elems * pb));
+  ensure_ws(2, std::max<int64_t>(16, plan.Lp.elems * pb));
+  ensure_ws(3, std::max<int64_t>(16, plan.Rp.elems * pb));
   const DevTables::P& lp = tab.p[0];
   const DevTables::P& rp = tab.p[1];
-  launch_pack(lp.tasks, lp.tiles, lp.ntiles, L_re, L_im, c.ws[2].ptr, lp.elems, f, c.stream);
-  launch_pack(rp.tasks, rp.tiles, rp.ntiles, R_re, R_im, c.ws[3].ptr, rp.elems, f, c.stream);
+  launch_pack(lp.tasks, lp.tiles, lp.ntiles, L_re, L_im, wsp(2), lp.elems, f, c.stream);
+  launch_pack(rp.tasks, rp.tiles, rp.ntiles, R_re, R_im, wsp(3), rp.elems, f, c.stream);
 }
 
 void HeffOp::launch_step(int step, int v, bool fp64, const double* xre, const double* xim,
                          double* yre, double* yim) {
   Ctx& c = *ctx;
   if (fp64) {
-    double* a = c.ws[0].as<double>();
-    double* b = c.ws[1].as<double>();
+    double* a = static_cast<double*>(wsp(0));
+    double* b = static_cast<double*>(wsp(1));
     if (step == 1)
       run_gemm_variant(c, tab.g[0], v, FORM_NN, PATH_F64, L_re, L_im, ET_F64, xre, xim, ET_F64,
                        a, a + plan.t1_elems, ET_F64);
@@ -715,7 +789,7 @@ void HeffOp::launch_step(int step, int v, bool fp64, const double* xre, const do
   // packed path: step 1 Lp . Xp^T -> FP32 T1 slabs; step 4 T3p . Rp^T -> y
   const DevTables::G& g = tab.g[step == 1 ? 2 : 3];
   if (v < 0 || v >= g.nvar) fail(TNT_E_STATE, "tile-table variant out of range");
-  float* t1 = c.ws[0].as<float>();
+  float* t1 = static_cast<float*>(wsp(0));
   PackedLaunch L{};
   L.tasks = g.tasks;
   L.segs = g.segs;
@@ -724,12 +798,12 @@ void HeffOp::launch_step(int step, int v, bool fp64, const double* xre, const do
   L.tile_cfg = g.cfg[v];
   L.fmt = fmt();
   if (step == 1) {
-    L.a = c.ws[2].ptr; L.a_plane = plan.Lp.elems;
-    L.b = c.ws[4].ptr; L.b_plane = plan.Xp.elems;
+    L.a = wsp(2); L.a_plane = plan.Lp.elems;
+    L.b = wsp(4); L.b_plane = plan.Xp.elems;
     L.c_re = t1; L.c_im = t1 + plan.t1_elems; L.c_t = ET_F32;
   } else {
-    L.a = c.ws[1].ptr; L.a_plane = plan.t3p_elems;
-    L.b = c.ws[3].ptr; L.b_plane = plan.Rp.elems;
+    L.a = wsp(1); L.a_plane = plan.t3p_elems;
+    L.b = wsp(3); L.b_plane = plan.Rp.elems;
     L.c_re = yre; L.c_im = yim; L.c_t = ET_F64;
   }
   if (!launch_packed_gemm(L, c.stream))
@@ -744,19 +818,19 @@ HeffOp::~HeffOp() {
 void HeffOp::prepare(const double* xre, const double* xim, double* yre, double* yim, int prec) {
   Ctx& c = *ctx;
   if (prec == TNT_FP64 || !plan.packed) {
-    c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(double));
-    c.ws[1].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(double));
+    ensure_ws(0, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(double));
+    ensure_ws(1, std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(double));
     if (!tuned && !plan.packed) autotune(xre, xim, yre, yim, prec);
     return;
   }
   const PackFmt f = fmt();
   const int64_t pb = (int64_t)pack_planes(f) * pack_elem_bytes(f);
-  c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(float));
-  c.ws[1].ensure(&c.pool, std::max<int64_t>(16, plan.t3p_elems * pb));
-  c.ws[4].ensure(&c.pool, std::max<int64_t>(16, plan.Xp.elems * pb));
+  ensure_ws(0, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(float));
+  ensure_ws(1, std::max<int64_t>(16, plan.t3p_elems * pb));
+  ensure_ws(4, std::max<int64_t>(16, plan.Xp.elems * pb));
   if (!tuned) {
     const DevTables::P& xp = tab.p[2];
-    launch_pack(xp.tasks, xp.tiles, xp.ntiles, xre, xim, c.ws[4].ptr, xp.elems, f, c.stream);
+    launch_pack(xp.tasks, xp.tiles, xp.ntiles, xre, xim, wsp(4), xp.elems, f, c.stream);
     autotune(xre, xim, yre, yim, prec);
   }
 }
@@ -770,15 +844,15 @@ void HeffOp::apply(const double* xre, const double* xim, double* yre, double* yi
   // FP64: the FP64 operator, or the refinement matvec of a reduced-precision
   // operator (on the FP64 environments)
   if (prec == TNT_FP64 || !plan.packed) {
-    c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(double));
-    c.ws[1].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(double));
+    ensure_ws(0, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(double));
+    ensure_ws(1, std::max<int64_t>(1, 2 * plan.t3_elems) * sizeof(double));
     if (!tuned && !plan.packed) autotune(xre, xim, yre, yim, prec);
     const int v1 = valid_variant(tab.g[0], PATH_F64), v4 = valid_variant(tab.g[1], PATH_F64);
     mark(2);
     launch_step(1, v1, true, xre, xim, yre, yim);
     mark(3);
-    run_comb(c, tab.c[0], c.ws[0].as<double>(), c.ws[0].as<double>() + plan.t1_elems,
-             c.ws[1].as<double>(), c.ws[1].as<double>() + plan.t3_elems, ET_F64);
+    run_comb(c, tab.c[0], static_cast<double*>(wsp(0)), static_cast<double*>(wsp(0)) + plan.t1_elems,
+             static_cast<double*>(wsp(1)), static_cast<double*>(wsp(1)) + plan.t3_elems, ET_F64);
     mark(4);
     launch_step(4, v4, true, xre, xim, yre, yim);
     mark(5);
@@ -786,18 +860,18 @@ void HeffOp::apply(const double* xre, const double* xim, double* yre, double* yi
   }
   const PackFmt f = fmt();
   const int64_t pb = (int64_t)pack_planes(f) * pack_elem_bytes(f);
-  c.ws[0].ensure(&c.pool, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(float));
-  c.ws[1].ensure(&c.pool, std::max<int64_t>(16, plan.t3p_elems * pb));
-  c.ws[4].ensure(&c.pool, std::max<int64_t>(16, plan.Xp.elems * pb));
+  ensure_ws(0, std::max<int64_t>(1, 2 * plan.t1_elems) * sizeof(float));
+  ensure_ws(1, std::max<int64_t>(16, plan.t3p_elems * pb));
+  ensure_ws(4, std::max<int64_t>(16, plan.Xp.elems * pb));
   const DevTables::P& xp = tab.p[2];
-  launch_pack(xp.tasks, xp.tiles, xp.ntiles, xre, xim, c.ws[4].ptr, xp.elems, f, c.stream);
+  launch_pack(xp.tasks, xp.tiles, xp.ntiles, xre, xim, wsp(4), xp.elems, f, c.stream);
   if (!tuned) autotune(xre, xim, yre, yim, prec);
   const DevTables::CP& cp = tab.cp[0];
   mark(2);
   launch_step(1, tab.g[2].sel, false, xre, xim, yre, yim);
   mark(3);
-  launch_combine_packed(cp.tasks, cp.terms, cp.chunks, cp.nchunks, c.ws[0].as<float>(),
-                        c.ws[0].as<float>() + plan.t1_elems, c.ws[1].ptr, plan.t3p_elems, f,
+  launch_combine_packed(cp.tasks, cp.terms, cp.chunks, cp.nchunks, static_cast<float*>(wsp(0)),
+                        static_cast<float*>(wsp(0)) + plan.t1_elems, wsp(1), plan.t3p_elems, f,
                         c.stream);
   mark(4);
   launch_step(4, tab.g[3].sel, false, xre, xim, yre, yim);

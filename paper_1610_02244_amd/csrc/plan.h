@@ -106,10 +106,17 @@ struct DevTables {
   std::vector<C> c;
   std::vector<CP> cp;
   std::vector<P> p;
+  // Copy the lists to the device: into pool memory, or to `dst` (at least
+  // image_bytes of the same lists) when given.
   void upload(Ctx& ctx, const std::vector<const HostGemm*>& gs,
               const std::vector<const HostComb*>& cs,
               const std::vector<const HostCombP*>& cps = {},
-              const std::vector<const HostPack*>& pks = {});
+              const std::vector<const HostPack*>& pks = {}, void* dst = nullptr);
+  // Device bytes the lists occupy (256-byte aligned pieces).
+  static size_t image_bytes(const std::vector<const HostGemm*>& gs,
+                            const std::vector<const HostComb*>& cs,
+                            const std::vector<const HostCombP*>& cps = {},
+                            const std::vector<const HostPack*>& pks = {});
 };
 
 void run_gemm(Ctx& ctx, const DevTables::G& g, GemmForm form, GemmPath path,
@@ -186,6 +193,17 @@ struct HeffOp {
   // tunable: time the tile-shape candidates at the first application when
   // the shape bucket has no cached decision (off for one-off operators)
   void build_plan(Ctx& c, HeffPlan&& p, int prec, bool tunable = true);
+  // build_plan in two parts: the tile tables on the host, then their copy
+  // to the device (pool memory, or `dst` with table_bytes() bytes)
+  void plan_tables(Ctx& c, HeffPlan&& p, int prec, bool tunable);
+  size_t table_bytes() const;
+  void upload_tables(void* dst);
+  // Caller-provided workspaces (ws[0..4] roles, see above), used instead of
+  // the context's when set; ws_bytes() gives the sizes an application needs.
+  void* ext_ws[5] = {};
+  void ws_bytes(int prec, int64_t out[5]) const;
+  void* wsp(int i) const;
+  void ensure_ws(int i, int64_t bytes);
   // point at the environments' FP64 planes (and refresh the packed copies)
   void bind_envs(const void* lre, const void* lim, const void* rre, const void* rim);
   PackFmt fmt() const { return precision == TNT_BF16X3 ? PK_BF16X3 : PK_F32; }
