@@ -7,15 +7,17 @@ update) of a Bose-Hubbard chain, on device-resident state.  The headline
 `value` is the H_eff matvec throughput of the whole timed sweeps:
 algorithmic flops of every matvec the sweeps performed / timed wall time.
 
-Default workload: L = 32, N = 32, nmax = 4 (d = 5), J = 1, U = 4, chi = 256
-(seeded random MPS), matvecs on FP32 MFMA; Krylov vectors, SVD, energies and
-environments in FP64.  Also reported: the same sweeps on the FP64 and the
-BF16x3 GPU paths, single-matvec rates at the middle bond of this chain and
-of the chi = 1024 chain (L = 64), the energy errors against the oracle's
-stored sweep energies, the grouped-GEMM roofline figure and the CPU oracle
-timed on a bounded sample.
+Default workload: the chi = 1024 chain, L = 64, N = 64, nmax = 4 (d = 5),
+J = 1, U = 3.3 (seeded random MPS, seed 3), matvecs on FP32 MFMA; Krylov
+vectors, SVD, energies and environments in FP64.  The energy after sweep k
+(k = the number of sweeps the oracle's stored run has) is compared with the
+oracle's.  Also reported: two sweeps each on the FP64 and the BF16x3 GPU
+paths from the same initial state, single-matvec rates at the middle bond,
+the 64-chain batch, the grouped-GEMM roofline figure and the CPU oracle
+(block matvec single-threaded and on all cores, plus its sweep time from the
+stored run).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg3]
 """
 from __future__ import annotations
 
@@ -78,10 +80,18 @@ class Roctx:
 TIMED_RANGE = "tnt_bench_timed"
 
 
-def run_sweeps(tnt, torch, mps, env, spec, precision, warmup, steps, roctx=None):
+def run_sweeps(tnt, torch, mps, env, spec, precision, warmup, steps, roctx=None, energies=None,
+               stats=None):
+    """W untimed then K timed sweeps; `energies` (a list) gets every sweep's
+    final energy and `stats` every sweep's result, warm-up sweeps included,
+    in order."""
     kw = dict(kmax=spec.lanczos_steps, precision=precision, rel_tol=spec.rel_cutoff)
     for i in range(warmup):
         r = tnt.sweep(mps, env, spec.chi, **kw)
+        if energies is not None:
+            energies.append(r["energy"])
+        if stats is not None:
+            stats.append(r)
         log(f"  warmup sweep {i + 1} [{precision}]: E = {r['energy']:.12f} ({r['seconds_total']:.2f}s)")
     torch.cuda.synchronize()
     if roctx:
@@ -93,6 +103,10 @@ def run_sweeps(tnt, torch, mps, env, spec, precision, warmup, steps, roctx=None)
     if roctx:
         roctx.pop()
     for i, r in enumerate(res):
+        if energies is not None:
+            energies.append(r["energy"])
+        if stats is not None:
+            stats.append(r)
         log(f"  timed sweep {i + 1} [{precision}]: E = {r['energy']:.12f} ({r['seconds_total']:.2f}s)")
     return res, dt
 
@@ -437,9 +451,21 @@ def batched_rates(tnt, B, torch, precision="fp32", reps=10):
             "lanczos_matvec_tflops_graph": 21 * flops / t_graph / 1e12}
 
 
-def cpu_baseline(spec, budget_s=12.0):
-    """The oracle's block H_eff at the middle bond, repeated for ~budget_s seconds."""
-    import numpy as np
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def cpu_baseline(spec, config, budget_s=10.0):
+    """The oracle's block H_eff at the middle bond, repeated for ~budget_s
+    seconds on all of the host's BLAS threads and again single-threaded, plus
+    the oracle's sweep time at this configuration from its stored run."""
     import synth
     from oracle import flops as oflops
     from oracle import heff as oheff
@@ -447,22 +473,39 @@ def cpu_baseline(spec, budget_s=12.0):
     W, qw = model.bh_mpo(spec.nmax, spec.J, spec.U, spec.mu)
     left, right, Le, Re, th = synth.middle_bond_inputs(spec, qw)
     f = oflops.heff2_flops(left, right, spec.d, qw, W, W)["total"]
+
+    def timed(budget):
+        n, t0 = 0, time.perf_counter()
+        while True:
+            oheff.heff2_block(Le, W, W, Re, th, left, right, qw, spec.d)
+            n += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return n, time.perf_counter() - t0
+
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         cores = os.cpu_count() or 1
-    n, t0 = 0, time.perf_counter()
-    while True:
-        oheff.heff2_block(Le, W, W, Re, th, left, right, qw, spec.d)
-        n += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    _ = np
-    return {"value": f * n / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} block H_eff matvecs (oracle, complex128 NumPy) at the middle bond of "
-                      f"the same chain shape, {dt:.1f}s"}
+    n, dt = timed(budget_s)
+    out = {"value": f * n / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n} block H_eff matvecs (oracle, complex128 NumPy) at the middle bond of "
+                     f"the same chain, {dt:.1f}s, {cores} BLAS threads",
+           "cpu_model": cpu_model(), "flops_per_matvec": f}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            n1, dt1 = timed(budget_s)
+        out["single_thread"] = {"value": f * n1 / dt1 / 1e12, "matvecs": n1, "seconds": dt1}
+    g = golden(config)
+    if g is not None and g["sweeps"]:
+        walls = [s_["wall_s"] for s_ in g["sweeps"] if "wall_s" in s_]
+        if walls:
+            out["oracle_sweep_s"] = {"per_sweep": walls, "host": g.get("host"),
+                                     "note": "the oracle's own two-site sweeps (block mode) at "
+                                             "this configuration, from its stored run"}
+    return out
 
 
 def traffic_for(config, precision):
@@ -601,16 +644,33 @@ def mfma_util(root, simds=1024, xcds=8):
     return out
 
 
-def golden_energy(config, total_sweeps):
-    names = {("cfg1", 2): "cfg1", ("cfg2", 1): "cfg2", ("cfg2", 2): "cfg2_2sweeps"}
-    case = names.get((config, total_sweeps))
+GOLDEN_CASE = {"cfg1": "cfg1", "cfg2": "cfg2_4sweeps", "cfg3": "cfg3"}
+
+
+def golden(config):
+    """The oracle's stored sweeps for a configuration's default chain (None if
+    there are none): per-sweep bond energies, kept dims and errors."""
+    case = GOLDEN_CASE.get(config)
     if case is None:
         return None
     p = os.path.join(ROOT, "tests", "golden", f"sweep_{case}.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
-        return json.load(f)["sweeps"][-1]["E"][-1]
+        return json.load(f)
+
+
+def oracle_compare(config, energies):
+    """GPU energy after sweep k against the oracle's, k = the last sweep both
+    have; None without a stored oracle run."""
+    g = golden(config)
+    if g is None or not g["sweeps"] or not energies:
+        return None
+    k = min(len(g["sweeps"]), len(energies))
+    e_ref = g["sweeps"][k - 1]["E"][-1]
+    e = energies[k - 1]
+    return {"sweep": k, "gpu": e, "oracle": e_ref, "rel_err": abs(e - e_ref) / abs(e_ref),
+            "oracle_sweeps_stored": len(g["sweeps"])}
 
 
 def main():
@@ -618,7 +678,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--config", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--leg-sweeps", type=int, default=2,
+                    help="sweeps of the FP64 and BF16x3 comparison legs (from the same state)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path sweeps")
     ap.add_argument("--no-bf16x3", action="store_true", help="skip the BF16x3-path sweeps")
@@ -714,8 +776,9 @@ def main():
         f"precision={args.precision} warmup={args.warmup} steps={args.steps}")
 
     mps, env = make_chain(tnt, B, spec)
+    e_main, s_main = [], []
     res, dt = run_sweeps(tnt, torch, mps, env, spec, args.precision, args.warmup, args.steps,
-                         roctx=Roctx())
+                         roctx=Roctx(), energies=e_main, stats=s_main)
     flops = sum(r["matvec_flops"] for r in res)
     value = flops / dt / 1e12
     gemm_flops = sum(r["gemm_flops"] for r in res)
@@ -723,31 +786,40 @@ def main():
     launches = sum(r["gemm_launches"] for r in res)
     achieved = gemm_flops / gemm_s / 1e12 if gemm_s > 0 else 0.0
     e_final = res[-1]["energy"]
-    e_ref = golden_energy(args.config, args.warmup + args.steps)
+    cmp_main = oracle_compare(args.config, e_main)
+    del env, mps
+
+    def leg(precision):
+        """A short run of another matvec path from the same initial state: its
+        energies at the same sweep indices as the main run's, sweep times."""
+        m, e = make_chain(tnt, B, spec)
+        en = []
+        k = max(1, args.leg_sweeps)
+        r, t = run_sweeps(tnt, torch, m, e, spec, precision, k - 1, 1, energies=en)
+        out = {"sweeps": k, "last_sweep_s": r[-1]["seconds_total"], "energy_by_sweep": en,
+               "matvec_tflops_last_sweep": r[-1]["matvec_flops"] / t / 1e12,
+               "matvec_device_s_last_sweep": r[-1]["seconds_matvec"],
+               "seconds_svd_last_sweep": r[-1]["seconds_svd"],
+               "rel_dE_vs_main_path_same_sweep": abs(en[-1] - e_main[k - 1]) / abs(e_main[k - 1])
+               if len(e_main) >= k else None,
+               "vs_oracle": oracle_compare(args.config, en)}
+        del m, e
+        return out
 
     fp64 = None
     if not args.no_fp64 and args.precision != "fp64":
-        del env, mps
-        mps64, env64 = make_chain(tnt, B, spec)
-        r64, dt64 = run_sweeps(tnt, torch, mps64, env64, spec, "fp64", args.warmup, args.steps)
-        f64 = sum(r["matvec_flops"] for r in r64)
-        fp64 = {"sweep_s": dt64 / args.steps, "matvec_tflops": f64 / dt64 / 1e12,
-                "matvec_device_s": sum(r["seconds_matvec"] for r in r64) / args.steps,
-                "energy": r64[-1]["energy"],
-                "rel_dE_vs_fp32_path": abs(r64[-1]["energy"] - e_final) / abs(r64[-1]["energy"]),
-                "speedup_fp32_over_fp64_sweep": (dt64 / dt)}
-        del env64, mps64
-
+        fp64 = leg("fp64")
+        # against the main path's sweep of the same index (like for like)
+        k = fp64["sweeps"]
+        if k <= len(s_main):
+            m = s_main[k - 1]
+            fp64["main_path_same_sweep_s"] = m["seconds_total"]
+            fp64["speedup_main_over_fp64_sweep"] = fp64["last_sweep_s"] / m["seconds_total"]
+            fp64["speedup_main_over_fp64_matvec_device"] = (fp64["matvec_device_s_last_sweep"] /
+                                                            m["seconds_matvec"])
     bf = None
     if not args.no_bf16x3 and args.precision != "bf16x3":
-        mpsb, envb = make_chain(tnt, B, spec)
-        rb, dtb = run_sweeps(tnt, torch, mpsb, envb, spec, "bf16x3", args.warmup, args.steps)
-        fb = sum(r["matvec_flops"] for r in rb)
-        bf = {"sweep_s": dtb / args.steps, "matvec_tflops": fb / dtb / 1e12,
-              "matvec_device_s": sum(r["seconds_matvec"] for r in rb) / args.steps,
-              "energy": rb[-1]["energy"],
-              "rel_err_vs_oracle": (abs(rb[-1]["energy"] - e_ref) / abs(e_ref)) if e_ref else None}
-        del envb, mpsb
+        bf = leg("bf16x3")
 
     bt = None if args.no_batched else batched_rates(tnt, B, torch, args.precision
                                                      if args.precision != "fp64" else "fp32")
@@ -763,7 +835,7 @@ def main():
             "launches": int(launches),
             "avg_launch_s": gemm_s / launches if launches else None,
             "avg_flops_per_launch": gemm_flops / launches if launches else None}
-    cpu = None if args.no_cpu_baseline else cpu_baseline(spec)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(spec, args.config)
     per = {k: sum(r[k] for r in res) / len(res) for k in
            ("seconds_total", "seconds_matvec", "seconds_lanczos", "seconds_svd", "seconds_env",
             "seconds_theta", "seconds_setup")}
@@ -781,8 +853,10 @@ def main():
         "sweep_breakdown_s": per,
         "matvec_flops_per_sweep": flops / len(res),
         "matvec_device_tflops": flops / sum(r["seconds_matvec"] for r in res) / 1e12,
-        "energy": {"final": e_final, "oracle": e_ref,
-                   "rel_err_vs_oracle": (abs(e_final - e_ref) / abs(e_ref)) if e_ref else None,
+        "energy": {"final": e_final, "by_sweep": e_main,
+                   "oracle": cmp_main["oracle"] if cmp_main else None,
+                   "rel_err_vs_oracle": cmp_main["rel_err"] if cmp_main else None,
+                   "compared_at_sweep": cmp_main["sweep"] if cmp_main else None,
                    "max_residual": max(r["max_residual"] for r in res),
                    "max_trunc_eps": max(r["max_eps"] for r in res)},
         "fp64_path": fp64, "bf16x3_path": bf, "single_matvec_middle_bond": mv,

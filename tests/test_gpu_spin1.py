@@ -9,7 +9,8 @@ to a Kronecker-product Hamiltonian).  Bars: FP64 |dE| <= 1e-9; FP32-MFMA and
 BF16x3 matvecs |dE/E| <= 1e-9 (FP64 refinement, FP64 SVD and environments).
 At the timing-table size (L = 101, chi = 200) the checks are properties: the
 energy per bond lies at the Haldane-chain value within the open-boundary
-correction, does not rise from sweep to sweep, and the kept bonds respect chi.
+correction, does not rise from sweep to sweep, and the middle bond keeps
+exactly chi = 200 states.
 """
 import numpy as np
 import pytest
@@ -64,4 +65,8 @@ def test_spin1_timing_size_properties(tnt):
     # the two open ends change the total by O(1)
     assert -1.4015 * (L - 1) - 2.0 < e2 < -1.4015 * (L - 1) + 2.0
     assert max(res[1]["bond_chi"]) <= chi
-    assert max(res[1]["bond_chi"]) >= chi // 2
+    # the middle bonds fill chi (the Schmidt values there reach far below the
+    # relative cut 1e-12); right pass, bond L/2
+    mid = res[1]["bond_chi"][L // 2 - 1]
+    print(f"  kept chi at the middle bond {mid}, max {max(res[1]['bond_chi'])}")
+    assert mid == chi
