@@ -787,6 +787,9 @@ def main():
     achieved = gemm_flops / gemm_s / 1e12 if gemm_s > 0 else 0.0
     e_final = res[-1]["energy"]
     cmp_main = oracle_compare(args.config, e_main)
+    free_b, total_b = torch.cuda.mem_get_info()
+    mem = {"device_used_gb_after_main_run": (total_b - free_b) / 1e9,
+           "note": "whole device, includes the library's pool and torch's cache"}
     del env, mps
 
     def leg(precision):
@@ -859,6 +862,7 @@ def main():
                    "compared_at_sweep": cmp_main["sweep"] if cmp_main else None,
                    "max_residual": max(r["max_residual"] for r in res),
                    "max_trunc_eps": max(r["max_eps"] for r in res)},
+        "memory": mem,
         "fp64_path": fp64, "bf16x3_path": bf, "single_matvec_middle_bond": mv,
         "single_matvec_chi1024": mv_big, "batched_64_chains": bt,
     }

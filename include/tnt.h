@@ -376,24 +376,12 @@ tnt_status tnt_mps_get_bond(tnt_mps mps, int32_t ell, int32_t cap, int32_t* q, i
 tnt_status tnt_mps_get_site(tnt_mps mps, int32_t j, int32_t cap, int32_t* nblocks,
                             int32_t* q_left, int32_t* s, int64_t ecap, double* re, double* im);
 /* Bring the MPS to right-canonical form (sites L..2 right isometries,
- * norm carried by site 1, then site 1 scaled to unit norm), by exact
- * (untruncated) SVDs on the device. */
+ * norm carried by site 1, then site 1 scaled to unit norm), by Householder
+ * QR of each left sector's (a) x (s, b) matrix on the device (no truncation;
+ * a sector shrinks to its rank bound min(rows, cols)); every absorbed factor
+ * is rescaled to unit norm on the way, so long chains cannot overflow. */
 tnt_status tnt_mps_right_canonicalize(tnt_ctx ctx, tnt_mps mps);
 
-/* Two-point correlations of the state for every pair of sites (the outputs
- * of the ground-state example of Sec. 5, Fig. fig:ground_state_results):
- *   out[(i-1) L + (j-1)] = <psi| O^dagger_i O_j |psi> / <psi|psi>,
- * i, j = 1..L, with i = j giving <(O^dagger O)_i>.  With O = b this is the
- * single-particle density matrix rho_ij = <b^dagger_i b_j>, whose diagonal
- * is the density <n_j>.  `op` (host, d*d doubles, op[s' d + s] = <s'|O|s>,
- * real) may be nonzero only where s' - s = dq.  out_re / out_im: host,
- * L*L doubles each (the matrix is Hermitian; both triangles are filled).
- * flops (host, may be NULL) receives the pass's algorithmic flops.  Any
- * gauge of the MPS is accepted and it is left unchanged.  Runs one
- * left-to-right pass of FP64 grouped GEMMs over all open strings at once
- * and synchronises the context's stream.  Errors: TNT_E_ARG (NULL),
- * TNT_E_STATE (a site not set, zero norm), TNT_E_CHARGE (an entry of op
- * breaks dq), TNT_E_NONFINITE. */
 /* One TEBD time step (time evolution by two-site Trotter gates, Sec. 1 and
  * the example of Sec. 5, Fig. fig:time_evolve_results): with the bond
  * Hamiltonians h (host, layout of tnt_bond_hamiltonians_*; each real
@@ -440,6 +428,20 @@ tnt_status tnt_auto_block_svd(tnt_ctx ctx, const double* a_re, const double* a_i
                               double* b_im, int64_t ldb, double* S, int32_t* chi,
                               int32_t* nblocks, double* eps);
 
+/* Two-point correlations of the state for every pair of sites (the outputs
+ * of the ground-state example of Sec. 5, Fig. fig:ground_state_results):
+ *   out[(i-1) L + (j-1)] = <psi| O^dagger_i O_j |psi> / <psi|psi>,
+ * i, j = 1..L, with i = j giving <(O^dagger O)_i>.  With O = b this is the
+ * single-particle density matrix rho_ij = <b^dagger_i b_j>, whose diagonal
+ * is the density <n_j>.  `op` (host, d*d doubles, op[s' d + s] = <s'|O|s>,
+ * real) may be nonzero only where s' - s = dq.  out_re / out_im: host,
+ * L*L doubles each (the matrix is Hermitian; both triangles are filled).
+ * flops (host, may be NULL) receives the pass's algorithmic flops.  Any
+ * gauge of the MPS is accepted and it is left unchanged.  Runs one
+ * left-to-right pass of FP64 grouped GEMMs over all open strings at once
+ * and synchronises the context's stream.  Errors: TNT_E_ARG (NULL),
+ * TNT_E_STATE (a site not set, zero norm), TNT_E_CHARGE (an entry of op
+ * breaks dq), TNT_E_NONFINITE. */
 tnt_status tnt_mps_correlation(tnt_ctx ctx, tnt_mps mps, const double* op, int32_t dq,
                                double* out_re, double* out_im, double* flops);
 

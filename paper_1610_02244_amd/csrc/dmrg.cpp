@@ -389,6 +389,23 @@ void right_canonicalize(Ctx& c, MpsH& m) {
     DevBuf nb(&c.pool, std::max<int64_t>(1, 2 * An.elems) * sizeof(double));
     run_gemm(c, t.g[0], FORM_NN, PATH_F64, m.re(j - 1), m.im(j - 1), ET_F64, rp, rp + rs, ET_F64,
              nb.as<double>(), nb.as<double>() + An.elems, ET_F64);
+    // The state is defined up to its norm (normalised at the end): site j-1
+    // is scaled to unit Frobenius norm so that the norms of the R factors,
+    // ~sqrt(d chi) each, do not multiply up over the chain (a random MPS of
+    // 128 sites at chi = 2048 would overflow FP64).
+    {
+      DevBuf pn(&c.pool, RED_BLOCKS * sizeof(double) + 64);
+      double* pp = pn.as<double>();
+      launch_norm2_partial(nb.as<double>(), 2 * An.elems, pp, c.stream);
+      launch_reduce_partials(pp, 1, RED_BLOCKS, pp + RED_BLOCKS, c.stream);
+      double n2 = 0;
+      TNT_HIP(hipMemcpyAsync(&n2, pp + RED_BLOCKS, sizeof(double), hipMemcpyDeviceToHost,
+                             c.stream));
+      TNT_HIP(hipStreamSynchronize(c.stream));
+      if (!(n2 > 0) || !std::isfinite(n2))
+        fail(TNT_E_NONFINITE, "MPS norm is zero or not finite at site " + std::to_string(j - 1));
+      launch_scale_host(nb.as<double>(), 2 * An.elems, 1.0 / std::sqrt(n2), c.stream);
+    }
     TNT_HIP(hipStreamSynchronize(c.stream));
     m.lay[j - 1] = Bn;
     m.dat[j - 1] = std::move(site);
