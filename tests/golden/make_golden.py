@@ -39,7 +39,7 @@ CASES = {
 def _spec(case: str):
     if case.startswith("cfg4_chain"):
         i = int(case[len("cfg4_chain"):])
-        return "cfg4", synth.batched_specs(4)[i], 2
+        return "cfg4", synth.batched_specs(4)[i], 4
     name, chi, sweeps, U = CASES[case]
     s = synth.CONFIGS[name]
     return name, synth.ChainSpec(L=s.L, N=s.N, nmax=s.nmax, J=s.J,

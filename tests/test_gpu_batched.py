@@ -247,9 +247,9 @@ def test_many_chain_matvec_sampled_vs_oracle(tnt):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_many_chain_sweeps_vs_oracle(tnt, precision):
-    """The 64-chain workload (L 18..64, chi 64..384) swept twice in lockstep by
+    """The 64-chain workload (L 18..64, chi 64..384) swept in lockstep by
     tnt_dmrg_sweep_batched; the chains the oracle ran (one per chi class) must
-    end at the oracle's energy to 1e-9, with the oracle's kept dims wherever it
+    reach the oracle's energy at its last stored sweep to 1e-9, with the oracle's kept dims wherever it
     fills chi above the noise level of the truncation error (test_gpu_dmrg)."""
     specs = synth.batched_specs(4)
     stored = {}
@@ -264,20 +264,25 @@ def test_many_chain_sweeps_vs_oracle(tnt, precision):
         ms.append(m)
         es.append(e)
         chis.append(s.chi)
-    print(f"[64 chains lockstep {precision}] oracle chains {sorted(stored)}", flush=True)
+    nsw = max(len(g["sweeps"]) for g in stored.values())
+    print(f"[64 chains lockstep {precision}] oracle chains {sorted(stored)}, {nsw} sweeps",
+          flush=True)
     res = [tnt.sweep_batched(ms, es, chis, kmax=20, precision=precision, rel_tol=1e-12)
-           for _ in range(2)]
+           for _ in range(nsw)]
     for i, g in sorted(stored.items()):
         assert (g["L"], g["chi"], g["seed"]) == (specs[i].L, specs[i].chi, specs[i].seed)
-        e = res[-1][i]["bond_E"][-1]
+        k = len(g["sweeps"])  # each chain at the last sweep the oracle stored
+        if k < 2:
+            continue  # the first sweep from a random state is not compared
+        e = res[k - 1][i]["bond_E"][-1]
         er = g["sweeps"][-1]["E"][-1]
         rel = abs(e - er) / abs(er)
-        got, ref = list(res[-1][i]["bond_chi"]), g["sweeps"][-1]["chi"]
-        diff = [(b, x, y, res[-1][i]["bond_eps"][b], g["sweeps"][-1]["eps"][b])
+        got, ref = list(res[k - 1][i]["bond_chi"]), g["sweeps"][-1]["chi"]
+        diff = [(b, x, y, res[k - 1][i]["bond_eps"][b], g["sweeps"][-1]["eps"][b])
                 for b, (x, y) in enumerate(zip(got, ref)) if x != y]
         print(f"  chain {i} (L {g['L']}, chi {g['chi']}, U {g['U']:.2f}): E {e:.12f} oracle "
               f"{er:.12f} |dE/E| {rel:.2e}; kept dims differ at {len(diff)} bonds: "
               f"(bond, gpu, oracle, eps gpu, eps oracle) {diff[:8]}", flush=True)
         assert rel <= 1e-9
-        check_kept(got, res[-1][i]["bond_eps"], ref, g["sweeps"][-1]["eps"], g["chi"],
+        check_kept(got, res[k - 1][i]["bond_eps"], ref, g["sweeps"][-1]["eps"], g["chi"],
                    precision)

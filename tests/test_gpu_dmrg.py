@@ -32,13 +32,22 @@ EPS_NOISE = {"fp64": 1e-10, "fp32": 1e-9, "bf16x3": 1e-7}
 
 def check_kept(got_chi, got_eps, ref_chi, ref_eps, chi_max, precision):
     """Kept dims equal wherever the oracle fills chi_max with a truncation error
-    above the noise level; truncation errors within that level elsewhere."""
+    above the noise level.  Truncation errors are compared for magnitude only
+    (within a factor 10 above ten times the noise level, within ten times the
+    level below it): the first sweep from a random state is far from
+    converged, GPU and oracle leave it ~1e-3 apart in the state (2e-6 in the
+    energy at chi = 1024, both FP64), and after the second sweep runs whose
+    energies agree to 1e-11 still differ in the discarded tail by up to a
+    factor 5 (measured).  Their exact parity is checked on converged
+    sweeps (the chi = 256 chain) and on given thetas (the SVD tests)."""
     noise = EPS_NOISE[precision]
     for b, (x, y, ex, ey) in enumerate(zip(got_chi, ref_chi, got_eps, ref_eps)):
         if y == chi_max and ey > noise:
             assert x == y, (b, x, y, ex, ey)
+        if max(ex, ey) > 10 * noise:
+            assert min(ex, ey) * 10 >= max(ex, ey), (b, x, y, ex, ey)
         else:
-            assert abs(ex - ey) <= noise, (b, x, y, ex, ey)
+            assert abs(ex - ey) <= 10 * noise, (b, x, y, ex, ey)
 
 
 def golden(case):
@@ -194,6 +203,13 @@ def test_sweep_cfg3_vs_oracle(tnt, precision):
                     "compared")
     print(f"[sweep cfg3 {precision}] {k} sweeps", flush=True)
     res, mps, _ = gpu_sweeps(tnt, g, precision, sweeps=k)
+    # the first bond updates, before the unconverged first sweep amplifies
+    # rounding differences (they reach chi = 1024 from the fifth bond on)
+    e1 = np.array(res[0]["bond_E"][:12])
+    r1 = np.array(g["sweeps"][0]["E"][:12])
+    rel1 = float(np.max(np.abs(e1 - r1) / np.abs(r1)))
+    print(f"  first 12 bond updates of sweep 1: max|dE/E| {rel1:.2e}", flush=True)
+    assert rel1 <= {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-5}[precision]
     e = res[-1]["bond_E"][-1]
     er = g["sweeps"][-1]["E"][-1]
     rel = abs(e - er) / abs(er)
