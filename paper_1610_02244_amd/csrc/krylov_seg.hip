@@ -226,7 +226,7 @@ __device__ inline void block_partials(double* v, double* red, double* part) {
 
 // partials of c = V^H w over V_0 .. V_{K-1}, as (re, im) pairs
 template <int K>
-__global__ __launch_bounds__(RED_THREADS) void seg_cgs_dot_kernel(
+__global__ __launch_bounds__(RED_THREADS) void seg_cgs_dot_lanes(
     const double* __restrict__ V, int64_t ld, const double* __restrict__ w, int64_t N,
     const SegBlock* __restrict__ blk, double* __restrict__ part) {
   constexpr int P = pow2_at_least(2 * K);
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(RED_THREADS) void seg_cgs_dot_kernel(
 // V^H w into part_out.  The instance's first workgroup writes the pair of
 // V_{K-1} to pair_dst + inst * S (the recurrence's alpha_j).
 template <int K>
-__global__ __launch_bounds__(RED_THREADS) void seg_cgs_update_dot_kernel(
+__global__ __launch_bounds__(RED_THREADS) void seg_cgs_update_dot_lanes(
     const double* __restrict__ V, int64_t ld, const double* __restrict__ part_in,
     double* __restrict__ w, int64_t N, const SegBlock* __restrict__ blk,
     const int2* __restrict__ inst_blk, double* __restrict__ part_out,
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(RED_THREADS) void seg_cgs_update_dot_kernel(
 // c = the instance's sum of part_in; w -= V c; partials of |w|^2 into
 // part_out (one value per workgroup)
 template <int K>
-__global__ __launch_bounds__(RED_THREADS) void seg_cgs_update_norm_kernel(
+__global__ __launch_bounds__(RED_THREADS) void seg_cgs_update_norm_lanes(
     const double* __restrict__ V, int64_t ld, const double* __restrict__ part_in,
     double* __restrict__ w, int64_t N, const SegBlock* __restrict__ blk,
     const int2* __restrict__ inst_blk, double* __restrict__ part_out) {
@@ -325,6 +325,215 @@ __global__ __launch_bounds__(RED_THREADS) void seg_cgs_update_norm_kernel(
   }
   __syncthreads();
   block_partials<1, 1>(acc, red, part_out);
+}
+
+// Two forms of each basis pass.  "lanes": every lane carries all K basis
+// entries and 2K projection sums of its entries; for small K this streams
+// at 5-7 TB/s.  "waves": the basis is split over the workgroup's waves
+// (below); fewer registers per lane, so from about ten vectors on it keeps
+// its occupancy where the lanes form drops to two waves per SIMD
+// (K = 20 update pass on a 2.9M-entry vector: 291 us against 489 us).
+
+// The three basis passes split the basis over the workgroup's four waves:
+// wave v owns vectors i = v, v + 4, v + 8, ... (KW = ceil(K / 4) of them),
+// and all four waves walk the same entries, SEG_U per lane per tile.  A
+// lane then holds only its wave's share of the basis entries and of the
+// projection sums (at most 2 * 8 of each for K <= 32), so the kernels run
+// at high occupancy with every basis entry read from memory once; the
+// update's partial sums meet in LDS.
+constexpr int SEG_WAVES = RED_THREADS / 64;
+constexpr int SEG_U = 2;                         // entries per lane per tile
+constexpr int SEG_TILE = RED_THREADS / SEG_WAVES * SEG_U;   // 128 entries
+static_assert(SEG_WAVES == 4, "the basis passes assume four waves per workgroup");
+
+// sum over the wave's 64 lanes of each of M values; every lane gets the totals
+template <int M>
+__device__ inline void wave_sum_all(double* v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) v[i] += __shfl_xor(v[i], o, 64);
+  }
+}
+
+// loads the wave's basis entries of one tile (zero beyond hi)
+template <int K, int KW>
+__device__ inline void load_tile(const double* __restrict__ V, int64_t ld, int64_t N,
+                                 int64_t x0, int64_t hi, int wv, double (&vr)[KW][SEG_U],
+                                 double (&vi)[KW][SEG_U]) {
+#pragma unroll
+  for (int q = 0; q < KW; ++q) {
+    const int i = wv + SEG_WAVES * q;
+#pragma unroll
+    for (int u = 0; u < SEG_U; ++u) {
+      const int64_t x = x0 + 64 * u;
+      const bool ok = i < K && x < hi;
+      vr[q][u] = ok ? V[i * ld + x] : 0.0;
+      vi[q][u] = ok ? V[i * ld + N + x] : 0.0;
+    }
+  }
+}
+
+// w_new = w - V c for one tile: each wave's share of V c (its vectors, in
+// order) goes to LDS, every wave adds the four shares in the same fixed
+// order and subtracts them from w.  Two barriers per tile keep `sh`
+// single-buffered.
+template <int K, int KW>
+__device__ inline void tile_update(const double* __restrict__ w, int64_t N, int64_t x0,
+                                   int64_t hi, int wv, int lane, const double* cs,
+                                   const double (&vr)[KW][SEG_U], const double (&vi)[KW][SEG_U],
+                                   double* sh, double (&wr)[SEG_U], double (&wi)[SEG_U]) {
+#pragma unroll
+  for (int u = 0; u < SEG_U; ++u) {
+    double pr = 0, pi = 0;
+#pragma unroll
+    for (int q = 0; q < KW; ++q) {
+      const int i = wv + SEG_WAVES * q;
+      if (i < K) {
+        const double cr = cs[2 * i], ci = cs[2 * i + 1];
+        pr += cr * vr[q][u] - ci * vi[q][u];
+        pi += cr * vi[q][u] + ci * vr[q][u];
+      }
+    }
+    sh[(wv * SEG_U + u) * 128 + lane] = pr;
+    sh[(wv * SEG_U + u) * 128 + 64 + lane] = pi;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < SEG_U; ++u) {
+    const int64_t x = x0 + 64 * u;
+    const double* s0 = sh + u * 128 + lane;
+    constexpr int WS = SEG_U * 128;  // stride between the waves' shares
+    const double pr = (s0[0] + s0[WS]) + (s0[2 * WS] + s0[3 * WS]);
+    const double pi = (s0[64] + s0[WS + 64]) + (s0[2 * WS + 64] + s0[3 * WS + 64]);
+    wr[u] = x < hi ? w[x] - pr : 0.0;
+    wi[u] = x < hi ? w[N + x] - pi : 0.0;
+  }
+  __syncthreads();
+}
+
+// the wave's 2 * KW projection sums (one wave per vector, no cross-wave
+// sum) into part[blockIdx.x * 2K + 2i + {0, 1}]
+template <int K, int KW>
+__device__ inline void store_projections(double (&acc)[2 * KW], int wv, int lane,
+                                         double* __restrict__ part) {
+  wave_sum_all<2 * KW>(acc);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < KW; ++q) {
+      const int i = wv + SEG_WAVES * q;
+      if (i < K) {
+        part[(size_t)blockIdx.x * 2 * K + 2 * i] = acc[2 * q];
+        part[(size_t)blockIdx.x * 2 * K + 2 * i + 1] = acc[2 * q + 1];
+      }
+    }
+  }
+}
+
+// partials of c = V^H w over V_0 .. V_{K-1}, as (re, im) pairs
+template <int K>
+__global__ __launch_bounds__(RED_THREADS) void seg_cgs_dot_waves(
+    const double* __restrict__ V, int64_t ld, const double* __restrict__ w, int64_t N,
+    const SegBlock* __restrict__ blk, double* __restrict__ part) {
+  constexpr int KW = (K + SEG_WAVES - 1) / SEG_WAVES;
+  const SegBlock sb = blk[blockIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc[2 * KW];
+#pragma unroll
+  for (int o = 0; o < 2 * KW; ++o) acc[o] = 0;
+  for (int64_t t = sb.lo; t < sb.hi; t += SEG_TILE) {
+    double vr[KW][SEG_U], vi[KW][SEG_U];
+    load_tile<K, KW>(V, ld, N, t + lane, sb.hi, wv, vr, vi);
+#pragma unroll
+    for (int u = 0; u < SEG_U; ++u) {
+      const int64_t x = t + lane + 64 * u;
+      const double wr = x < sb.hi ? w[x] : 0.0, wi = x < sb.hi ? w[N + x] : 0.0;
+#pragma unroll
+      for (int q = 0; q < KW; ++q) {
+        acc[2 * q] += vr[q][u] * wr + vi[q][u] * wi;
+        acc[2 * q + 1] += vr[q][u] * wi - vi[q][u] * wr;
+      }
+    }
+  }
+  store_projections<K, KW>(acc, wv, lane, part);
+}
+
+// c = the instance's sum of part_in (2K values); w -= V c; partials of
+// V^H w into part_out.  The instance's first workgroup writes the pair of
+// V_{K-1} to pair_dst + inst * S (the recurrence's alpha_j).
+template <int K>
+__global__ __launch_bounds__(RED_THREADS) void seg_cgs_update_dot_waves(
+    const double* __restrict__ V, int64_t ld, const double* __restrict__ part_in,
+    double* __restrict__ w, int64_t N, const SegBlock* __restrict__ blk,
+    const int2* __restrict__ inst_blk, double* __restrict__ part_out,
+    double* __restrict__ pair_dst, int S) {
+  constexpr int KW = (K + SEG_WAVES - 1) / SEG_WAVES;
+  __shared__ double red[RED_THREADS > 4 * SEG_U * 128 ? RED_THREADS : 4 * SEG_U * 128];
+  __shared__ double cs[2 * K];
+  const SegBlock sb = blk[blockIdx.x];
+  const int2 r = inst_blk[sb.inst];
+  instance_sums<2 * K>(part_in, r.x, r.y, red, cs);
+  if (pair_dst && blockIdx.x == r.x && threadIdx.x < 2)
+    pair_dst[(size_t)sb.inst * S + threadIdx.x] = cs[2 * (K - 1) + threadIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc[2 * KW];
+#pragma unroll
+  for (int o = 0; o < 2 * KW; ++o) acc[o] = 0;
+  for (int64_t t = sb.lo; t < sb.hi; t += SEG_TILE) {
+    double vr[KW][SEG_U], vi[KW][SEG_U], wr[SEG_U], wi[SEG_U];
+    load_tile<K, KW>(V, ld, N, t + lane, sb.hi, wv, vr, vi);
+    tile_update<K, KW>(w, N, t + lane, sb.hi, wv, lane, cs, vr, vi, red, wr, wi);
+#pragma unroll
+    for (int u = 0; u < SEG_U; ++u) {
+      const int64_t x = t + lane + 64 * u;
+      if (wv == 0 && x < sb.hi) {
+        w[x] = wr[u];
+        w[N + x] = wi[u];
+      }
+#pragma unroll
+      for (int q = 0; q < KW; ++q) {
+        acc[2 * q] += vr[q][u] * wr[u] + vi[q][u] * wi[u];
+        acc[2 * q + 1] += vr[q][u] * wi[u] - vi[q][u] * wr[u];
+      }
+    }
+  }
+  store_projections<K, KW>(acc, wv, lane, part_out);
+}
+
+// c = the instance's sum of part_in; w -= V c; partials of |w|^2 into
+// part_out (one value per workgroup)
+template <int K>
+__global__ __launch_bounds__(RED_THREADS) void seg_cgs_update_norm_waves(
+    const double* __restrict__ V, int64_t ld, const double* __restrict__ part_in,
+    double* __restrict__ w, int64_t N, const SegBlock* __restrict__ blk,
+    const int2* __restrict__ inst_blk, double* __restrict__ part_out) {
+  constexpr int KW = (K + SEG_WAVES - 1) / SEG_WAVES;
+  __shared__ double red[RED_THREADS > 4 * SEG_U * 128 ? RED_THREADS : 4 * SEG_U * 128];
+  __shared__ double cs[2 * K];
+  const SegBlock sb = blk[blockIdx.x];
+  const int2 r = inst_blk[sb.inst];
+  instance_sums<2 * K>(part_in, r.x, r.y, red, cs);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc[1] = {0};
+  for (int64_t t = sb.lo; t < sb.hi; t += SEG_TILE) {
+    double vr[KW][SEG_U], vi[KW][SEG_U], wr[SEG_U], wi[SEG_U];
+    load_tile<K, KW>(V, ld, N, t + lane, sb.hi, wv, vr, vi);
+    tile_update<K, KW>(w, N, t + lane, sb.hi, wv, lane, cs, vr, vi, red, wr, wi);
+    if (wv == 0) {
+#pragma unroll
+      for (int u = 0; u < SEG_U; ++u) {
+        const int64_t x = t + lane + 64 * u;
+        if (x < sb.hi) {
+          w[x] = wr[u];
+          w[N + x] = wi[u];
+        }
+        acc[0] += wr[u] * wr[u] + wi[u] * wi[u];
+      }
+    }
+  }
+  // wave 0 holds the sums; one value per workgroup
+  wave_sum_all<1>(acc);
+  if (threadIdx.x == 0) part_out[blockIdx.x] = acc[0];
 }
 
 // nrm2 = the instance's sum of part_in; beta_j = sqrt(nrm2); scale_j =
@@ -364,13 +573,22 @@ __global__ __launch_bounds__(RED_THREADS) void seg_cgs_next_kernel(
   M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16) \
   M(17) M(18) M(19) M(20) M(21) M(22) M(23) M(24) M(25) M(26) M(27) M(28) M(29) M(30) M(31) M(32)
 
+// Smallest basis size at which each pass takes the waves form (measured on
+// a 2.9M-entry vector: dot 5.5 vs 5.8 TB/s at K = 15; update-and-dot 2.9 vs
+// 3.5 TB/s at K = 10; update-and-norm 3.5 vs 3.6 TB/s at K = 15).
+constexpr int kDotWavesFrom = 12, kUpdateDotWavesFrom = 8, kUpdateNormWavesFrom = 12;
+
 void launch_seg_cgs_dot(const double* V, int64_t ld, int k, const double* w, int64_t N,
                         const SegBlock* blk, int nblk, double* part, hipStream_t s) {
   switch (k) {
-#define TNT_CASE(KK)                                                                          \
-  case KK:                                                                                    \
-    hipLaunchKernelGGL(seg_cgs_dot_kernel<KK>, dim3(nblk), dim3(RED_THREADS), 0, s, V, ld, w, \
-                       N, blk, part);                                                         \
+#define TNT_CASE(KK)                                                                              \
+  case KK:                                                                                        \
+    if constexpr (KK >= kDotWavesFrom)                                                            \
+      hipLaunchKernelGGL(seg_cgs_dot_waves<KK>, dim3(nblk), dim3(RED_THREADS), 0, s, V, ld,       \
+                         w, N, blk, part);                                                        \
+    else                                                                                          \
+      hipLaunchKernelGGL(seg_cgs_dot_lanes<KK>, dim3(nblk), dim3(RED_THREADS), 0, s, V, ld,       \
+                         w, N, blk, part);                                                        \
     break;
     TNT_K_CASES(TNT_CASE)
 #undef TNT_CASE
@@ -383,10 +601,14 @@ void launch_seg_cgs_update_dot(const double* V, int64_t ld, int k, const double*
                                int nblk, double* part_out, double* pair_dst, int S,
                                hipStream_t s) {
   switch (k) {
-#define TNT_CASE(KK)                                                                             \
-  case KK:                                                                                       \
-    hipLaunchKernelGGL(seg_cgs_update_dot_kernel<KK>, dim3(nblk), dim3(RED_THREADS), 0, s, V, ld, \
-                       part_in, w, N, blk, inst_blk, part_out, pair_dst, S);                     \
+#define TNT_CASE(KK)                                                                              \
+  case KK:                                                                                        \
+    if constexpr (KK >= kUpdateDotWavesFrom)                                                      \
+      hipLaunchKernelGGL(seg_cgs_update_dot_waves<KK>, dim3(nblk), dim3(RED_THREADS), 0, s,       \
+                         V, ld, part_in, w, N, blk, inst_blk, part_out, pair_dst, S);             \
+    else                                                                                          \
+      hipLaunchKernelGGL(seg_cgs_update_dot_lanes<KK>, dim3(nblk), dim3(RED_THREADS), 0, s,       \
+                         V, ld, part_in, w, N, blk, inst_blk, part_out, pair_dst, S);             \
     break;
     TNT_K_CASES(TNT_CASE)
 #undef TNT_CASE
@@ -398,10 +620,14 @@ void launch_seg_cgs_update_norm(const double* V, int64_t ld, int k, const double
                                 double* w, int64_t N, const SegBlock* blk, const int2* inst_blk,
                                 int nblk, double* part_out, hipStream_t s) {
   switch (k) {
-#define TNT_CASE(KK)                                                                           \
-  case KK:                                                                                     \
-    hipLaunchKernelGGL(seg_cgs_update_norm_kernel<KK>, dim3(nblk), dim3(RED_THREADS), 0, s, V, \
-                       ld, part_in, w, N, blk, inst_blk, part_out);                            \
+#define TNT_CASE(KK)                                                                              \
+  case KK:                                                                                        \
+    if constexpr (KK >= kUpdateNormWavesFrom)                                                     \
+      hipLaunchKernelGGL(seg_cgs_update_norm_waves<KK>, dim3(nblk), dim3(RED_THREADS), 0, s,      \
+                         V, ld, part_in, w, N, blk, inst_blk, part_out);                          \
+    else                                                                                          \
+      hipLaunchKernelGGL(seg_cgs_update_norm_lanes<KK>, dim3(nblk), dim3(RED_THREADS), 0, s,      \
+                         V, ld, part_in, w, N, blk, inst_blk, part_out);                          \
     break;
     TNT_K_CASES(TNT_CASE)
 #undef TNT_CASE
