@@ -81,6 +81,16 @@ const char* tnt_last_error(tnt_ctx ctx);
 tnt_status tnt_sync(tnt_ctx ctx);
 /* Bytes currently held by the context's device pool (in use + cached). */
 int64_t tnt_pool_bytes(tnt_ctx ctx);
+/* Device memory of the context in bytes (host query, no device work):
+ * out[0] held by the pool (in use + cached), out[1] in use, out[2] the
+ * most in use at once since the context was created, out[3] the device
+ * workspace held by the library's rocBLAS / rocSOLVER handles.  The pool
+ * keeps released blocks for reuse; before it allocates more it returns
+ * its cached blocks to the runtime (a device synchronisation) when they
+ * exceed both 4 GiB and the bytes in use, so out[0] stays below about
+ * twice out[2] plus 4 GiB.  out is caller-owned host memory of 4 values.
+ * Errors: TNT_E_ARG (null out). */
+tnt_status tnt_ctx_memory(tnt_ctx ctx, int64_t* out);
 /* Tile-shape autotuning of the H_eff grouped GEMMs (on by default): the
  * first application of a new block structure times every candidate tile
  * shape of each GEMM step of at least 1e9 flops and caches the choice per
@@ -481,6 +491,9 @@ typedef struct {
   double seconds_theta;   /* wall time of theta formation                   */
   double seconds_setup;   /* wall time of H_eff plan lookup or build,
                              environment packing and Krylov reservation     */
+  int64_t eig_retries;    /* sector eigenproblems of the SVD steps redone with
+                             the Jacobi eigensolver after divide and conquer
+                             failed or returned non-finite vectors          */
 } tnt_sweep_result;
 
 /* One sweep: right pass over bonds 1..L-1 then left pass L-1..1 (each:

@@ -81,7 +81,7 @@ class SweepResult(C.Structure):
                 ("seconds_svd", C.c_double), ("seconds_env", C.c_double),
                 ("gemm_flops", C.c_double), ("seconds_gemm", C.c_double),
                 ("gemm_launches", C.c_int64), ("seconds_theta", C.c_double),
-                ("seconds_setup", C.c_double)]
+                ("seconds_setup", C.c_double), ("eig_retries", C.c_int64)]
 
 
 # name -> (restype, argtypes); mirrors include/tnt.h
@@ -91,6 +91,7 @@ SIGNATURES = {
     "tnt_last_error": (C.c_char_p, [P]),
     "tnt_sync": (C.c_int32, [P]),
     "tnt_pool_bytes": (C.c_int64, [P]),
+    "tnt_ctx_memory": (C.c_int32, [P, C.POINTER(C.c_int64)]),
     "tnt_ctx_set_autotune": (C.c_int32, [P, C.c_int32]),
     "tnt_ctx_set_graphs": (C.c_int32, [P, C.c_int32]),
     "tnt_mpo_spin1_heisenberg": (C.c_int32, [C.c_double, F64P, I32P]),
@@ -404,6 +405,14 @@ class Tnt:
     def pool_bytes(self):
         return int(self.lib.tnt_pool_bytes(self.ctx))
 
+    def memory(self) -> dict:
+        """tnt_ctx_memory: the pool's held / in-use / peak in-use bytes and
+        the rocBLAS / rocSOLVER handles' device workspace."""
+        out = (C.c_int64 * 4)()
+        self._check("tnt_ctx_memory", self.lib.tnt_ctx_memory(self.ctx, out))
+        return {"pool_held": int(out[0]), "pool_in_use": int(out[1]),
+                "pool_peak_in_use": int(out[2]), "blas_workspace": int(out[3])}
+
     def set_autotune(self, on: bool):
         self._check("tnt_ctx_set_autotune", self.lib.tnt_ctx_set_autotune(self.ctx, int(on)))
 
@@ -595,8 +604,8 @@ class Tnt:
                   err_type=TNT_ERR_2NORM, renormalise=True):
         """One second-order TEBD step of dt with bond Hamiltonians h
         (L-1, d^2, d^2); returns per-gate truncation errors, kept dims, stats.
-        The default relative cut (as in sweep) drops singular values that are
-        zero to working precision; rel_tol=-1 keeps up to chi_max values."""
+        The default relative cut (as in sweep) drops Schmidt values below
+        1e-12 of the largest; rel_tol=-1 keeps up to chi_max values."""
         h = np.ascontiguousarray(h, dtype=np.float64)
         cap = 2 * (mps.L - 1)
         eps = np.zeros(cap)

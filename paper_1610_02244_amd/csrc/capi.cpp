@@ -73,7 +73,8 @@ static void raw_mpo(uint64_t& h, const tnt_mpo_site* m) {
   raw_add(h, m->W, sizeof(double) * (size_t)m->D * m->D * m->d * m->d);
 }
 
-void destroy_blas(void* h);  // svd.cpp
+void destroy_blas(void* h);                  // svd.cpp
+int64_t blas_workspace_bytes(const Ctx& c);  // svd.cpp
 
 Ctx::~Ctx() {
   if (stream) (void)hipStreamSynchronize(stream);
@@ -411,6 +412,16 @@ tnt_status tnt_sync(tnt_ctx ctx) {
 
 int64_t tnt_pool_bytes(tnt_ctx ctx) {
   return ctx ? reinterpret_cast<Ctx*>(ctx)->pool.held() : -1;
+}
+
+tnt_status tnt_ctx_memory(tnt_ctx ctx, int64_t* out) {
+  TNT_API_BEGIN(ctx)
+  if (!out) fail(TNT_E_ARG, "tnt_ctx_memory: null out");
+  out[0] = c.pool.held();
+  out[1] = c.pool.in_use();
+  out[2] = c.pool.peak_in_use();
+  out[3] = blas_workspace_bytes(c);
+  TNT_API_END
 }
 
 tnt_status tnt_ctx_set_autotune(tnt_ctx ctx, int32_t on) {

@@ -514,6 +514,7 @@ static void fill_result(const SweepStats& st, tnt_sweep_result* r) {
   r->gemm_flops = st.gemm_flops;
   r->seconds_gemm = st.t_gemm;
   r->gemm_launches = st.gemm_launches;
+  r->eig_retries = st.eig_retries;
 }
 
 tnt_status tnt_dmrg_sweep_batched(tnt_ctx ctx, int32_t n, const tnt_mps* mps, const tnt_env* env,

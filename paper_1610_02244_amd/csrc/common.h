@@ -32,20 +32,27 @@ struct Error : std::runtime_error {
 // for reuse after release, so steady-state sweeps call hipMalloc only while
 // bond dimensions grow.  Released blocks are reused only after the context
 // stream has passed the release point (the pool is per-stream and every
-// kernel runs on that stream, so stream order makes reuse safe).
+// kernel runs on that stream, so stream order makes reuse safe).  Block
+// sizes drift along a sweep (every bond has other dimensions), so cached
+// blocks that no request fits pile up: before allocating more, the pool
+// returns its cached blocks to the runtime when they exceed both
+// kCacheFloor and the bytes in use.
 class Pool {
  public:
+  static constexpr int64_t kCacheFloor = int64_t(4) << 30;
   ~Pool();
   void* get(size_t bytes);
   void put(void* p);
   int64_t held() const { return held_; }
+  int64_t in_use() const { return in_use_; }
+  int64_t peak_in_use() const { return peak_; }
   void release_all();
 
  private:
   static size_t round(size_t b);
   std::multimap<size_t, void*> free_;
   std::map<void*, size_t> live_;
-  int64_t held_ = 0;
+  int64_t held_ = 0, in_use_ = 0, peak_ = 0;
 };
 
 // RAII handle on pool memory.
@@ -105,6 +112,9 @@ struct Ctx {
   // recording runs on a stream of its own (the context's stream may be the
   // null stream, which cannot be recorded)
   int graphs = 0;
+  // sector eigenproblems the SVD redid with the Jacobi eigensolver because
+  // divide and conquer failed or returned non-finite vectors (running count)
+  int64_t eig_retries = 0;
   hipStream_t gstream = nullptr;
   std::map<uint64_t, int> tune_cache;
   static constexpr int kSide = 8;

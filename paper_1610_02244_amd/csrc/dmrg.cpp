@@ -431,6 +431,7 @@ void right_canonicalize(Ctx& c, MpsH& m) {
 // ---------------------------------------------------------------------------
 void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats& st) {
   const double t0 = now_s();
+  const int64_t retries0 = c.eig_retries;
   const int L = m.L;
   if (L < 2) fail(TNT_E_STATE, "need at least two sites");
   if (p.record_cap < 2 * (L - 1) && (p.bond_E || p.bond_eps || p.bond_chi || p.bond_steps))
@@ -506,6 +507,7 @@ void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats&
     }
   }
   st.t_total = now_s() - t0;
+  st.eig_retries = c.eig_retries - retries0;
 }
 
 // ---------------------------------------------------------------------------
@@ -517,6 +519,7 @@ void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats&
 void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<EnvS*>& es,
                         const tnt_sweep_params* ps, std::vector<SweepStats>& st) {
   const double t0 = now_s();
+  const int64_t retries0 = c.eig_retries;
   const int nc = (int)ms.size();
   st.assign(nc, SweepStats{});
   int T = 0;
@@ -677,6 +680,7 @@ void dmrg_sweep_batched(Ctx& c, const std::vector<MpsH*>& ms, const std::vector<
   const double total = now_s() - t0;
   for (SweepStats& s : st) {
     s.t_total = total;
+    s.eig_retries = c.eig_retries - retries0;
     s.t_matvec = t_matvec;
     s.t_lanczos = t_lanczos;
     s.t_gemm = t_gemm;

@@ -68,6 +68,7 @@ struct SweepStats {
   double gemm_flops = 0, t_gemm = 0;
   int64_t gemm_launches = 0;
   double t_total = 0, t_matvec = 0, t_lanczos = 0, t_svd = 0, t_env = 0, t_theta = 0, t_setup = 0;
+  int64_t eig_retries = 0;
 };
 
 void dmrg_sweep(Ctx& c, MpsH& m, EnvS& e, const tnt_sweep_params& p, SweepStats& st);

@@ -351,6 +351,15 @@ struct ZNormTask {
 };
 void launch_zcopy(const ZCopyTask* t, int ntask, int64_t max_n, hipStream_t s);
 void launch_znorm2(const ZNormTask* t, int ntask, hipStream_t s);
+// flags[t.slot] = 1 when any of t.x[0 .. t.n) is not finite (flags cleared
+// by the caller)
+struct FiniteTask {
+  const double* x;
+  int64_t n;
+  int slot;
+};
+void launch_check_finite_batch(const FiniteTask* t, int ntask, int64_t max_n, int* flags,
+                               hipStream_t s);
 
 // z[2k] = re[k], z[2k+1] = (conj ? -im[k] : im[k]) for k < n
 void launch_interleave(const double* re, const double* im, double* z, int64_t n, int conj,

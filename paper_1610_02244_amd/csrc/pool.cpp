@@ -22,9 +22,14 @@ void* Pool::get(size_t bytes) {
   if (it != free_.end() && it->first <= 2 * r) {
     void* p = it->second;
     live_[p] = it->first;
+    in_use_ += (int64_t)it->first;
+    peak_ = std::max(peak_, in_use_);
     free_.erase(it);
     return p;
   }
+  // cached blocks that no request fits: hand them back before growing
+  const int64_t cached = held_ - in_use_;
+  if (cached > kCacheFloor && cached > in_use_) release_all();
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, r);
   if (e != hipSuccess) {
@@ -38,6 +43,8 @@ void* Pool::get(size_t bytes) {
   }
   live_[p] = r;
   held_ += (int64_t)r;
+  in_use_ += (int64_t)r;
+  peak_ = std::max(peak_, in_use_);
   return p;
 }
 
@@ -45,6 +52,7 @@ void Pool::put(void* p) {
   auto it = live_.find(p);
   if (it == live_.end()) return;
   free_.insert({it->second, p});
+  in_use_ -= (int64_t)it->second;
   live_.erase(it);
 }
 
@@ -62,6 +70,7 @@ Pool::~Pool() {
   release_all();
   for (auto& kv : live_) (void)hipFree(kv.first);
   live_.clear();
+  in_use_ = 0;
 }
 
 }  // namespace tnt

@@ -54,6 +54,19 @@ namespace tnt {
 
 void destroy_blas(void* h) { rocblas_destroy_handle(static_cast<rocblas_handle>(h)); }
 
+int64_t blas_workspace_bytes(const Ctx& c) {
+  int64_t total = 0;
+  auto add = [&](void* h) {
+    size_t b = 0;
+    if (h && rocblas_get_device_memory_size(static_cast<rocblas_handle>(h), &b) ==
+                 rocblas_status_success)
+      total += (int64_t)b;
+  };
+  add(c.blas);
+  for (void* h : c.side_blas) add(h);
+  return total;
+}
+
 static rocblas_handle blas(Ctx& c) {
   if (!c.blas) {
     rocblas_handle h = nullptr;
@@ -507,11 +520,37 @@ static void eig_batch(Ctx& c, std::vector<EigProb>& probs) {
                       hipMemcpyDeviceToHost));
     for (size_t q = 0; q < raw.size(); ++q) *probs[small[g][q]].info = raw[q];
   }
-  // divide and conquer can fail on large clusters of (near-)zero eigenvalues;
+  // divide and conquer can fail on large clusters of (near-)zero eigenvalues,
+  // with an error code or with non-finite eigenvectors and a zero code;
   // redo such a problem with the library's Jacobi eigensolver
+  std::vector<FiniteTask> ft;
+  int64_t ftmax = 0;
+  for (size_t i = 0; i < probs.size(); ++i) {
+    const EigProb& P = probs[i];
+    if (P.n <= 0) continue;
+    ft.push_back(FiniteTask{P.z + 2 * P.zoff, 2 * (int64_t)P.n * P.n, (int)i});
+    ft.push_back(FiniteTask{P.w + P.woff, P.n, (int)i});
+    ftmax = std::max<int64_t>(ftmax, 2 * (int64_t)P.n * P.n);
+  }
+  std::vector<int> bad(probs.size(), 0);
+  if (!ft.empty()) {
+    DevBuf ftab(&c.pool, ft.size() * sizeof(FiniteTask));
+    DevBuf flags(&c.pool, probs.size() * sizeof(int));
+    TNT_HIP(hipMemcpyAsync(ftab.ptr, ft.data(), ft.size() * sizeof(FiniteTask),
+                           hipMemcpyHostToDevice, c.stream));
+    TNT_HIP(hipMemcpyAsync(flags.ptr, bad.data(), bad.size() * sizeof(int),
+                           hipMemcpyHostToDevice, c.stream));
+    launch_check_finite_batch(ftab.as<FiniteTask>(), (int)ft.size(), ftmax, flags.as<int>(),
+                              c.stream);
+    TNT_HIP(hipMemcpyAsync(bad.data(), flags.ptr, bad.size() * sizeof(int),
+                           hipMemcpyDeviceToHost, c.stream));
+    TNT_HIP(hipStreamSynchronize(c.stream));
+  }
   rocblas_handle h = blas(c);
-  for (EigProb& P : probs) {
-    if (P.n <= 0 || *P.info == 0) continue;
+  for (size_t i = 0; i < probs.size(); ++i) {
+    EigProb& P = probs[i];
+    if (P.n <= 0 || (*P.info == 0 && !bad[i])) continue;
+    ++c.eig_retries;
     P.rebuild();
     DevBuf rj(&c.pool, 64), inf(&c.pool, sizeof(rocblas_int));
     if (rocsolver_zheevj(h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper,

@@ -34,6 +34,8 @@ using FactorAlloc = std::function<FactorPlanes(const SvdOut&)>;
 
 // The context's rocBLAS handle (created on first use) bound to its stream.
 void* blas_handle(Ctx& c);
+// Device workspace bytes held by the context's rocBLAS / rocSOLVER handles.
+int64_t blas_workspace_bytes(const Ctx& c);
 
 // Selection of the kept count (host); see tnt_trunc_select.
 int trunc_select(const double* lam, int n, const tnt_trunc_params& p, double* eps);

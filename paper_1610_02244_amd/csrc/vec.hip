@@ -181,6 +181,26 @@ void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(check_finite_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, flag);
 }
 
+// one task per grid row, chunks of its range per grid column
+__global__ __launch_bounds__(256) void check_finite_batch_kernel(
+    const FiniteTask* __restrict__ tasks, int* __restrict__ flags) {
+  const FiniteTask t = tasks[blockIdx.y];
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < t.n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(t.x[i])) bad = true;
+  if (bad) flags[t.slot] = 1;  // benign race: every writer stores the same value
+}
+
+void launch_check_finite_batch(const FiniteTask* t, int ntask, int64_t max_n, int* flags,
+                               hipStream_t s) {
+  if (ntask <= 0 || max_n <= 0) return;
+  int64_t gx = (max_n + 255) / 256;
+  if (gx > 64) gx = 64;
+  hipLaunchKernelGGL(check_finite_batch_kernel, dim3((unsigned)gx, ntask), dim3(256), 0, s, t,
+                     flags);
+}
+
 // ---------------------------------------------------------------------------
 // SVD staging: split planes <-> interleaved complex (the eigensolver's format)
 // ---------------------------------------------------------------------------

@@ -269,6 +269,8 @@ def test_many_chain_sweeps_vs_oracle(tnt, precision):
           flush=True)
     res = [tnt.sweep_batched(ms, es, chis, kmax=20, precision=precision, rel_tol=1e-12)
            for _ in range(nsw)]
+    print(f"  sector eigenproblems redone with the Jacobi eigensolver, by sweep: "
+          f"{[r[0]['eig_retries'] for r in res]}", flush=True)
     for i, g in sorted(stored.items()):
         assert (g["L"], g["chi"], g["seed"]) == (specs[i].L, specs[i].chi, specs[i].seed)
         k = len(g["sweeps"])  # each chain at the last sweep the oracle stored
