@@ -97,18 +97,67 @@ def run_sweeps(tnt, torch, mps, env, spec, precision, warmup, steps, roctx=None,
     if roctx:
         roctx.push(TIMED_RANGE)
     t0 = time.perf_counter()
-    res = [tnt.sweep(mps, env, spec.chi, **kw) for _ in range(steps)]
+    res = []
+    for i in range(steps):
+        # tnt_dmrg_sweep returns when its sweep is done; one progress line per
+        # sweep (a long timed region must not look silent)
+        r = tnt.sweep(mps, env, spec.chi, **kw)
+        res.append(r)
+        log(f"  timed sweep {i + 1} [{precision}]: E = {r['energy']:.12f} ({r['seconds_total']:.2f}s)")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     if roctx:
         roctx.pop()
-    for i, r in enumerate(res):
+    for r in res:
         if energies is not None:
             energies.append(r["energy"])
         if stats is not None:
             stats.append(r)
-        log(f"  timed sweep {i + 1} [{precision}]: E = {r['energy']:.12f} ({r['seconds_total']:.2f}s)")
     return res, dt
+
+
+def reference_schedule_flops(left, right, d, W, qw):
+    """F_alg of the unpruned contraction order (Sec. 4.2, Fig. mpspmpomps):
+    step 1 for every (w, theta block) whose L block exists, W1 and W2 as two
+    separate real-times-complex passes over every slab they produce, step 4
+    for every produced slab whose output block is allowed and whose R block
+    exists.  8 flops per complex multiply-add, 4 per real-times-complex term
+    and element.  The library's own count (tnt_heff2_flops) prunes slabs that
+    reach no output and combines W1 W2 into one pass, so it is a few percent
+    lower; both are reported."""
+    import numpy as np
+    W = np.asarray(W)
+    D = len(qw)
+    theta = [(qa, s1, s2) for qa in sorted(left) for s1 in range(d) for s2 in range(d)
+             if qa + s1 + s2 in right]
+    nz = [(w, v, sp, s) for w in range(D) for v in range(D) for sp in range(d) for s in range(d)
+          if W[w, v, sp, s] != 0]
+    f1 = fm = f4 = 0
+    t1 = set()
+    for qa, s1, s2 in theta:
+        qb = qa + s1 + s2
+        for w in range(D):
+            qap = qa + qw[w]
+            if qap in left:
+                f1 += 8 * left[qap] * left[qa] * right[qb]
+                t1.add((w, qap, s1, s2, qb))
+    t2 = set()
+    for w, qap, s1, s2, qb in t1:   # T2[v] = sum_{w, s1} W1[w, v, s1', s1] T1[w]
+        for ww, v, s1p, ss in nz:
+            if ww == w and ss == s1:
+                fm += 4 * left[qap] * right[qb]
+                t2.add((v, qap, s1p, s2, qb))
+    t3 = set()
+    for v, qap, s1p, s2, qb in t2:  # T3[u] = sum_{v, s2} W2[v, u, s2', s2] T2[v]
+        for vv, u, s2p, ss in nz:
+            if vv == v and ss == s2:
+                fm += 4 * left[qap] * right[qb]
+                t3.add((u, qap, s1p, s2p, qb))
+    for u, qap, s1p, s2p, qb in t3:
+        qbp = qap + s1p + s2p
+        if qbp in right and qb == qbp - qw[u]:
+            f4 += 8 * left[qap] * right[qb] * right[qbp]
+    return {"step1": f1, "mpo": fm, "step4": f4, "total": f1 + fm + f4}
 
 
 def matvec_rates(tnt, B, torch, spec, precs=("fp64", "fp32", "bf16x3"), reps=20):
@@ -122,6 +171,7 @@ def matvec_rates(tnt, B, torch, spec, precs=("fp64", "fp32", "bf16x3"), reps=20)
     Ld, Rd, td = tnt.env(Le, qw), tnt.env(Re, qw), tnt.theta(th)
     out = tnt.theta_like(td)
     flops, parts = tnt.heff2_flops(Ld, mpo, mpo, Rd, td)
+    f_ref = reference_schedule_flops(left, right, spec.d, W, qw)["total"]
     rates = {}
     for prec in precs:
         for _ in range(3):   # plan, tile-shape tuning, warm caches
@@ -135,10 +185,12 @@ def matvec_rates(tnt, B, torch, spec, precs=("fp64", "fp32", "bf16x3"), reps=20)
         e1.synchronize()
         t = e0.elapsed_time(e1) * 1e-3 / reps
         rates[prec] = {"s": t, "tflops": flops / t / 1e12,
-                       "frac_fp32_peak": flops / t / 1e12 / PEAK["fp32"]}
+                       "frac_fp32_peak": flops / t / 1e12 / PEAK["fp32"],
+                       "tflops_reference_schedule": f_ref / t / 1e12}
     del Ld, Rd, td, out
     return {"chi": spec.chi, "bond": f"middle bond of L={spec.L}",
-            "flops": int(flops), "parts": [int(x) for x in parts], **rates}
+            "flops": int(flops), "parts": [int(x) for x in parts],
+            "flops_reference_schedule": int(f_ref), **rates}
 
 
 def batched_sweep(tnt, B, torch, precision="fp32"):
@@ -160,19 +212,23 @@ def batched_sweep(tnt, B, torch, precision="fp32"):
     ms, es = [c[0] for c in chains], [c[1] for c in chains]
     tnt.sweep_batched(ms, es, chis, **kw)
     torch.cuda.synchronize()
+    log("  warm-up lockstep sweep done")
     t0 = time.perf_counter()
     rb = tnt.sweep_batched(ms, es, chis, **kw)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    log(f"  timed lockstep sweep: {t_batch:.2f}s")
     del chains, ms, es
     chains = build()
     for (m, e), s in zip(chains, specs):
         tnt.sweep(m, e, s.chi, **kw)
     torch.cuda.synchronize()
+    log("  warm-up chain-by-chain sweeps done")
     t0 = time.perf_counter()
     rs = [tnt.sweep(m, e, s.chi, **kw) for (m, e), s in zip(chains, specs)]
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
+    log(f"  timed chain-by-chain sweeps: {t_single:.2f}s")
     del chains
     flops = sum(r["matvec_flops"] for r in rb)
     per = {k: sum(r[k] for r in rb) / len(rb) for k in
@@ -186,6 +242,47 @@ def batched_sweep(tnt, B, torch, precision="fp32"):
             "batched_breakdown_s": per,
             "max_rel_dE_batched_vs_single": max(abs(a["energy"] - b["energy"]) / abs(b["energy"])
                                                 for a, b in zip(rb, rs))}
+
+
+def batched_lockstep_vs_oracle(tnt, B, torch, precision="fp32", sweeps=4):
+    """The 64-chain workload swept `sweeps` times in lockstep
+    (tnt_dmrg_sweep_batched) from its seeded states; the chains with a stored
+    oracle run (one per chi class) are compared with the oracle's energy
+    after the same number of sweeps."""
+    import synth
+    specs = synth.batched_specs(4)
+    kw = dict(kmax=specs[0].lanczos_steps, precision=precision, rel_tol=specs[0].rel_cutoff)
+    chains = [make_chain(tnt, B, s) for s in specs]
+    ms, es = [c[0] for c in chains], [c[1] for c in chains]
+    times = []
+    res = None
+    for _ in range(sweeps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = tnt.sweep_batched(ms, es, [s.chi for s in specs], **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"  lockstep sweep {len(times)} of {len(specs)} chains: {times[-1]:.2f}s")
+    del chains, ms, es
+    per_chain = {}
+    for f in sorted(os.listdir(os.path.join(ROOT, "tests", "golden"))):
+        if not (f.startswith("sweep_cfg4_chain") and f.endswith(".json")):
+            continue
+        i = int(f[len("sweep_cfg4_chain"):-len(".json")])
+        with open(os.path.join(ROOT, "tests", "golden", f)) as fh:
+            g = json.load(fh)
+        if len(g["sweeps"]) < sweeps:
+            continue
+        e_ref = g["sweeps"][sweeps - 1]["E"][-1]
+        e = res[i]["energy"]
+        per_chain[str(i)] = {"L": specs[i].L, "chi": specs[i].chi, "gpu": e, "oracle": e_ref,
+                             "rel_err": abs(e - e_ref) / abs(e_ref)}
+    return {"sweeps": sweeps, "precision": precision, "sweep_s": times,
+            "bond_updates_per_sweep": int(sum(r["updates"] for r in res)),
+            "matvec_tflops_last_sweep": sum(r["matvec_flops"] for r in res) / times[-1] / 1e12,
+            "vs_oracle": per_chain,
+            "max_rel_err_vs_oracle": max((v["rel_err"] for v in per_chain.values()),
+                                         default=None)}
 
 
 def spin1_sweeps(tnt, B, torch, precisions=("fp32", "fp64"), steps=2):
@@ -284,9 +381,11 @@ def tebd_steps(tnt, B, torch):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         eps = 0.0
-        for _ in range(100):
+        for step in range(100):
             r = tnt.tebd_step(mps, h, 0.01, 200, rel_tol=rel, renormalise=False)
             eps += r["sum_eps"]
+            if (step + 1) % 20 == 0:
+                log(f"  hard-core CDW ({name}): step {step + 1}, chi {r['max_chi']}")
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[f"hardcore_cdw_L51_chi200_{name}"] = {"s_per_step": dt / 100, "steps": 100,
@@ -788,8 +887,12 @@ def main():
     e_final = res[-1]["energy"]
     cmp_main = oracle_compare(args.config, e_main)
     free_b, total_b = torch.cuda.mem_get_info()
+    lib_mem = tnt.memory()
     mem = {"device_used_gb_after_main_run": (total_b - free_b) / 1e9,
-           "note": "whole device, includes the library's pool and torch's cache"}
+           "torch_reserved_gb": torch.cuda.memory_reserved() / 1e9,
+           **{k + "_gb": v / 1e9 for k, v in lib_mem.items()},
+           "note": "device_used is the whole device (library pool, library handles' "
+                   "workspace, torch's cache); the pool figures are the library's own"}
     del env, mps
 
     def leg(precision):
@@ -826,6 +929,10 @@ def main():
 
     bt = None if args.no_batched else batched_rates(tnt, B, torch, args.precision
                                                      if args.precision != "fp64" else "fp32")
+    if bt is not None:
+        log("[bench] 64-chain lockstep sweeps against the oracle")
+        bt["lockstep_sweeps"] = batched_lockstep_vs_oracle(
+            tnt, B, torch, args.precision if args.precision != "fp64" else "fp32")
     mv = matvec_rates(tnt, B, torch, spec)
     mv_big = None
     if not args.no_chi1024 and spec.chi < 1024:

@@ -50,3 +50,27 @@ def test_mfma_util_arithmetic(tmp_path):
     assert r["avg_gpu_cycles"] == pytest.approx(1000.0)
     assert r["mfma_busy_frac"] == pytest.approx(0.375)
     assert r["avg_mfma_insts"] == pytest.approx(10.0)
+
+
+@pytest.mark.parametrize("cfg", ["cfg1", "cfg2", "cfg3", "cfg5"])
+def test_reference_schedule_flops(cfg):
+    """The unpruned count against the oracle's pruned one at the middle bond:
+    step 4 is the same (every produced Bose-Hubbard slab reaches an allowed
+    output), step 1 and the MPO passes can only count more, and the total
+    stays within a few percent."""
+    import synth
+    from oracle import flops as oflops
+    from oracle import model
+    b = load_bench()
+    s = synth.CONFIGS[cfg]
+    bonds = synth.chain_bonds(s.L, s.N, s.nmax, s.chi)
+    left, right = bonds[s.L // 2 - 1], bonds[s.L // 2 + 1]
+    W, qw = model.bh_mpo(s.nmax, s.J, s.U, s.mu)
+    ref = b.reference_schedule_flops(left, right, s.d, W, qw)
+    pruned = oflops.heff2_flops(left, right, s.d, qw, W, W)
+    assert ref["step4"] == pruned["step4"]
+    assert ref["step1"] >= pruned["step1"] and ref["mpo"] >= pruned["mpo"]
+    assert pruned["total"] <= ref["total"] <= 1.15 * pruned["total"]
+    if cfg == "cfg3":
+        # the sector recipe's own estimate of the reference-schedule count
+        assert ref["total"] == pytest.approx(3.656e10, rel=5e-3)
