@@ -180,6 +180,15 @@ __device__ inline void instance_sums(const double* __restrict__ part, int b0, in
   __syncthreads();
 }
 
+// Two forms of each basis pass.  "lanes": every lane carries all K basis
+// entries and 2K projection sums of its entries; for small K this streams
+// at 5-7 TB/s.  "waves": the basis is split over the workgroup's waves
+// (below); fewer registers per lane, so from about ten vectors on it keeps
+// its occupancy where the lanes form drops to two waves per SIMD
+// (K = 20 update pass on a 2.9M-entry vector: 291 us against 489 us).
+
+// --- lanes form ------------------------------------------------------------
+
 // smallest power of two >= n
 constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
 
@@ -327,14 +336,8 @@ __global__ __launch_bounds__(RED_THREADS) void seg_cgs_update_norm_lanes(
   block_partials<1, 1>(acc, red, part_out);
 }
 
-// Two forms of each basis pass.  "lanes": every lane carries all K basis
-// entries and 2K projection sums of its entries; for small K this streams
-// at 5-7 TB/s.  "waves": the basis is split over the workgroup's waves
-// (below); fewer registers per lane, so from about ten vectors on it keeps
-// its occupancy where the lanes form drops to two waves per SIMD
-// (K = 20 update pass on a 2.9M-entry vector: 291 us against 489 us).
-
-// The three basis passes split the basis over the workgroup's four waves:
+// --- waves form ------------------------------------------------------------
+// The basis is split over the workgroup's four waves:
 // wave v owns vectors i = v, v + 4, v + 8, ... (KW = ceil(K / 4) of them),
 // and all four waves walk the same entries, SEG_U per lane per tile.  A
 // lane then holds only its wave's share of the basis entries and of the
