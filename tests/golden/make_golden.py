@@ -31,8 +31,8 @@ CASES = {
     "cfg2_4sweeps": ("cfg2", None, 4, None),
     "cfg3_chi128": ("cfg3", 128, 2, None),
     "cfg3": ("cfg3", None, 4, None),
-    "cfg3_U2": ("cfg3", None, 2, 2.0),
-    "cfg3_U6": ("cfg3", None, 2, 6.0),
+    "cfg3_U2": ("cfg3", None, 4, 2.0),
+    "cfg3_U6": ("cfg3", None, 4, 6.0),
 }
 
 

@@ -211,19 +211,23 @@ def test_sweep_cfg2_converged(tnt, precision):
             assert (x == y) if y == chi_max else (x >= y)
 
 
+@pytest.mark.parametrize("case", ["cfg3", "cfg3_U2", "cfg3_U6"])
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp64"])
-def test_sweep_cfg3_vs_oracle(tnt, precision):
-    """The chi = 1024 chain (L = 64, N = 64, d = 5, U = 3.3): the oracle's stored
-    sweeps (written sweep by sweep; the first from a random state is not
-    converged and not compared) against the GPU's at the same sweep index:
-    energy to 1e-9 relative; kept dims equal wherever the oracle fills chi with
-    a truncation error above the noise level, errors within it elsewhere."""
-    g = golden("cfg3")
+def test_sweep_cfg3_vs_oracle(tnt, precision, case):
+    """The chi = 1024 chain (L = 64, N = 64, d = 5; U = 3.3, and the same seeded
+    MPS at U = 2 and U = 6): the oracle's stored sweeps (written sweep by
+    sweep; the first from a random state is not converged and not compared)
+    against the GPU's at the same sweep index: energy to 1e-9 relative; kept
+    dims equal wherever the oracle fills chi with a truncation error above the
+    noise level, errors within it elsewhere."""
+    if not os.path.exists(os.path.join(GOLD, f"sweep_{case}.json")):
+        pytest.skip(f"no stored oracle run for {case}")
+    g = golden(case)
     k = len(g["sweeps"])
     if k < 2:
         pytest.skip(f"the oracle's chi = 1024 run has {k} stored sweep(s); the first is not "
                     "compared")
-    print(f"[sweep cfg3 {precision}] {k} sweeps", flush=True)
+    print(f"[sweep {case} (U = {g['U']}) {precision}] {k} sweeps", flush=True)
     res, mps, _ = gpu_sweeps(tnt, g, precision, sweeps=k)
     # the first bond updates, before the unconverged first sweep amplifies
     # rounding differences (they reach chi = 1024 from the fifth bond on)
