@@ -211,8 +211,10 @@ def test_sweep_cfg2_converged(tnt, precision):
             assert (x == y) if y == chi_max else (x >= y)
 
 
-@pytest.mark.parametrize("case", ["cfg3", "cfg3_U2", "cfg3_U6"])
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp64"])
+@pytest.mark.parametrize("precision,case", [
+    ("fp32", "cfg3"), ("bf16x3", "cfg3"), ("fp64", "cfg3"),
+    # the same seeded MPS at the other two couplings: the headline path and FP64
+    ("fp32", "cfg3_U2"), ("fp64", "cfg3_U2"), ("fp32", "cfg3_U6"), ("fp64", "cfg3_U6")])
 def test_sweep_cfg3_vs_oracle(tnt, precision, case):
     """The chi = 1024 chain (L = 64, N = 64, d = 5; U = 3.3, and the same seeded
     MPS at U = 2 and U = 6): the oracle's stored sweeps (written sweep by
