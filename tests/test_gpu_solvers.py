@@ -170,23 +170,32 @@ def test_svd_truncate_parity(tnt, absorb, rules):
             np.testing.assert_allclose(V @ V.conj().T, np.eye(k), atol=1e-13)
 
 
-SMALL_L = {0: 1, 1: 2, 2: 5, 3: 7, 4: 4}
-SMALL_R = {1: 3, 2: 6, 3: 5, 4: 8, 5: 2, 6: 1}
+SMALL_L0 = {0: 1, 1: 2, 2: 5, 3: 7, 4: 4}
+SMALL_R0 = {1: 3, 2: 6, 3: 5, 4: 8, 5: 2, 6: 1}
+
+
+# 21 charges of dimension 24 on each side, d = 2: 20 sectors whose Gram
+# matrices have order 48, one batched library call of 20 problems
+MID_L = {q: 24 for q in range(21)}
+MID_R = {q: 24 for q in range(1, 23)}
 
 
 @pytest.mark.parametrize("absorb", ["right", "left"])
-def test_svd_truncate_small_sectors_graded(tnt, absorb):
-    """Only small sectors (Gram orders 1..~20, odd and even: the Jacobi
-    eigensolver's range), with theta's blocks scaled by a geometric factor
-    per block so the Gram eigenvalues span ~10 orders of magnitude; every
-    value is kept.  Checked against the oracle like the general case."""
-    d = 3
+@pytest.mark.parametrize("shape", ["small", "mid"])
+def test_svd_truncate_small_sectors_graded(tnt, absorb, shape):
+    """Only small sectors: Gram orders 1..~20, odd and even (the Jacobi
+    eigensolver's range), or 20 sectors of order 48 (one batched library
+    eigensolve), with theta's blocks scaled by a geometric factor per block so
+    the Gram eigenvalues span ~10 orders of magnitude; every value is kept.
+    Checked against the oracle like the general case."""
+    d, SMALL_L, SMALL_R = (3, SMALL_L0, SMALL_R0) if shape == "small" else (2, MID_L, MID_R)
     rng = np.random.Generator(np.random.PCG64(21))
     th = synth.random_theta(SMALL_L, SMALL_R, d, rng)
+    step = 0.12 if shape == "small" else 10.0 / len(th)
     for i, k in enumerate(sorted(th)):
-        th[k] = th[k] * 10.0 ** (-0.12 * i)
-    ref = osvd.svd_truncate(th, SMALL_L, SMALL_R, d, 1000, absorb=absorb)
-    got = tnt.svd_truncate(tnt.theta(th), absorb=absorb, chi_max=1000)
+        th[k] = th[k] * 10.0 ** (-step * i)
+    ref = osvd.svd_truncate(th, SMALL_L, SMALL_R, d, 10 ** 4, absorb=absorb)
+    got = tnt.svd_truncate(tnt.theta(th), absorb=absorb, chi_max=10 ** 4)
     assert got["chi"] == ref["chi"]
     assert got["bond"] == ref["bond"]
     all_ref = np.concatenate([ref["lambdas"][m] for m in ref["bond"]])
