@@ -743,7 +743,8 @@ def mfma_util(root, simds=1024, xcds=8):
     return out
 
 
-GOLDEN_CASE = {"cfg1": "cfg1", "cfg2": "cfg2_4sweeps", "cfg3": "cfg3"}
+GOLDEN_CASE = {"cfg1": "cfg1", "cfg2": "cfg2_4sweeps", "cfg3": "cfg3", "cfg3_U2": "cfg3_U2",
+               "cfg3_U6": "cfg3_U6"}
 
 
 def golden(config):
@@ -778,6 +779,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--U", type=float, default=None,
+                    help="on-site interaction of the chain (default: the configuration's); "
+                         "the chi = 1024 chain has stored oracle runs at U = 2 and 6 as well")
     ap.add_argument("--leg-sweeps", type=int, default=2,
                     help="sweeps of the FP64 and BF16x3 comparison legs (from the same state)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
@@ -846,6 +850,11 @@ def main():
     from paper_1610_02244_amd import binding as B
 
     spec = synth.CONFIGS[args.config]
+    case = args.config
+    if args.U is not None and args.U != spec.U:
+        import dataclasses
+        spec = dataclasses.replace(spec, U=args.U)
+        case = f"{args.config}_U{args.U:g}"
     tnt = B.load()
     if args.batched_sweep:
         print(json.dumps(batched_sweep(tnt, B, torch, args.precision)), flush=True)
@@ -885,7 +894,7 @@ def main():
     launches = sum(r["gemm_launches"] for r in res)
     achieved = gemm_flops / gemm_s / 1e12 if gemm_s > 0 else 0.0
     e_final = res[-1]["energy"]
-    cmp_main = oracle_compare(args.config, e_main)
+    cmp_main = oracle_compare(case, e_main)
     free_b, total_b = torch.cuda.mem_get_info()
     lib_mem = tnt.memory()
     mem = {"device_used_gb_after_main_run": (total_b - free_b) / 1e9,
@@ -908,7 +917,7 @@ def main():
                "seconds_svd_last_sweep": r[-1]["seconds_svd"],
                "rel_dE_vs_main_path_same_sweep": abs(en[-1] - e_main[k - 1]) / abs(e_main[k - 1])
                if len(e_main) >= k else None,
-               "vs_oracle": oracle_compare(args.config, en)}
+               "vs_oracle": oracle_compare(case, en)}
         del m, e
         return out
 
@@ -945,7 +954,7 @@ def main():
             "launches": int(launches),
             "avg_launch_s": gemm_s / launches if launches else None,
             "avg_flops_per_launch": gemm_flops / launches if launches else None}
-    cpu = None if args.no_cpu_baseline else cpu_baseline(spec, args.config)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(spec, case)
     per = {k: sum(r[k] for r in res) / len(res) for k in
            ("seconds_total", "seconds_matvec", "seconds_lanczos", "seconds_svd", "seconds_env",
             "seconds_theta", "seconds_setup")}
@@ -953,7 +962,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": f"{args.config}: Bose-Hubbard open chain L={spec.L}, N={spec.N}, "
+        "config": {"workload": f"{case}: Bose-Hubbard open chain L={spec.L}, N={spec.N}, "
                                f"nmax={spec.nmax} (d={spec.d}), J={spec.J}, U={spec.U}, "
                                f"chi={spec.chi}, seeded random MPS (seed {spec.seed}), "
                                f"one two-site sweep per step, Lanczos {spec.lanczos_steps} steps",
