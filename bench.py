@@ -785,6 +785,10 @@ def main():
     ap.add_argument("--leg-sweeps", type=int, default=2,
                     help="sweeps of the FP64 and BF16x3 comparison legs (from the same state)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--eig-reduction", type=int, default=None, metavar="ORDER",
+                    help="padded sector order from which the SVD's eigenproblems use the "
+                         "library's own tridiagonal reduction (0: rocSOLVER's eigensolver "
+                         "for all; default: the library's)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path sweeps")
     ap.add_argument("--no-bf16x3", action="store_true", help="skip the BF16x3-path sweeps")
     ap.add_argument("--no-chi1024", action="store_true",
@@ -856,6 +860,8 @@ def main():
         spec = dataclasses.replace(spec, U=args.U)
         case = f"{args.config}_U{args.U:g}"
     tnt = B.load()
+    if args.eig_reduction is not None:
+        tnt.set_eig_reduction(args.eig_reduction)
     if args.batched_sweep:
         print(json.dumps(batched_sweep(tnt, B, torch, args.precision)), flush=True)
         return

@@ -109,6 +109,18 @@ tnt_status tnt_ctx_set_autotune(tnt_ctx ctx, int32_t on);
  * seconds_gemm and gemm_launches stay 0).  Errors: TNT_E_ARG. */
 tnt_status tnt_ctx_set_graphs(tnt_ctx ctx, int32_t on);
 
+/* Tridiagonal reduction of the SVD's sector eigenproblems (Appendix B.1.2,
+ * the node SVD; Gram matrices of the sectors, see tnt_theta_svd_truncate).
+ * Problems whose padded order is >= min_order (and <= 2048) are reduced to
+ * tridiagonal form by the library's own panel Householder kernels (two
+ * launches per column) and finished by rocSOLVER's divide and conquer and
+ * back-transformation; the others, and all of them with min_order = 0, go
+ * through rocSOLVER's batched Hermitian eigensolver.  Both give the
+ * eigenpairs to the backward error of a stable FP64 eigensolver, so kept
+ * dimensions and truncation errors agree wherever the cut is decisive.
+ * A negative min_order restores the default. */
+tnt_status tnt_ctx_set_eig_reduction(tnt_ctx ctx, int32_t min_order);
+
 /* ------------------------------------------------------------------------
  * Block tensors (appendix A.1.1)
  *

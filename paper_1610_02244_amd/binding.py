@@ -94,6 +94,7 @@ SIGNATURES = {
     "tnt_ctx_memory": (C.c_int32, [P, C.POINTER(C.c_int64)]),
     "tnt_ctx_set_autotune": (C.c_int32, [P, C.c_int32]),
     "tnt_ctx_set_graphs": (C.c_int32, [P, C.c_int32]),
+    "tnt_ctx_set_eig_reduction": (C.c_int32, [P, C.c_int32]),
     "tnt_mpo_spin1_heisenberg": (C.c_int32, [C.c_double, F64P, I32P]),
     "tnt_mpo_bose_hubbard": (C.c_int32, [C.c_int32, C.c_double, C.c_double, C.c_double, F64P,
                                          I32P]),
@@ -418,6 +419,13 @@ class Tnt:
 
     def set_graphs(self, on: bool):
         self._check("tnt_ctx_set_graphs", self.lib.tnt_ctx_set_graphs(self.ctx, int(on)))
+
+    def set_eig_reduction(self, min_order: int):
+        """Padded sector order from which the SVD's eigenproblems use the
+        library's own tridiagonal reduction (0: rocSOLVER's eigensolver for
+        all; negative: the library default)."""
+        self._check("tnt_ctx_set_eig_reduction",
+                    self.lib.tnt_ctx_set_eig_reduction(self.ctx, int(min_order)))
 
     def heff2_apply(self, L, W1, W2, R, theta, out, precision="fp64"):
         code = self.lib.tnt_heff2_apply(self.ctx, L.ref, W1.ref, W2.ref, R.ref, theta.ref,

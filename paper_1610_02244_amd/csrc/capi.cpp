@@ -518,6 +518,12 @@ tnt_status tnt_ctx_set_graphs(tnt_ctx ctx, int32_t on) {
   TNT_API_END
 }
 
+tnt_status tnt_ctx_set_eig_reduction(tnt_ctx ctx, int32_t min_order) {
+  TNT_API_BEGIN(ctx)
+  c.eig_trd_min = min_order < 0 ? Ctx::kEigTrdDefault : min_order;
+  TNT_API_END
+}
+
 tnt_status tnt_heff2_apply(tnt_ctx ctx, const tnt_btensor* L, const tnt_mpo_site* W1,
                            const tnt_mpo_site* W2, const tnt_btensor* R,
                            const tnt_btensor* theta, tnt_btensor* out, int32_t precision) {

@@ -115,6 +115,11 @@ struct Ctx {
   // sector eigenproblems the SVD redid with the Jacobi eigensolver because
   // divide and conquer failed or returned non-finite vectors (running count)
   int64_t eig_retries = 0;
+  // sector eigenproblems whose padded order is at least this use the library's
+  // divide and conquer on a tridiagonal form reduced by trd.hip; smaller ones,
+  // and every one when 0, use the library's whole Hermitian eigensolver
+  static constexpr int kEigTrdDefault = 0;
+  int eig_trd_min = kEigTrdDefault;
   hipStream_t gstream = nullptr;
   std::map<uint64_t, int> tune_cache;
   static constexpr int kSide = 8;

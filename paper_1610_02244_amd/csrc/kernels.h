@@ -334,6 +334,39 @@ void launch_pad_embed(const PadTask* t, int ntask, int max_n, int max_npad, doub
 void launch_pad_extract(const PadTask* t, int ntask, int max_n, const double* slot_z,
                         const double* slot_w, hipStream_t s);
 
+// Householder reduction of a batch of Hermitian matrices of one order np to
+// real symmetric tridiagonal form (LAPACK's lower convention: reflector k in
+// A(k+2:, k) with A(k+1, k) = 1, scalars tau, diagonal d, off-diagonal e), in
+// panels of TRD_NB columns; matrix b of the batch starts at A + b sA, and so
+// on for every array.  Per column k of a panel starting at j0 (in-panel
+// index i = k - j0, nbp columns): launch_trd_column, then launch_trd_gemv if
+// k < np - 1; after the panel, if columns remain, launch_trd_column with
+// do_col = 0 (finishes the panel's last W column) and the trailing update
+// A(t0:, t0:) -= X(t0:, 0:2 nbp) X(t0:, nbp:3 nbp)^H (t0 = j0 + nbp), a
+// complex GEMM left to the caller.  np <= TRD_MAX_N.
+constexpr int TRD_NB = 32;
+constexpr int TRD_MAX_N = 2048;
+struct TrdBatch {
+  double2* A;     // matrices, np x np, full storage, column-major (ld np)
+  int64_t sA;
+  double2* X;     // panel columns [V | W | V], np x 3 nbp (ld np)
+  int64_t sX;
+  double2* yp;    // partial products, ceil(np / 64) x np
+  int64_t sY;
+  double2* tp;    // partial dot products, ceil(np / 64) x 2 TRD_NB
+  int64_t sT;
+  double* d;      // np diagonal entries
+  int64_t sd;
+  double* e;      // np - 1 off-diagonal entries
+  int64_t se;
+  double2* tau;   // np - 1 reflector scalars
+  int64_t stau;
+  int np;
+};
+void launch_trd_column(const TrdBatch& b, int cnt, int j0, int nbp, int i, int do_col,
+                       hipStream_t s);
+void launch_trd_gemv(const TrdBatch& b, int cnt, int k, int i, int nbp, hipStream_t s);
+
 // Column staging of the deflated SVD (interleaved complex, column-major):
 // dst = scale * src over n complex values (one task per column), and the
 // squared 2-norm of n complex values at src into *out (one workgroup per

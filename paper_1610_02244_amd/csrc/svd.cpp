@@ -362,6 +362,48 @@ std::shared_ptr<SvdJob> svd_begin(Ctx& c, const ThetaH& th, const double* re, co
   return job;
 }
 
+// Eigenpairs of cnt Hermitian matrices of order np (b.A, full storage):
+// tridiagonal form by the panel kernels (trd.hip) with one complex GEMM per
+// panel for the trailing update, then per matrix the library's tridiagonal
+// divide and conquer (eigenvalues ascending into b.d, eigenvectors of T into
+// z) and its back-transformation z <- Q z with the reflectors left in b.A.
+static void trd_eig_bucket(rocblas_handle h, hipStream_t s, const TrdBatch& b, int cnt,
+                           double* z, rocblas_int* info) {
+  const int np = b.np;
+  const rocblas_double_complex m1{-1.0, 0.0}, p1{1.0, 0.0};
+  for (int j0 = 0; j0 < np; j0 += TRD_NB) {
+    const int nbp = std::min(TRD_NB, np - j0);
+    for (int i = 0; i < nbp; ++i) {
+      launch_trd_column(b, cnt, j0, nbp, i, 1, s);
+      if (j0 + i < np - 1) launch_trd_gemv(b, cnt, j0 + i, i, nbp, s);
+    }
+    const int t0 = j0 + nbp;
+    if (t0 >= np) continue;
+    launch_trd_column(b, cnt, j0, nbp, nbp, 0, s);
+    // A(t0:, t0:) -= [V W] [W V]^H
+    const int mt = np - t0;
+    auto* X = reinterpret_cast<rocblas_double_complex*>(b.X);
+    auto* A = reinterpret_cast<rocblas_double_complex*>(b.A);
+    if (rocblas_zgemm_strided_batched(h, rocblas_operation_none,
+                                      rocblas_operation_conjugate_transpose, mt, mt, 2 * nbp, &m1,
+                                      X + t0, np, b.sX, X + t0 + (int64_t)nbp * np, np, b.sX,
+                                      &p1, A + t0 + (int64_t)t0 * np, np, b.sA,
+                                      cnt) != rocblas_status_success)
+      fail(TNT_E_HIP, "rocblas_zgemm_strided_batched failed");
+  }
+  for (int q = 0; q < cnt; ++q) {
+    auto* zq = reinterpret_cast<rocblas_double_complex*>(z) + (int64_t)q * b.sA;
+    if (rocsolver_zstedc(h, rocblas_evect_tridiagonal, np, b.d + q * b.sd, b.e + q * b.se, zq,
+                         np, info + q) != rocblas_status_success)
+      fail(TNT_E_HIP, "rocsolver_zstedc failed");
+    if (rocsolver_zunmtr(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, np,
+                         np, reinterpret_cast<rocblas_double_complex*>(b.A + q * b.sA), np,
+                         reinterpret_cast<rocblas_double_complex*>(b.tau + q * b.stau), zq,
+                         np) != rocblas_status_success)
+      fail(TNT_E_HIP, "rocsolver_zunmtr failed");
+  }
+}
+
 // Eigendecompositions of a batch of Hermitian matrices of any orders.
 static void eig_batch(Ctx& c, std::vector<EigProb>& probs) {
   // Small problems are solved by cyclic Jacobi in LDS (see below).  For the
@@ -378,6 +420,7 @@ static void eig_batch(Ctx& c, std::vector<EigProb>& probs) {
     std::vector<int> ids;
     std::vector<PadTask> tasks;
     DevBuf slots, w, e, tab, info, sc;
+    DevBuf X, yp, tp, tau, zv;  // own tridiagonal reduction (trd_eig_bucket)
   };
   constexpr int kMaxBuckets = Ctx::kSide - 1;
   std::vector<int> all, small[2];
@@ -490,14 +533,44 @@ static void eig_batch(Ctx& c, std::vector<EigProb>& probs) {
                            hipMemcpyHostToDevice, ss));
     launch_pad_embed(bk.tab.as<PadTask>(), cnt, maxn, np, bk.e.as<double>(),
                      bk.slots.as<double>(), ss);
-    if (rocsolver_zheevd_strided_batched(
-            static_cast<rocblas_handle>(c.side_blas[k]), rocblas_evect_original,
-            rocblas_fill_upper, np, reinterpret_cast<rocblas_double_complex*>(bk.slots.ptr), np,
-            slot, bk.w.as<double>(), np, bk.e.as<double>(), np, bk.info.as<rocblas_int>(),
-            cnt) != rocblas_status_success)
-      fail(TNT_E_HIP, "rocsolver_zheevd_strided_batched failed");
-    launch_pad_extract(bk.tab.as<PadTask>(), cnt, maxn, bk.slots.as<double>(), bk.w.as<double>(),
-                       ss);
+    const rocblas_handle hs = static_cast<rocblas_handle>(c.side_blas[k]);
+    if (c.eig_trd_min > 0 && np >= c.eig_trd_min && np <= TRD_MAX_N) {
+      // the slots keep the reflectors; the eigenvectors go to bk.zv
+      bk.X = DevBuf(&c.pool, (size_t)cnt * np * 3 * TRD_NB * sizeof(double2));
+      const int64_t nt = (np + 63) / 64;
+      bk.yp = DevBuf(&c.pool, (size_t)cnt * nt * np * sizeof(double2));
+      bk.tp = DevBuf(&c.pool, (size_t)cnt * nt * 2 * TRD_NB * sizeof(double2));
+      bk.tau = DevBuf(&c.pool, (size_t)cnt * np * sizeof(double2));
+      bk.zv = DevBuf(&c.pool, (size_t)2 * slot * cnt * sizeof(double));
+      TrdBatch b;
+      b.A = bk.slots.as<double2>();
+      b.sA = slot;
+      b.X = bk.X.as<double2>();
+      b.sX = (int64_t)np * 3 * TRD_NB;
+      b.yp = bk.yp.as<double2>();
+      b.sY = nt * np;
+      b.tp = bk.tp.as<double2>();
+      b.sT = nt * 2 * TRD_NB;
+      b.d = bk.w.as<double>();
+      b.sd = np;
+      b.e = bk.e.as<double>();
+      b.se = np;
+      b.tau = bk.tau.as<double2>();
+      b.stau = np;
+      b.np = np;
+      trd_eig_bucket(hs, ss, b, cnt, bk.zv.as<double>(), bk.info.as<rocblas_int>());
+      launch_pad_extract(bk.tab.as<PadTask>(), cnt, maxn, bk.zv.as<double>(), bk.w.as<double>(),
+                         ss);
+    } else {
+      if (rocsolver_zheevd_strided_batched(
+              hs, rocblas_evect_original, rocblas_fill_upper, np,
+              reinterpret_cast<rocblas_double_complex*>(bk.slots.ptr), np, slot,
+              bk.w.as<double>(), np, bk.e.as<double>(), np, bk.info.as<rocblas_int>(),
+              cnt) != rocblas_status_success)
+        fail(TNT_E_HIP, "rocsolver_zheevd_strided_batched failed");
+      launch_pad_extract(bk.tab.as<PadTask>(), cnt, maxn, bk.slots.as<double>(),
+                         bk.w.as<double>(), ss);
+    }
     k = (k + 1) % (Ctx::kSide - 1);
   }
   for (int q = 0; q < Ctx::kSide; ++q) {

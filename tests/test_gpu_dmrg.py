@@ -250,3 +250,16 @@ def test_sweep_cfg3_vs_oracle(tnt, precision, case):
           f"{[r['eig_retries'] for r in res]}", flush=True)
     assert rel <= 1e-9
     check_kept(got, res[-1]["bond_eps"], ref, g["sweeps"][-1]["eps"], g["chi"], precision)
+
+
+def test_sweep_own_eig_reduction(tnt):
+    """The converged chi = 256 FP64 sweeps (kept dims and errors equal the
+    oracle's at every bond) with the SVD's eigenproblems of padded order >= 48
+    reduced to tridiagonal form by the library's own panel kernels (divide and
+    conquer and back-transformation from rocSOLVER), against the same stored
+    oracle run and bars."""
+    tnt.set_eig_reduction(48)
+    try:
+        test_sweep_cfg2_converged(tnt, "fp64")
+    finally:
+        tnt.set_eig_reduction(-1)

@@ -12,6 +12,8 @@ truncation rules.  Singular values are compared with an absolute tolerance of
 SVD, the oracle's included, is of that size, so no sharper bar separates two
 correct results; values far above it agree to 1e-12 relative.
 """
+import contextlib
+
 import numpy as np
 import pytest
 
@@ -180,9 +182,26 @@ MID_L = {q: 24 for q in range(21)}
 MID_R = {q: 24 for q in range(1, 23)}
 
 
+# The SVD's sector eigenproblems either through rocSOLVER's batched Hermitian
+# eigensolver ("library") or, from padded order 48 up, through the library's
+# own panel tridiagonal reduction followed by rocSOLVER's divide and conquer
+# and back-transformation ("own"); the context's default is restored after.
+EIG_PATHS = {"library": 0, "own": 48}
+
+
+@contextlib.contextmanager
+def eig_path(tnt, path):
+    tnt.set_eig_reduction(EIG_PATHS[path])
+    try:
+        yield
+    finally:
+        tnt.set_eig_reduction(-1)
+
+
+@pytest.mark.parametrize("eig", list(EIG_PATHS))
 @pytest.mark.parametrize("absorb", ["right", "left"])
 @pytest.mark.parametrize("shape", ["small", "mid"])
-def test_svd_truncate_small_sectors_graded(tnt, absorb, shape):
+def test_svd_truncate_small_sectors_graded(tnt, absorb, shape, eig):
     """Only small sectors: Gram orders 1..~20, odd and even (the Jacobi
     eigensolver's range), or 20 sectors of order 48 (one batched library
     eigensolve), with theta's blocks scaled by a geometric factor per block so
@@ -195,7 +214,8 @@ def test_svd_truncate_small_sectors_graded(tnt, absorb, shape):
     for i, k in enumerate(sorted(th)):
         th[k] = th[k] * 10.0 ** (-step * i)
     ref = osvd.svd_truncate(th, SMALL_L, SMALL_R, d, 10 ** 4, absorb=absorb)
-    got = tnt.svd_truncate(tnt.theta(th), absorb=absorb, chi_max=10 ** 4)
+    with eig_path(tnt, eig):
+        got = tnt.svd_truncate(tnt.theta(th), absorb=absorb, chi_max=10 ** 4)
     assert got["chi"] == ref["chi"]
     assert got["bond"] == ref["bond"]
     all_ref = np.concatenate([ref["lambdas"][m] for m in ref["bond"]])
@@ -223,8 +243,9 @@ def test_svd_truncate_small_sectors_graded(tnt, absorb, shape):
             np.testing.assert_allclose(V @ V.conj().T, np.eye(k), atol=1e-13)
 
 
+@pytest.mark.parametrize("eig", list(EIG_PATHS))
 @pytest.mark.parametrize("absorb", ["right", "left"])
-def test_svd_truncate_large_sectors_with_zero_rows(tnt, absorb):
+def test_svd_truncate_large_sectors_with_zero_rows(tnt, absorb, eig):
     """Sectors of 100-200 rows (the eigensolver's divide-and-conquer range),
     with every fifth row and column of theta exactly zero: the Gram matrices
     then have exact zero rows, which must not break the padded batched
@@ -240,7 +261,8 @@ def test_svd_truncate_large_sectors_with_zero_rows(tnt, absorb):
     chi_max = 150
     print(f"[svd zero rows {absorb}]", flush=True)
     ref = osvd.svd_truncate(th, L, R, d, chi_max, absorb=absorb)
-    got = tnt.svd_truncate(tnt.theta(th), absorb=absorb, chi_max=chi_max)
+    with eig_path(tnt, eig):
+        got = tnt.svd_truncate(tnt.theta(th), absorb=absorb, chi_max=chi_max)
     assert got["chi"] == ref["chi"]
     assert got["bond"] == ref["bond"]
     n = max(sum(L.values()), sum(R.values()))
@@ -284,11 +306,12 @@ def sector_spectrum_theta(left, right, d, rng, spectrum):
     return {k: th[k] for k in keys}, exact
 
 
-def check_svd_vs_oracle(tnt, th, left, right, d, absorb, n, **rules):
+def check_svd_vs_oracle(tnt, th, left, right, d, absorb, n, eig="library", **rules):
     ref = osvd.svd_truncate(th, left, right, d, rules.get("chi_max", 10 ** 6),
                             a=rules.get("abs_tol", -1.0), r=rules.get("rel_tol", -1.0),
                             e=rules.get("err_tol", -1.0), absorb=absorb)
-    got = tnt.svd_truncate(tnt.theta(th), absorb=absorb, **rules)
+    with eig_path(tnt, eig):
+        got = tnt.svd_truncate(tnt.theta(th), absorb=absorb, **rules)
     assert got["chi"] == ref["chi"]
     assert got["bond"] == ref["bond"]
     lam0 = np.concatenate([ref["lambdas"][m] for m in ref["bond"]]).max()
@@ -329,7 +352,8 @@ GRADED_R = {12: 5, 13: 26, 14: 52, 15: 33, 16: 11, 17: 2}
                                    dict(chi_max=10 ** 6),
                                    dict(chi_max=130),
                                    dict(chi_max=10 ** 6, err_tol=1e-9)])
-def test_svd_truncate_deep_spectrum(tnt, absorb, rules):
+@pytest.mark.parametrize("eig", list(EIG_PATHS))
+def test_svd_truncate_deep_spectrum(tnt, absorb, rules, eig):
     """Sector spectra that fall geometrically from 1 to 1e-15 (orders 2..~140,
     both eigensolver paths): the relative cut at 1e-12, keeping everything,
     a chi cut deep in the spectrum and the error rule at 1e-9 must all give
@@ -350,8 +374,9 @@ def test_svd_truncate_deep_spectrum(tnt, absorb, rules):
 
     th, exact = sector_spectrum_theta(GRADED_L, GRADED_R, d, rng, spec)
     n = max(sum(GRADED_L.values()), sum(GRADED_R.values()))
-    print(f"[svd deep spectrum {absorb} {rules}]", flush=True)
-    ref, got, worst = check_svd_vs_oracle(tnt, th, GRADED_L, GRADED_R, d, absorb, n, **rules)
+    print(f"[svd deep spectrum {absorb} {rules} {eig}]", flush=True)
+    ref, got, worst = check_svd_vs_oracle(tnt, th, GRADED_L, GRADED_R, d, absorb, n, eig,
+                                          **rules)
     print(f"  chi {got['chi']} eps {got['eps']:.3e} (oracle {ref['eps']:.3e}) worst/tol {worst:.2e}")
 
 
@@ -367,8 +392,9 @@ def graded_theta(left, right, d, rng, decades):
     return th
 
 
+@pytest.mark.parametrize("eig", list(EIG_PATHS))
 @pytest.mark.parametrize("cfg,chi_max", [("cfg3", 1024), ("cfg5", 2048)])
-def test_svd_truncate_full_size(tnt, cfg, chi_max):
+def test_svd_truncate_full_size(tnt, cfg, chi_max, eig):
     """The middle-bond theta of the chi = 1024 and chi = 2048 chains (sectors
     up to 963 and 1925 rows), with a graded spectrum spanning ~12 decades:
     kept set, values and error equal the oracle's for a chi cut and for the
@@ -390,7 +416,8 @@ def test_svd_truncate_full_size(tnt, cfg, chi_max):
     if cfg == "cfg3":
         cases += [("left", dict(chi_max=chi_max)), ("right", dict(chi_max=10 ** 6))]
     for absorb, rules in cases:
-        print(f"[svd full size {cfg} {absorb} {rules}] max sector order {n}", flush=True)
-        ref, got, worst = check_svd_vs_oracle(tnt, th, left, right, s.d, absorb, n, **rules)
+        print(f"[svd full size {cfg} {absorb} {rules} {eig}] max sector order {n}", flush=True)
+        ref, got, worst = check_svd_vs_oracle(tnt, th, left, right, s.d, absorb, n, eig,
+                                              **rules)
         print(f"  chi {got['chi']} eps {got['eps']:.6e} (oracle {ref['eps']:.6e}) "
               f"worst/tol {worst:.2e}", flush=True)
