@@ -334,6 +334,20 @@ void launch_pad_embed(const PadTask* t, int ntask, int max_n, int max_npad, doub
 void launch_pad_extract(const PadTask* t, int ntask, int max_n, const double* slot_z,
                         const double* slot_w, hipStream_t s);
 
+// Grouped complex GEMM (zgemm_grouped.hip): one 64 x 64 tile of
+// C = op(A) B (sub = 0) or C -= op(A) B (sub = 1) per task, op(A) = A (opa = 0)
+// or A^H (opa = 1); A, B, C interleaved complex FP64, column-major with the
+// given leading dimensions; m x n is the whole product, (i0, j0) the tile's
+// origin.  K is summed in increasing order within each tile.
+struct ZTask {
+  const double* A;
+  const double* B;
+  double* C;
+  int32_t m, n, k, lda, ldb, ldc;
+  int32_t i0, j0, opa, sub;
+};
+void launch_zgemm_grouped(const ZTask* tasks, int ntask, hipStream_t s);
+
 // Householder reduction of a batch of Hermitian matrices of one order np to
 // real symmetric tridiagonal form (LAPACK's lower convention: reflector k in
 // A(k+2:, k) with A(k+1, k) = 1, scalars tau, diagonal d, off-diagonal e), in

@@ -267,6 +267,29 @@ void zgemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, 
       rocblas_status_success)
     fail(TNT_E_HIP, "rocblas_zgemm failed");
 }
+// Tiles of several independent products C = op(A) B or C -= op(A) B
+// (interleaved complex, column-major), run as one grouped launch on the
+// context's stream.  The object (its host table) must live until that stream
+// has been synchronised.
+struct ZGroup {
+  std::vector<ZTask> t;
+  DevBuf tab;
+  void add(int opa, bool sub, int m, int n, int k, const double* A, int lda, const double* B,
+           int ldb, double* C, int ldc) {
+    if (m <= 0 || n <= 0) return;
+    if (k <= 0) fail(TNT_E_ARG, "empty inner dimension in an SVD product");
+    for (int j0 = 0; j0 < n; j0 += 64)
+      for (int i0 = 0; i0 < m; i0 += 64)
+        t.push_back(ZTask{A, B, C, m, n, k, lda, ldb, ldc, i0, j0, opa, sub ? 1 : 0});
+  }
+  void run(Ctx& c) {
+    if (t.empty()) return;
+    tab = DevBuf(&c.pool, t.size() * sizeof(ZTask));
+    TNT_HIP(hipMemcpyAsync(tab.ptr, t.data(), t.size() * sizeof(ZTask), hipMemcpyHostToDevice,
+                           c.stream));
+    launch_zgemm_grouped(tab.as<ZTask>(), (int)t.size(), c.stream);
+  }
+};
 }  // namespace
 
 // State of one theta between the SVD phases.
@@ -934,29 +957,35 @@ void svd_refine(Ctx& c, const std::vector<SvdJob*>& jobs,
                                hipMemcpyHostToDevice, c.stream));
         launch_zcopy(tab.as<ZCopyTask>(), (int)cp.size(), cpmax, c.stream);
       }
-      size_t tmax = 1;
-      for (auto& a : act) {
-        const Sector& s = *a.second;
-        tmax = std::max(tmax, (size_t)s.nres * s.lv[level - 1].clus);
+      // T_s = V_s^+ Z_c,s ; Z_c,s -= V_s T_s, every sector in one launch per
+      // product (twice)
+      std::vector<int64_t> toff(act.size());
+      int64_t tsum = 0;
+      for (size_t i = 0; i < act.size(); ++i) {
+        const Sector& s = *act[i].second;
+        toff[i] = tsum;
+        tsum += (int64_t)s.nres * s.lv[level - 1].clus;
       }
-      DevBuf t(&c.pool, 2 * tmax * sizeof(double));
-      for (auto& a : act) {
-        Sector& s = *a.second;
-        Level& P = s.lv[level - 1];
-        const double* V = s.vres.as<double>();
-        for (int pass = 0; pass < 2; ++pass) {
-          // T = V^+ Z_c ; Z_c -= V T
-          zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, s.nres, P.clus,
-                s.nother, V, s.nother, P.Z, s.nother, t.as<double>(), s.nres);
-          zgemm(h, rocblas_operation_none, rocblas_operation_none, s.nother, P.clus, s.nres, V,
-                s.nother, t.as<double>(), s.nres, P.Z, s.nother, -1.0, 1.0);
+      DevBuf t(&c.pool, (size_t)2 * std::max<int64_t>(1, tsum) * sizeof(double));
+      ZGroup proj[2], upd[2];
+      for (int pass = 0; pass < 2; ++pass) {
+        for (size_t i = 0; i < act.size(); ++i) {
+          Sector& s = *act[i].second;
+          Level& P = s.lv[level - 1];
+          proj[pass].add(1, false, s.nres, P.clus, s.nother, s.vres.as<double>(), s.nother, P.Z,
+                         s.nother, t.as<double>() + 2 * toff[i], s.nres);
+          upd[pass].add(0, true, s.nother, P.clus, s.nres, s.vres.as<double>(), s.nother,
+                        t.as<double>() + 2 * toff[i], s.nres, P.Z, s.nother);
         }
+        proj[pass].run(c);
+        upd[pass].run(c);
       }
-      // the copies' host table must outlive the launch
+      // the copies' and products' host tables must outlive the launches
       TNT_HIP(hipStreamSynchronize(c.stream));
     }
     std::vector<EigProb> probs;
     probs.reserve(act.size());
+    ZGroup builds;  // Q_L (level >= 2) and the clusters' Gram matrices, one launch
     for (auto& a : act) {
       Sector& s = *a.second;
       if ((int)s.lv.size() != level) fail(TNT_E_STATE, "SVD level bookkeeping");
@@ -973,19 +1002,19 @@ void svd_refine(Ctx& c, const std::vector<SvdJob*>& jobs,
       if (level == 1) {
         L.Q = s.lv[0].U;  // the first n columns of level 0's eigenvectors
       } else {
-        double* Q = L.Z + 2 * zz;
-        zgemm(h, rocblas_operation_none, rocblas_operation_none, ng, n, P.n, P.Q, ng, P.U, P.n,
-              Q, ng);
+        double* Q = L.Z + 2 * zz;  // Q_L = Q_P U_P
+        builds.add(0, false, ng, n, P.n, P.Q, ng, P.U, P.n, Q, ng);
         L.Q = Q;
       }
-      // G = Z_c^+ Z_c  (the cluster rows' Gram matrix)
+      // G = Z_c^+ Z_c  (the cluster rows' Gram matrix; the fallback solver
+      // rebuilds it with the library's product)
       const double* Zc = P.Z;
       double* U = L.U;
+      builds.add(1, false, n, n, no, Zc, no, Zc, no, U, n);
       auto build = [=]() {
         zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, n, n, no, Zc, no,
               Zc, no, U, n);
       };
-      build();
       EigProb E;
       E.z = L.U;
       E.w = L.w;
@@ -994,18 +1023,20 @@ void svd_refine(Ctx& c, const std::vector<SvdJob*>& jobs,
       E.rebuild = build;
       probs.push_back(std::move(E));
     }
-    eig_batch(c, probs);
+    builds.run(c);
+    eig_batch(c, probs);  // synchronises the context's stream
     NormReads lr;
+    ZGroup zl;
     for (auto& a : act) {
       Sector& s = *a.second;
       Level& P = s.lv[level - 1];
       Level& L = s.lv[level];
       // Z_L = Z_c U_L
-      zgemm(h, rocblas_operation_none, rocblas_operation_none, s.nother, L.n, L.n, P.Z, s.nother,
-            L.U, L.n, L.Z, s.nother);
+      zl.add(0, false, s.nother, L.n, L.n, P.Z, s.nother, L.U, L.n, L.Z, s.nother);
       lr.add(L, s.nother);
     }
-    lr.run(c);
+    zl.run(c);
+    lr.run(c);  // synchronises the context's stream
     for (auto& a : act) {
       classify(*a.second, level);
       collect(*a.second);
@@ -1039,7 +1070,6 @@ SvdOut svd_finish(Ctx& c, SvdJob& J, const tnt_trunc_params& p, const FactorAllo
   const double* im = J.im;
   const bool right = J.right;
   std::vector<Sector>& secs = J.secs;
-  rocblas_handle h = blas(c);
   // pool (lambda desc, then sector asc, then in-sector position asc), select
   struct Ent { double lam; int sec, pos; };
   std::vector<Ent> pool;
@@ -1181,13 +1211,14 @@ SvdOut svd_finish(Ctx& c, SvdJob& J, const tnt_trunc_params& p, const FactorAllo
                            hipMemcpyHostToDevice, c.stream));
     launch_zcopy(cptab.as<ZCopyTask>(), (int)cp.size(), cpmax, c.stream);
   }
+  ZGroup kp;  // kept vectors of the refined levels: Q_L times their eigenvectors
   for (auto& pr : prods) {
     const Sector& s = *pr.s;
     const Level& L = s.lv[pr.level];
-    zgemm(h, rocblas_operation_none, rocblas_operation_none, s.n, pr.cnt, L.n, L.Q, s.n,
-          tprod.as<double>() + 2 * pr.toff, L.n, ukp + 2 * (s.ukbase + (int64_t)pr.pos * s.n),
-          s.n);
+    kp.add(0, false, s.n, pr.cnt, L.n, L.Q, s.n, tprod.as<double>() + 2 * pr.toff, L.n,
+           ukp + 2 * (s.ukbase + (int64_t)pr.pos * s.n), s.n);
   }
+  kp.run(c);
   // --- factors -----------------------------------------------------------
   std::vector<ScatterTask> st;
   int mr = 1, mc = 1;
